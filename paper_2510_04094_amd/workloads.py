@@ -1,0 +1,143 @@
+"""Seeded synthetic ODE workloads (manufactured solutions).
+
+This module only draws problem instances: a grid, coefficient functions, a
+manufactured solution y* and the forcing / conditions that make y* exact.
+It contains none of the solver's arithmetic and imports nothing else from the
+package, so the HIP binding and the CPU oracle can both consume its output.
+
+Every instance is a plain dict:
+  p, n, m            ODE order, grid size, number of landmarks
+  t0, dt, t          uniform grid t_i = t0 + i*dt (t is the float64 array)
+  f                  [p, n] coefficients f_k(t_i) of y^(p) = sum_k f_k y^(p-k) + r
+  r                  [n] forcing r(t_i)
+  cond_d, cond_i, v  conditions y^(d_j)(t_{i_j}) = v_j
+  sigma, gamma, tau  RBF bandwidth (K = exp(-(u-v)^2/sigma^2)), ridge, eigen cut-off
+  ystar              [n] manufactured solution on the grid (for accuracy reports)
+  lidx               None: landmarks follow the solver's default equidistant rule
+Nonlinear (Riccati) instances carry `q` [n] with y' = q(t) - y^2 instead of f/r.
+
+Seeds: numpy.random.default_rng(251004094 + 100000*config + instance); draws
+in the order bandwidth, coefficients, solution parameters, noise.
+"""
+import numpy as np
+
+SEED_BASE = 251004094
+
+
+def _rng(config, instance):
+    return np.random.default_rng(SEED_BASE + 100000 * config + instance)
+
+
+def _grid(t_end, n):
+    dt = t_end / (n - 1)
+    return 0.0, dt, 0.0 + np.arange(n, dtype=np.float64) * dt
+
+
+def _sines(rng, k, t, damp=0.0):
+    """y*, y*', y*'' of exp(-damp t) sum_k c_k sin(w_k t + ph_k)."""
+    c = rng.uniform(-1.0, 1.0, k)
+    w = rng.uniform(1.0, 6.0, k)
+    ph = rng.uniform(0.0, 2.0 * np.pi, k)
+    arg = w[None, :] * t[:, None] + ph[None, :]
+    s = np.sin(arg) @ c
+    ds = (np.cos(arg) * w[None, :]) @ c
+    dds = (-np.sin(arg) * (w * w)[None, :]) @ c
+    e = np.exp(-damp * t)
+    y = e * s
+    dy = e * (ds - damp * s)
+    ddy = e * (dds - 2.0 * damp * ds + damp * damp * s)
+    return y, dy, ddy, dict(c=c, w=w, ph=ph, damp=damp)
+
+
+def ystar_at(prob, s):
+    """Manufactured solution of a linear instance at arbitrary times s."""
+    sp = prob["sol"]
+    s = np.asarray(s, dtype=np.float64)
+    arg = sp["w"][None, :] * s[:, None] + sp["ph"][None, :]
+    return np.exp(-sp["damp"] * s) * (np.sin(arg) @ sp["c"])
+
+
+def linear_first_order(instance, n=200, m=20, t_end=1.0, sigma=0.1, gamma=1e8,
+                       tau=1e-12, config=1):
+    """y' + a(t) y = g(t), y(0) = y*(0); a = a0 + a1 cos t, a ~ U(.5, 2); y* = 3 sinusoids."""
+    rng = _rng(config, instance)
+    t0, dt, t = _grid(t_end, n)
+    a01 = rng.uniform(0.5, 2.0, 2)
+    a = a01[0] + a01[1] * np.cos(t)
+    y, dy, _, sp = _sines(rng, 3, t)
+    g = dy + a * y
+    return dict(p=1, n=n, m=m, t0=t0, dt=dt, t=t, f=(-a)[None, :].copy(), r=g,
+                cond_d=[0], cond_i=[0], v=np.array([y[0]]), sigma=float(sigma),
+                gamma=float(gamma), tau=float(tau), ystar=y, lidx=None,
+                coef=dict(alpha=a01), sol=sp)
+
+
+def linear_second_order(instance, n=10000, m=50, t_end=10.0, gamma=1e7, tau=1e-8,
+                        sigma=None, config=2, obs=0, noise=1e-3):
+    """y'' + b(t) y' + a(t) y = g(t) with y(0), y'(0) from y*.
+
+    sigma ~ U(0.2, 1); a = a0 + a1 cos t, a ~ U(.5, 2); b = b0 + b1 sin t,
+    b ~ U(0, .5); y* = exp(-lam t) * (5 sinusoids), lam ~ U(0, .3).
+    With obs > 0 the same stream then draws `obs` sorted observation times
+    s_j ~ U(t0, t_end) and y_obs = y*(s_j) + noise * N(0, 1) (keys t_obs, y_obs).
+    """
+    rng = _rng(config, instance)
+    s_draw = rng.uniform(0.2, 1.0)
+    sig = s_draw if sigma is None else sigma
+    t0, dt, t = _grid(t_end, n)
+    a01 = rng.uniform(0.5, 2.0, 2)
+    b01 = rng.uniform(0.0, 0.5, 2)
+    a = a01[0] + a01[1] * np.cos(t)
+    bb = b01[0] + b01[1] * np.sin(t)
+    lam = rng.uniform(0.0, 0.3)
+    y, dy, ddy, sp = _sines(rng, 5, t, damp=lam)
+    g = ddy + bb * dy + a * y
+    f = np.stack([-bb, -a])
+    prob = dict(p=2, n=n, m=m, t0=t0, dt=dt, t=t, f=f, r=g, cond_d=[0, 1],
+                cond_i=[0, 0], v=np.array([y[0], dy[0]]), sigma=float(sig),
+                gamma=float(gamma), tau=float(tau), ystar=y, lidx=None,
+                coef=dict(alpha=a01, beta=b01, damp=lam), sol=sp)
+    if obs > 0:
+        s = np.sort(rng.uniform(t0, t0 + (n - 1) * dt, obs))
+        prob["t_obs"] = s
+        prob["y_obs"] = ystar_at(prob, s) + noise * rng.standard_normal(obs)
+    return prob
+
+
+def riccati(instance, n=2000, m=50, t_end=2.0, sigma=0.1, gamma=1e6, tau=1e-12,
+            config=3):
+    """y' = q(t) - y^2 with y* = 0.5 + 0.3 tanh(kappa (t - 1)), kappa ~ U(1, 4)."""
+    rng = _rng(config, instance)
+    t0, dt, t = _grid(t_end, n)
+    kappa = rng.uniform(1.0, 4.0)
+    th = np.tanh(kappa * (t - 1.0))
+    y = 0.5 + 0.3 * th
+    dy = 0.3 * kappa * (1.0 - th * th)
+    q = dy + y * y
+    return dict(p=1, n=n, m=m, t0=t0, dt=dt, t=t, q=q, cond_d=[0], cond_i=[0],
+                v=np.array([y[0]]), sigma=float(sigma), gamma=float(gamma),
+                tau=float(tau), ystar=y, lidx=None, coef=dict(kappa=kappa))
+
+
+def mixed_batch(count=4096, n_lo=500, n_hi=10000, ms=(20, 50, 100), tau=1e-8, config=4):
+    """Uneven batch: p in {1, 2} (exactly half each, shuffled), n ~ U{n_lo..n_hi}, m from ms."""
+    rng = _rng(config, 0)
+    orders = np.array([1] * (count // 2) + [2] * (count - count // 2))
+    rng.shuffle(orders)
+    ns = rng.integers(n_lo, n_hi + 1, count)
+    mm = rng.choice(np.array(ms), count)
+    out = []
+    for i in range(count):
+        if orders[i] == 1:
+            prob = linear_first_order(i + 1, n=int(ns[i]), m=int(mm[i]), tau=tau,
+                                      config=config)
+        else:
+            prob = linear_second_order(i + 1, n=int(ns[i]), m=int(mm[i]), tau=tau,
+                                       config=config)
+        out.append(prob)
+    return out
+
+
+def adjoint_batch(count=1024, n=5000, m=50, obs=100, config=5):
+    """Second-order instances with observations for the parameter-estimation loss."""
+    return [linear_second_order(i, n=n, m=m, config=config, obs=obs) for i in range(count)]
