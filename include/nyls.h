@@ -1,0 +1,215 @@
+/*
+ * nyls.h -- C ABI of the Nystrom-accelerated primal LS-SVM ODE solver (gfx950 / MI355X).
+ *
+ * Method: arXiv 2510.04094.  A p-th order ODE
+ *     y^(p)(t) - sum_{k=1..p} f_k(t) y^(p-k)(t) = r(t),   y^(d_j)(t_{i_j}) = v_j  (j = 1..p)
+ * (Sec. 3.1) is solved with the model y_hat(t) = omega^T phi(t) + b, where phi is the
+ * explicit Nystrom feature map of the RBF kernel K(u, v) = exp(-(u - v)^2 / sigma^2)
+ * (App. A.2, eq32): K_mm = U Lambda U^T over m landmarks, phi(t) = Lambda^{-1/2} U^T k_m(t)
+ * restricted to eigenvalues lambda_k > tau * lambda_1, and phi^(d) its time derivatives
+ * (Sec. 3).  Linear ODEs solve the Lemma 1 KKT system (Sec. 3.1); first-order nonlinear
+ * ODEs y' = F(t, y) iterate Newton on the Lemma 2 system (Sec. 3.2, App. A.5).
+ *
+ * Conventions for every function below
+ *   - All array arguments are DEVICE pointers unless marked "host", FP64 unless marked
+ *     otherwise, row-major, owned by the caller.  The library never frees them.
+ *   - Work functions only enqueue kernels on `stream` (no host synchronisation, no
+ *     allocation) and return 0, or a negative NYLS_E* code when an argument is invalid;
+ *     nothing is enqueued then.  Numerical outcomes are reported per instance in the
+ *     `status` bitmask (NYLS_S*), readable after the stream is synchronised.
+ *   - `ws` is a caller-allocated device workspace of nyls_workspace_size(plan) bytes.  It
+ *     carries state between calls: nyls_solve leaves the basis, factors and solution there
+ *     for nyls_predict / nyls_backward; nyls_newton_step keeps its basis there.  One plan
+ *     with one workspace must not be used from two streams at once; distinct plans can.
+ *   - Per-instance padded layouts use MAXM = max m over the batch and KN = MAXM + 1 + 4.
+ *   - Only the plan functions allocate (the device descriptor table).
+ */
+#ifndef NYLS_H
+#define NYLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NYLS_MAX_P 4   /* highest ODE order */
+#define NYLS_MAX_M 128 /* most landmarks per instance */
+
+/* Arithmetic of the solve (nyls_plan_create `mode`). */
+enum {
+  NYLS_FP64 = 0,          /* every step in FP64 */
+  NYLS_MIXED = 1,         /* FP32 kernel values, rotated into the eigenbasis and contracted
+                             on the matrix cores (FP32 MFMA, FP64 cross-tile sums), FP64
+                             eigen, solve and matrix-free FP64 iterative refinement;
+                             m <= 126 */
+  NYLS_FP64_EXPLICIT = 2  /* reference-style FP64: explicit feature matrices, one instance
+                             per launch sequence (a baseline, not the fast path) */
+};
+
+/* Return codes (negative: nothing was enqueued). */
+enum {
+  NYLS_OK = 0,
+  NYLS_E_NULL = -1,       /* a required pointer is NULL */
+  NYLS_E_BATCH = -2,      /* batch < 1 */
+  NYLS_E_MODE = -3,       /* unknown mode, or the call does not support the plan's mode */
+  NYLS_E_ORDER = -4,      /* p outside 1..NYLS_MAX_P */
+  NYLS_E_SIZE = -5,       /* n < 2, m < 2, m > n or m > NYLS_MAX_M (126 in mixed mode) */
+  NYLS_E_PARAM = -6,      /* sigma <= 0, gamma <= 0, tau outside [0, 1), or non-finite */
+  NYLS_E_GRID = -7,       /* uniform grid with dt <= 0, or explicit grid missing */
+  NYLS_E_LANDMARK = -8,   /* landmark indices not strictly ascending inside [0, n) */
+  NYLS_E_COND = -9,       /* condition order outside 0..p-1, index outside [0, n), or a
+                             duplicated (order, index) pair */
+  NYLS_E_NONLINEAR = -10, /* Newton step on a plan that is not first order */
+  NYLS_E_HIP = -11,       /* a HIP runtime call failed */
+  NYLS_E_ARG = -12        /* another argument is out of range (e.g. dmax, refine steps) */
+};
+
+/* Per-instance status bits (device int32 array written by the work functions). */
+enum {
+  NYLS_S_TRUNCATED = 1,       /* info: the basis kept r < m eigenpairs */
+  NYLS_S_SINGULAR = 2,        /* a zero pivot in the KKT / Schur factorisation */
+  NYLS_S_NONFINITE = 4,       /* a NaN or Inf appeared in the solution */
+  NYLS_S_EIG_NOCONV = 8,      /* the Jacobi eigensolver hit its sweep limit */
+  NYLS_S_SMALL_PIVOT = 16     /* Newton: a diagonal y-block entry |d_i| < 1e-10 gamma */
+};
+
+/*
+ * One ODE instance, as stated in Sec. 3.1 (linear) or App. A.5 (nonlinear, p = 1).
+ *   p          order, 1..4
+ *   n          grid size; grid t_i = t0 + i*dt when uniform != 0, else t[i] (device,
+ *              strictly ascending)
+ *   m          number of landmarks (sub-sample size), 2 <= m <= min(n, 128)
+ *   lidx       HOST array of m strictly ascending grid indices, or NULL for the
+ *              equidistant rule i_s = floor(s (n-1)/(m-1) + 1/2), s = 0..m-1 (Sec. 4.1)
+ *   f          device [p][n]: f[(k-1)*n + i] = f_k(t_i); unused by the nonlinear path
+ *   r          device [n]: forcing r(t_i); unused by the nonlinear path
+ *   v          device [p]: condition values v_j
+ *   cond_d/i   condition j prescribes y^(cond_d[j]) at grid index cond_i[j] (j < p).
+ *              Grid points that carry a condition carry no ODE residual (IVP: the
+ *              residual set is 2..n as in Lemma 1; two-point BVP: 2..n-1, App. A.4).
+ *   sigma      RBF bandwidth (the kernel divides by sigma^2), > 0
+ *   gamma      regularisation constant of the residual term, > 0
+ *   tau        relative eigenvalue cut-off in [0, 1): eigenpairs with
+ *              lambda_k <= tau * lambda_1 are dropped (the paper assumes K_mm positive
+ *              definite; in FP64 it is numerically singular for smooth kernels)
+ */
+typedef struct nyls_problem {
+  int32_t p, n, m, uniform;
+  double t0, dt;
+  const double* t;
+  const int32_t* lidx;
+  const double* f;
+  const double* r;
+  const double* v;
+  int32_t cond_d[NYLS_MAX_P];
+  int32_t cond_i[NYLS_MAX_P];
+  double sigma, gamma, tau;
+} nyls_problem;
+
+typedef struct nyls_plan nyls_plan;
+
+/* Validate `batch` instances (host array) and upload their descriptors; *out receives the
+ * plan.  mode is NYLS_FP64, NYLS_MIXED or NYLS_FP64_EXPLICIT.  Device data pointers are
+ * stored, not copied: they must stay valid while the plan is used, and new values written
+ * into them are picked up by the next call.  Returns 0 or a NYLS_E* code (then *out = NULL). */
+int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyls_plan** out);
+void nyls_plan_destroy(nyls_plan* plan);
+/* Bytes of device workspace every work function of this plan needs. */
+size_t nyls_workspace_size(const nyls_plan* plan);
+/* Sum of n over the batch: length of per-grid-point outputs (yhat, dL/dr, ...).
+ * Instance i's points start at the prefix sum of the n before it. */
+int64_t nyls_total_points(const nyls_plan* plan);
+/* MAXM of the batch (the padded stride of omega, eigval and phi). */
+int32_t nyls_max_m(const nyls_plan* plan);
+
+/* Feature map (App. A.2 eq32, Sec. 3): eigendecompose K_mm and evaluate
+ * phi^(d)(t) for d = 0..dmax (dmax <= 4) at caller times.
+ *   t_eval    [E] evaluation times, instance i owns t_eval[eval_off[i] .. eval_off[i+1])
+ *   eval_off  [batch+1] int64 offsets (device)
+ *   phi       [E][dmax+1][MAXM]: phi[e][d][k], columns k >= rank are zero
+ *   eigval    [batch][MAXM] eigenvalues of K_mm, descending (may be NULL)
+ *   rank      [batch] int32 retained rank r (may be NULL)
+ * Eigenvectors are signed so that their largest-magnitude entry is positive. */
+int nyls_features(const nyls_plan* plan, const double* t_eval, const int64_t* eval_off,
+                  int32_t dmax, double* phi, double* eigval, int32_t* rank, void* ws,
+                  hipStream_t stream);
+
+/* Assemble the Lemma 1 system (Sec. 3.1) in feature coordinates (omega, b, lambda):
+ *   kkt [batch][KN*KN]: instance i's N = m+1+p system in the leading N x N block
+ *       (row stride N), rows/columns of dropped eigen-directions replaced by identity;
+ *   rhs [batch][KN]. */
+int nyls_assemble(const nyls_plan* plan, double* kkt, double* rhs, void* ws, hipStream_t stream);
+
+/* Solve the Lemma 1 system and evaluate y_hat on the grid.
+ *   refine_steps  most FP64 iterative-refinement steps after the solve, 0..8.  Each step
+ *                 forms the exact residual matrix-free from one pass over the points and
+ *                 stops early once its correction is at rounding level.  The fused modes
+ *                 factor an approximation of the system (a kernel-space FP64 Gram, or an
+ *                 FP32 Gram), so >= 2 steps are recommended when K_mm is ill-conditioned;
+ *                 NYLS_FP64_EXPLICIT assembles the exact system (0 steps suffice).
+ *   omega [batch][MAXM], bias [batch], lambda [batch][4], yhat [total points] (each may
+ *   be NULL except yhat), status [batch] int32.  The basis, LU factors and solution stay
+ *   in `ws` for nyls_predict and nyls_backward. */
+int nyls_solve(const nyls_plan* plan, int32_t refine_steps, double* omega, double* bias,
+               double* lambda, double* yhat, int32_t* status, void* ws, hipStream_t stream);
+
+/* y_hat^(d)(t) = alpha^T k_m^(d)(t) + [d == 0] b at caller times, from the solution a
+ * previous nyls_solve or nyls_newton_step left in `ws` (d = 0..4). */
+int nyls_predict(const nyls_plan* plan, const double* t_eval, const int64_t* eval_off,
+                 int32_t d, double* out, const void* ws, hipStream_t stream);
+
+/* Newton iteration on the Lemma 2 system of y' = F(t, y) (p = 1, App. A.5), unknowns
+ * (omega, b, lambda, y_i over the residual set).  State x is [batch][XS] with
+ * XS = nyls_newton_state_stride(plan) = MAXM + 2 + NMAX (NMAX = max n):
+ * x = (omega[MAXM], b, lambda, y[n]) with y indexed by grid point (entries at condition
+ * points are unused).
+ *
+ * nyls_newton_init: build the basis and the constant Jacobian blocks in `ws` and write the
+ * starting point omega = 0, b = v, lambda = 0, y_i = v into x.  Every instance must be
+ * first order with one condition y(t_{i_1}) = v. */
+int nyls_newton_init(const nyls_plan* plan, double* x, void* ws, hipStream_t stream);
+int64_t nyls_newton_state_stride(const nyls_plan* plan);
+
+/* One step x <- x - J^{-1} Y of Lemma 2's Newton method (Sec. 3.2).
+ *   F, Fy, Fyy  [total points] F(t_i, y_i), dF/dy, d2F/dy2 at the current y_i (the caller
+ *               owns the nonlinearity; passing Fyy = 0 gives the Gauss-Newton y-block)
+ *   x           [batch][XS] in/out
+ *   step_inf    [batch] |dx|_inf of this step (may be NULL)
+ * The diagonal y-block d_i = gamma (1 + Fy^2 - rho_i Fyy) is eliminated first (Schur
+ * complement on (omega, b, lambda)), so a step costs O(n m^2 + m^3); |d_i| < 1e-10 gamma
+ * sets NYLS_S_SMALL_PIVOT.  Afterwards nyls_predict evaluates the current y_hat. */
+int nyls_newton_step(const nyls_plan* plan, const double* F, const double* Fy,
+                     const double* Fyy, double* x, double* step_inf, int32_t* status,
+                     void* ws, hipStream_t stream);
+
+/* The Riccati right-hand side F(t, y) = q(t) - y^2 of the nonlinear workload, evaluated
+ * at the current Newton state x: F = q_i - y_i^2, Fy = -2 y_i, Fyy = -2 (0 when
+ * gauss_newton != 0, i.e. the Gauss-Newton y-block).  q, F, Fy, Fyy are [total points]. */
+int nyls_riccati_eval(const nyls_plan* plan, const double* q, const double* x,
+                      int32_t gauss_newton, double* F, double* Fy, double* Fyy,
+                      hipStream_t stream);
+
+/* Adjoint of nyls_solve (FP64): gradients of a loss l(y_hat(s_1..s_J)) given
+ * g_j = dl/dy_hat(s_j), reusing the factorisation left in `ws` by nyls_solve.
+ *   t_obs [J_total], obs_off [batch+1] int64, dl_dyobs [J_total]
+ *   dl_df [4][total points]: dl/df_k(t_i) of instance i at dl_df[(k-1)*total + off_i + i]
+ *         (rows k > p left untouched); dl_dr [total points];
+ *   dl_dv [batch][4]; dl_dsigma [batch]; dl_dgamma [batch]  (outputs may be NULL)
+ * Gradients w.r.t. the data f, r, v are exact derivatives of the Lemma 1 solution;
+ * sigma enters through the kernel values and through K_mm (spectral derivative).  In
+ * mixed mode the adjoint solve is refined in FP64 (two matrix-free steps).  Not available
+ * for NYLS_FP64_EXPLICIT plans. */
+int nyls_backward(const nyls_plan* plan, const double* t_obs, const int64_t* obs_off,
+                  const double* dl_dyobs, double* dl_df, double* dl_dr, double* dl_dv,
+                  double* dl_dsigma, double* dl_dgamma, void* ws, hipStream_t stream);
+
+/* Static text for a NYLS_E* code or a single NYLS_S* bit. */
+const char* nyls_error_string(int32_t code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NYLS_H */

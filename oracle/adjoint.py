@@ -75,14 +75,16 @@ def grad(prob, t_obs, g_obs):
     dpk = dks[p].copy()
     for k in range(1, p + 1):
         dpk = dpk - f[k - 1, idx][:, None] * dks[p - k]
-    direct = float(g_obs @ (nystrom_dsigma(0, t_obs, t_land, sig) @ alpha))
-    direct -= gam * float(np.sum((e[:, None] * beta[None, :] + nu[:, None] * alpha[None, :]) * dpk))
+    term_obs = float(g_obs @ (nystrom_dsigma(0, t_obs, t_land, sig) @ alpha))
+    term_pts = -gam * float(np.sum((e[:, None] * beta[None, :] + nu[:, None] * alpha[None, :]) * dpk))
+    term_cond = 0.0
     lam_kkt = sol["lam_kkt"]
     hk = []
     for j, (d, i) in enumerate(zip(prob["cond_d"], prob["cond_i"])):
         dh = nystrom_dsigma(int(d), t[int(i)], t_land, sig)[0]
-        direct -= float((lam_kkt[j] * beta + mu_l[j] * alpha) @ dh)
+        term_cond -= float((lam_kkt[j] * beta + mu_l[j] * alpha) @ dh)
         hk.append(nystrom.kvec(int(d), t[int(i)], t_land, sig)[0])
+    direct = term_obs + term_pts + term_cond
     hk = np.stack(hk, axis=1)                               # m x p, kernel space
 
     # 4b. sigma through K_mm: dl/dW, then Q_bar, then Daleckii-Krein
@@ -114,7 +116,8 @@ def grad(prob, t_obs, g_obs):
 
     return dict(dl_df=dl_df, dl_dr=dl_dr, dl_dv=dl_dv, dl_dsigma=dl_dsigma,
                 dl_dgamma=dl_dgamma, sol=sol, mu=mu, e=e, nu=nu,
-                sigma_direct=direct, sigma_kmm=via_kmm)
+                sigma_direct=direct, sigma_kmm=via_kmm,
+                sigma_terms=np.array([term_obs, term_pts, term_cond, via_kmm]))
 
 
 def nystrom_dsigma(d, t, t_land, sigma):

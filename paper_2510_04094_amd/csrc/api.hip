@@ -1,0 +1,297 @@
+// Host side of the C ABI: plan creation and validation, workspace layout, and the work
+// functions, which only enqueue kernels on the caller's stream.
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "nyls_internal.h"
+
+struct nyls_plan {
+  int32_t batch = 0, mode = 0, maxm = 0, maxp = 0, maxn = 0;
+  int64_t total = 0;        // sum of n
+  int64_t ws_doubles = 0;   // per-instance blocks
+  int64_t scratch_off = 0;  // explicit-mode scratch (doubles)
+  int64_t scratch_doubles = 0;
+  bool linear_ok = true;    // every instance has f and r
+  bool all_first_order = true;
+  unsigned nt_mask = 0;
+  nyls_desc* d_desc = nullptr;
+  int32_t* d_lidx = nullptr;
+  int32_t* d_order = nullptr;
+  std::vector<nyls_desc> h_desc;
+  rocblas_handle blas = nullptr;
+};
+
+namespace {
+
+bool finite(double x) { return std::isfinite(x); }
+
+int validate(const nyls_problem& q, std::vector<int32_t>& lidx) {
+  if (q.p < 1 || q.p > NYLS_MAX_P) return NYLS_E_ORDER;
+  if (q.n < 2 || q.m < 2 || q.m > q.n || q.m > NYLS_MAX_M) return NYLS_E_SIZE;
+  if (!(finite(q.sigma) && q.sigma > 0) || !(finite(q.gamma) && q.gamma > 0) ||
+      !(finite(q.tau) && q.tau >= 0 && q.tau < 1))
+    return NYLS_E_PARAM;
+  if (q.uniform) {
+    if (!(finite(q.dt) && q.dt > 0 && finite(q.t0))) return NYLS_E_GRID;
+  } else if (!q.t) {
+    return NYLS_E_GRID;
+  }
+  if (!q.v) return NYLS_E_NULL;
+  lidx.resize(q.m);
+  if (q.lidx) {
+    for (int s = 0; s < q.m; ++s) {
+      lidx[s] = q.lidx[s];
+      if (lidx[s] < 0 || lidx[s] >= q.n || (s > 0 && lidx[s] <= lidx[s - 1])) return NYLS_E_LANDMARK;
+    }
+  } else {
+    // equidistant rule i_s = floor(s (n-1)/(m-1) + 1/2), in integers
+    for (int s = 0; s < q.m; ++s)
+      lidx[s] = (int32_t)((2LL * s * (q.n - 1) + (q.m - 1)) / (2LL * (q.m - 1)));
+  }
+  for (int j = 0; j < q.p; ++j) {
+    if (q.cond_d[j] < 0 || q.cond_d[j] >= q.p || q.cond_i[j] < 0 || q.cond_i[j] >= q.n)
+      return NYLS_E_COND;
+    for (int k = 0; k < j; ++k)
+      if (q.cond_d[k] == q.cond_d[j] && q.cond_i[k] == q.cond_i[j]) return NYLS_E_COND;
+  }
+  return NYLS_OK;
+}
+
+nyls_plan_view view(const nyls_plan* pl) {
+  nyls_plan_view v;
+  v.batch = pl->batch;
+  v.mode = pl->mode;
+  v.maxm = pl->maxm;
+  v.maxp = pl->maxp;
+  v.maxn = pl->maxn;
+  v.d_desc = pl->d_desc;
+  v.d_order = pl->d_order;
+  v.total = pl->total;
+  v.nt_mask = pl->nt_mask;
+  return v;
+}
+
+int hip_rc(hipError_t e) { return e == hipSuccess ? NYLS_OK : NYLS_E_HIP; }
+
+}  // namespace
+
+// accessors used by the other translation units
+int64_t nyls_plan_newton_stride(const nyls_plan* pl) {
+  return pl ? (int64_t)pl->maxm + 2 + pl->maxn : 0;
+}
+bool nyls_plan_first_order(const nyls_plan* pl) { return pl && pl->all_first_order; }
+nyls_plan_view nyls_plan_get_view(const nyls_plan* pl) { return view(pl); }
+
+extern "C" {
+
+int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyls_plan** out) {
+  if (!out) return NYLS_E_NULL;
+  *out = nullptr;
+  if (!probs) return NYLS_E_NULL;
+  if (batch < 1) return NYLS_E_BATCH;
+  if (mode != NYLS_FP64 && mode != NYLS_MIXED && mode != NYLS_FP64_EXPLICIT) return NYLS_E_MODE;
+  nyls_plan* pl = new (std::nothrow) nyls_plan;
+  if (!pl) return NYLS_E_HIP;
+  pl->batch = batch;
+  pl->mode = mode;
+  pl->h_desc.resize(batch);
+  std::vector<int32_t> all_lidx, lid;
+  std::vector<int64_t> lidx_off(batch);
+  int64_t wsd = 0, goff = 0;
+  for (int i = 0; i < batch; ++i) {
+    const nyls_problem& q = probs[i];
+    int rc = validate(q, lid);
+    if (rc == NYLS_OK && mode == NYLS_MIXED && q.m > 126) rc = NYLS_E_SIZE;
+    if (rc != NYLS_OK) { delete pl; return rc; }
+    if (!q.f || !q.r) pl->linear_ok = false;
+    if (q.p != 1) pl->all_first_order = false;
+    nyls_desc& d = pl->h_desc[i];
+    d.p = q.p; d.n = q.n; d.m = q.m; d.uniform = q.uniform ? 1 : 0;
+    d.t0 = q.t0; d.dt = q.dt; d.t = q.t; d.f = q.f; d.r = q.r; d.v = q.v;
+    for (int j = 0; j < NYLS_MAX_P; ++j) {
+      d.cond_d[j] = j < q.p ? q.cond_d[j] : 0;
+      d.cond_i[j] = j < q.p ? q.cond_i[j] : -1;
+    }
+    d.sigma = q.sigma; d.gamma = q.gamma; d.tau = q.tau;
+    d.ws = wsd;
+    d.goff = goff;
+    wsd += nyls_layout(q.m, q.p, q.p == 1 ? q.n : 0).end;
+    goff += q.n;
+    lidx_off[i] = (int64_t)all_lidx.size();
+    all_lidx.insert(all_lidx.end(), lid.begin(), lid.end());
+    pl->nt_mask |= 1u << ((q.m + 2 + 15) / 16);
+    pl->maxm = std::max(pl->maxm, q.m);
+    pl->maxp = std::max(pl->maxp, q.p);
+    pl->maxn = std::max(pl->maxn, q.n);
+  }
+  pl->total = goff;
+  pl->ws_doubles = wsd;
+  pl->scratch_off = wsd;
+  pl->scratch_doubles = 0;
+  if (mode == NYLS_FP64_EXPLICIT) {
+    const int64_t nn = pl->maxn, mm = pl->maxm;
+    pl->scratch_doubles = nn * (NYLS_MAX_P + 1) * mm + nn * (mm + 2) + (mm + 2) * (mm + 2) + 64;
+  }
+  // explicit grids must be strictly ascending (checked on a host copy)
+  for (int i = 0; i < batch; ++i) {
+    if (probs[i].uniform) continue;
+    std::vector<double> t(probs[i].n);
+    if (hipMemcpy(t.data(), probs[i].t, sizeof(double) * t.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+      delete pl;
+      return NYLS_E_HIP;
+    }
+    for (size_t k = 1; k < t.size(); ++k)
+      if (!(t[k] > t[k - 1])) { delete pl; return NYLS_E_GRID; }
+  }
+  // instance order: most expensive first (n m^2), ties by index
+  std::vector<int32_t> order(batch);
+  for (int i = 0; i < batch; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const double ca = (double)probs[a].n * probs[a].m * probs[a].m;
+    const double cb = (double)probs[b].n * probs[b].m * probs[b].m;
+    return ca > cb;
+  });
+  bool ok = hipMalloc(&pl->d_lidx, sizeof(int32_t) * all_lidx.size()) == hipSuccess &&
+            hipMalloc(&pl->d_desc, sizeof(nyls_desc) * batch) == hipSuccess &&
+            hipMalloc(&pl->d_order, sizeof(int32_t) * batch) == hipSuccess;
+  if (ok) {
+    for (int i = 0; i < batch; ++i) pl->h_desc[i].lidx = pl->d_lidx + lidx_off[i];
+    ok = hipMemcpy(pl->d_lidx, all_lidx.data(), sizeof(int32_t) * all_lidx.size(),
+                   hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(pl->d_desc, pl->h_desc.data(), sizeof(nyls_desc) * batch,
+                   hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(pl->d_order, order.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice) ==
+             hipSuccess;
+  }
+  if (ok && mode == NYLS_FP64_EXPLICIT) ok = rocblas_create_handle(&pl->blas) == rocblas_status_success;
+  if (!ok) {
+    nyls_plan_destroy(pl);
+    return NYLS_E_HIP;
+  }
+  *out = pl;
+  return NYLS_OK;
+}
+
+void nyls_plan_destroy(nyls_plan* pl) {
+  if (!pl) return;
+  if (pl->blas) rocblas_destroy_handle(pl->blas);
+  if (pl->d_desc) (void)hipFree(pl->d_desc);
+  if (pl->d_lidx) (void)hipFree(pl->d_lidx);
+  if (pl->d_order) (void)hipFree(pl->d_order);
+  delete pl;
+}
+
+size_t nyls_workspace_size(const nyls_plan* pl) {
+  if (!pl) return 0;
+  return (size_t)(pl->ws_doubles + pl->scratch_doubles) * sizeof(double);
+}
+
+int64_t nyls_total_points(const nyls_plan* pl) { return pl ? pl->total : 0; }
+
+int32_t nyls_max_m(const nyls_plan* pl) { return pl ? pl->maxm : 0; }
+
+int nyls_features(const nyls_plan* pl, const double* t_eval, const int64_t* eval_off, int32_t dmax,
+                  double* phi, double* eigval, int32_t* rank, void* ws, hipStream_t stream) {
+  if (!pl || !t_eval || !eval_off || !phi || !ws) return NYLS_E_NULL;
+  if (dmax < 0 || dmax > NYLS_MAX_P) return NYLS_E_ARG;
+  const nyls_plan_view pv = view(pl);
+  double* w = static_cast<double*>(ws);
+  hipError_t e = nyls_launch_eig(pv, w, -1, stream);
+  if (e == hipSuccess)
+    e = nyls_launch_features(pv, w, t_eval, eval_off, dmax, phi, eigval, rank, 1 << 20, -1, stream);
+  return hip_rc(e);
+}
+
+int nyls_assemble(const nyls_plan* pl, double* kkt, double* rhs, void* ws, hipStream_t stream) {
+  if (!pl || !kkt || !rhs || !ws) return NYLS_E_NULL;
+  if (!pl->linear_ok) return NYLS_E_NULL;
+  const nyls_plan_view pv = view(pl);
+  double* w = static_cast<double*>(ws);
+  hipError_t e = nyls_launch_eig(pv, w, -1, stream);
+  if (e == hipSuccess)
+    e = (pl->mode == NYLS_MIXED) ? nyls_launch_gram32(pv, w, stream) : nyls_launch_gram64(pv, w, stream);
+  if (e == hipSuccess) e = nyls_launch_kkt(pv, w, kkt, rhs, 0, stream);
+  return hip_rc(e);
+}
+
+int nyls_solve(const nyls_plan* pl, int32_t refine_steps, double* omega, double* bias,
+               double* lambda, double* yhat, int32_t* status, void* ws, hipStream_t stream) {
+  if (!pl || !yhat || !ws) return NYLS_E_NULL;
+  if (!pl->linear_ok) return NYLS_E_NULL;
+  if (refine_steps < 0 || refine_steps > 8) return NYLS_E_ARG;
+  const nyls_plan_view pv = view(pl);
+  double* w = static_cast<double*>(ws);
+  hipError_t e = hipSuccess;
+  if (pl->mode == NYLS_FP64_EXPLICIT) {
+    double* scratch = w + pl->scratch_off;
+    rocblas_set_stream(pl->blas, stream);
+    for (int i = 0; i < pl->batch && e == hipSuccess; ++i) {
+      const nyls_desc& d = pl->h_desc[i];
+      const int g = d.m + 2;
+      double* phi = scratch;
+      double* rows = phi + (int64_t)pl->maxn * (NYLS_MAX_P + 1) * pl->maxm;
+      double* C = rows + (int64_t)pl->maxn * (pl->maxm + 2);
+      e = nyls_launch_eig(pv, w, i, stream);
+      if (e == hipSuccess)
+        e = nyls_launch_features(pv, w, nullptr, nullptr, d.p, phi, nullptr, nullptr, d.n, i, stream);
+      if (e == hipSuccess) e = nyls_launch_explicit_rows(pv, i, w, phi, rows, d.n, d.m, stream);
+      if (e == hipSuccess) {
+        // C (g x g, row-major == column-major symmetric) = rows^T rows; rows is n x g row-major,
+        // i.e. a column-major g x n matrix A with lda = g:  C = A A^T.
+        const double one = 1.0, zero = 0.0;
+        if (rocblas_dgemm(pl->blas, rocblas_operation_none, rocblas_operation_transpose, g, g, d.n,
+                          &one, rows, g, rows, g, &zero, C, g) != rocblas_status_success)
+          e = hipErrorUnknown;
+      }
+      if (e == hipSuccess) e = nyls_launch_explicit_kkt(pv, i, w, phi, C, stream);
+      if (e == hipSuccess)
+        e = nyls_launch_points(pv, w, refine_steps, yhat, omega, bias, lambda, status, i, stream);
+    }
+    return hip_rc(e);
+  }
+  e = nyls_launch_eig(pv, w, -1, stream);
+  if (e == hipSuccess)
+    e = (pl->mode == NYLS_MIXED) ? nyls_launch_gram32(pv, w, stream) : nyls_launch_gram64(pv, w, stream);
+  if (e == hipSuccess) e = nyls_launch_kkt(pv, w, nullptr, nullptr, 1, stream);
+  if (e == hipSuccess)
+    e = nyls_launch_points(pv, w, refine_steps, yhat, omega, bias, lambda, status, -1, stream);
+  return hip_rc(e);
+}
+
+int nyls_predict(const nyls_plan* pl, const double* t_eval, const int64_t* eval_off, int32_t d,
+                 double* out, const void* ws, hipStream_t stream) {
+  if (!pl || !t_eval || !eval_off || !out || !ws) return NYLS_E_NULL;
+  if (d < 0 || d > NYLS_MAX_P) return NYLS_E_ARG;
+  return hip_rc(nyls_launch_predict(view(pl), static_cast<const double*>(ws), t_eval, eval_off, d,
+                                    out, 1 << 20, stream));
+}
+
+const char* nyls_error_string(int32_t code) {
+  switch (code) {
+    case NYLS_OK: return "ok";
+    case NYLS_E_NULL: return "a required pointer is NULL";
+    case NYLS_E_BATCH: return "batch must be >= 1";
+    case NYLS_E_MODE: return "unknown or unsupported mode";
+    case NYLS_E_ORDER: return "ODE order p outside 1..4";
+    case NYLS_E_SIZE: return "need 2 <= m <= n and m <= 128";
+    case NYLS_E_PARAM: return "need sigma > 0, gamma > 0, 0 <= tau < 1 (finite)";
+    case NYLS_E_GRID: return "grid: dt <= 0 or explicit times missing / not ascending";
+    case NYLS_E_LANDMARK: return "landmark indices not strictly ascending inside [0, n)";
+    case NYLS_E_COND: return "condition order or index out of range, or duplicated";
+    case NYLS_E_NONLINEAR: return "Newton steps need first-order instances";
+    case NYLS_E_HIP: return "HIP runtime error";
+    case NYLS_E_ARG: return "argument out of range";
+    case NYLS_S_TRUNCATED: return "basis truncated (r < m)";
+    case NYLS_S_SINGULAR: return "zero pivot in the factorisation";
+    case NYLS_S_NONFINITE: return "non-finite value in the solution";
+    case NYLS_S_EIG_NOCONV: return "eigensolver hit its sweep limit";
+    case NYLS_S_SMALL_PIVOT: return "Newton diagonal block entry below 1e-10 gamma";
+    default: return "unknown code";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,178 @@
+// Lemma 1 KKT system in feature coordinates (Sec. 3.1), one workgroup per instance:
+//
+//   [ I + gamma W^T S W   gamma W^T u   H ] [omega]   [gamma W^T z]
+//   [ gamma u^T W         gamma s_cc    d ] [  b  ] = [gamma s_cr ]
+//   [ H^T                 d^T           0 ] [ lam ]   [     v     ]
+//
+// from the Gram S~ = [[S, u, z], [u^T, s_cc, s_cr], ...] of the Gram kernel (kernel space:
+// W^T S W; eigenbasis, rows rotated by U^T: Lambda^{-1/2} S Lambda^{-1/2}), W from the
+// basis kernel, condition rows h_j = W^T k^(d_j)(t_{i_j}) and delta_j = [d_j = 0].
+// Directions dropped by the eigenvalue cut-off get identity rows (their omega is 0).  The
+// system is optionally written out, then LU-factorised with partial pivoting in LDS; the
+// factors stay in the workspace for refinement and the adjoint, and the solution x and
+// alpha = W omega are stored.
+#include "nyls_dense.h"
+
+namespace {
+
+__device__ inline int instance_of(const int32_t* order) {
+  return order ? order[blockIdx.x] : (int)blockIdx.x;
+}
+
+__global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict__ desc,
+                                                    const int32_t* __restrict__ order,
+                                                    double* __restrict__ wsbase,
+                                                    double* __restrict__ kkt_out,
+                                                    double* __restrict__ rhs_out, int kn,
+                                                    int factor, int single, int eigbasis) {
+  extern __shared__ double sm[];
+  const int inst = single >= 0 ? single : instance_of(order);
+  const nyls_desc& d = desc[inst];
+  const int m = d.m, p = d.p;
+  const int g = m + 2, N = m + 1 + p, lda = N + 1;
+  const nyls_wsl L = nyls_layout(m, p, 0);
+  double* ws = wsbase + d.ws;
+  const double* W = ws + L.W;
+  const double* S = ws + L.gram;
+  double* T = ws + L.tmp;  // T = S W  (m x m, global scratch)
+  const int tid = threadIdx.x;
+  const int r = (int)ws[L.info + 0];
+  const double gam = d.gamma;
+
+  double* K = sm;                       // [N][lda]
+  double* rhs = K + N * lda;            // [N]
+  double* kc = rhs + (N + 1);           // [p][m] kernel-derivative vectors of the conditions
+  double* red = kc + NYLS_MAX_P * NYLS_MAX_M;
+  int* piv = reinterpret_cast<int*>(red + 16);
+
+  // T = S W over the landmark block (kernel-space Gram only); with the eigenbasis Gram
+  // (rows rotated by U^T) the transform is the diagonal Lambda^{-1/2}.
+  const double* lamv = ws + L.lam;
+  if (!eigbasis)
+    for (int e = tid; e < m * m; e += NYLS_BLOCK) {
+      const int a = e / m, k = e - a * m;
+      double acc = 0.0;
+      if (k < r)
+        for (int s = 0; s < m; ++s) acc += S[a * g + s] * W[s * m + k];
+      T[a * m + k] = acc;
+    }
+  // condition kernel vectors k^(d_j)(t_{i_j})
+  const double inv_sigma = 1.0 / d.sigma;
+  for (int e = tid; e < p * m; e += NYLS_BLOCK) {
+    const int j = e / m, s = e - j * m;
+    const double z = (nyls_grid_t(d, d.cond_i[j]) - nyls_grid_t(d, d.lidx[s])) * inv_sigma;
+    double kd[NYLS_MAX_P + 1];
+    nyls_kderiv(z, inv_sigma, kd);
+    kc[j * NYLS_MAX_M + s] = nyls_pick(kd, d.cond_d[j]);
+  }
+  __syncthreads();
+  for (int e = tid; e < N * N; e += NYLS_BLOCK) {
+    const int a = e / N, b = e - a * N;
+    double val = 0.0;
+    if (a < m && b < m) {
+      if (a < r && b < r) {
+        double acc = 0.0;
+        if (eigbasis) {
+          acc = S[a * g + b] / sqrt(lamv[a] * lamv[b]);
+        } else {
+          for (int s = 0; s < m; ++s) acc += W[s * m + a] * T[s * m + b];
+        }
+        val = gam * acc + (a == b ? 1.0 : 0.0);
+      } else {
+        val = (a == b) ? 1.0 : 0.0;
+      }
+    } else if (a < m || b < m) {
+      const int k = a < m ? a : b, o = a < m ? b : a;  // k: feature index, o: b or lambda
+      if (k < r) {
+        if (o == m) {
+          double acc = 0.0;
+          if (eigbasis) acc = S[k * g + m] / sqrt(lamv[k]);
+          else
+            for (int s = 0; s < m; ++s) acc += W[s * m + k] * S[s * g + m];
+          val = gam * acc;
+        } else {
+          const int j = o - m - 1;
+          double acc = 0.0;
+          for (int s = 0; s < m; ++s) acc += W[s * m + k] * kc[j * NYLS_MAX_M + s];
+          val = acc;
+        }
+      }
+    } else if (a == m && b == m) {
+      val = gam * S[m * g + m];
+    } else if (a == m || b == m) {
+      const int j = (a == m ? b : a) - m - 1;
+      val = d.cond_d[j] == 0 ? 1.0 : 0.0;
+    }
+    K[a * lda + b] = val;
+  }
+  for (int a = tid; a < N; a += NYLS_BLOCK) {
+    double val;
+    if (a < m) {
+      double acc = 0.0;
+      if (a < r) {
+        if (eigbasis) acc = S[a * g + m + 1] / sqrt(lamv[a]);
+        else
+          for (int s = 0; s < m; ++s) acc += W[s * m + a] * S[s * g + m + 1];
+      }
+      val = gam * acc;
+    } else if (a == m) {
+      val = gam * S[m * g + m + 1];
+    } else {
+      val = d.v[a - m - 1];
+    }
+    rhs[a] = val;
+  }
+  // feature-space condition rows for later passes
+  for (int e = tid; e < p * m; e += NYLS_BLOCK) {
+    const int j = e / m, k = e - j * m;
+    double acc = 0.0;
+    if (k < r)
+      for (int s = 0; s < m; ++s) acc += W[s * m + k] * kc[j * NYLS_MAX_M + s];
+    ws[L.H + e] = acc;
+  }
+  __syncthreads();
+  if (kkt_out) {
+    double* ko = kkt_out + (size_t)inst * kn * kn;
+    for (int e = tid; e < N * N; e += NYLS_BLOCK) ko[e] = K[(e / N) * lda + e % N];
+    for (int a = tid; a < N; a += NYLS_BLOCK) rhs_out[(size_t)inst * kn + a] = rhs[a];
+  }
+  if (!factor) return;
+  const int sing = nyls_lu(K, lda, N, piv, red);
+  nyls_lu_solve(K, lda, N, piv, rhs);
+  for (int e = tid; e < N * N; e += NYLS_BLOCK) ws[L.lu + e] = K[(e / N) * lda + e % N];
+  for (int a = tid; a < N; a += NYLS_BLOCK) {
+    ws[L.piv + a] = (double)piv[a];
+    ws[L.x + a] = rhs[a];
+  }
+  for (int s = tid; s < m; s += NYLS_BLOCK) {
+    double acc = 0.0;
+    for (int k = 0; k < r; ++k) acc += W[s * m + k] * rhs[k];
+    ws[L.alpha + s] = acc;
+  }
+  if (tid == 0) {
+    int bits = (int)ws[L.info + 1];
+    if (sing) bits |= NYLS_S_SINGULAR;
+    for (int a = 0; a < N; ++a)
+      if (!(fabs(rhs[a]) <= 1.7976931348623157e308)) bits |= NYLS_S_NONFINITE;
+    ws[L.info + 1] = (double)bits;
+  }
+}
+
+}  // namespace
+
+size_t nyls_kkt_lds_bytes(int maxm, int maxp) {
+  const int N = maxm + 1 + maxp;
+  return ((size_t)N * (N + 1) + (N + 1) + NYLS_MAX_P * NYLS_MAX_M + 16) * sizeof(double) +
+         (size_t)(N + 1) * sizeof(int);
+}
+
+hipError_t nyls_launch_kkt(const nyls_plan_view& pv, double* ws, double* kkt_out, double* rhs_out,
+                           int factor, hipStream_t st) {
+  const size_t lds = nyls_kkt_lds_bytes(pv.maxm, pv.maxp);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_kkt),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const int kn = pv.maxm + 1 + NYLS_MAX_P;
+  hipLaunchKernelGGL(k_kkt, dim3(pv.batch), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws,
+                     kkt_out, rhs_out, kn, factor, -1, pv.mode == NYLS_MIXED ? 1 : 0);
+  return hipGetLastError();
+}

@@ -1,0 +1,150 @@
+// Internal declarations shared by the nyls HIP sources (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nyls.h"
+
+#define NYLS_BLOCK 256
+
+// One instance as the kernels see it (device-resident table, one entry per instance).
+struct nyls_desc {
+  int32_t p, n, m, uniform;
+  double t0, dt;
+  const double* t;       // explicit grid (uniform == 0)
+  const int32_t* lidx;   // [m] landmark grid indices (plan-owned device copy)
+  const double* f;       // [p][n]
+  const double* r;       // [n]
+  const double* v;       // [p]
+  int32_t cond_d[NYLS_MAX_P];
+  int32_t cond_i[NYLS_MAX_P];
+  double sigma, gamma, tau;
+  int64_t ws;            // first double of this instance's workspace block
+  int64_t goff;          // first grid point of this instance in per-point outputs
+};
+
+// Per-instance workspace block (offsets in doubles from nyls_desc::ws).
+struct nyls_wsl {
+  int64_t W, lam, info, gram, lu, piv, x, alpha, acc, H, mu, beta, tmp, U, aux, end;
+};
+
+__host__ __device__ inline nyls_wsl nyls_layout(int m, int p, int n_newton) {
+  // n_newton > 0 adds the Newton state (constant Jacobian block and scratch).
+  nyls_wsl L;
+  const int64_t g = m + 2, nk = m + 1 + p;
+  L.W = 0;                       // m*m   W[s*m + k] = U[s][k] / sqrt(lam_k), k < r
+  L.lam = L.W + (int64_t)m * m;  // m     eigenvalues, descending
+  L.info = L.lam + m;            // 8     [0] rank r, [1] status bits, [2] sweeps
+  L.gram = L.info + 8;           // g*g   kernel-space Gram of (p_i, c_i, r_i)
+  L.lu = L.gram + g * g;         // nk*nk LU factors of the KKT system (row-major)
+  L.piv = L.lu + nk * nk;        // nk    pivot rows
+  L.x = L.piv + nk;              // nk    (omega, b, lambda)
+  L.alpha = L.x + nk;            // m     alpha = W omega
+  L.acc = L.alpha + m;           // 4g    accumulators of the per-point passes
+  L.H = L.acc + 4 * g;           // p*m   condition rows h_j = W^T k^(d_j)(t_{i_j})
+  L.mu = L.H + (int64_t)p * m;   // nk    adjoint solution
+  L.beta = L.mu + nk;            // m     W mu_omega
+  L.tmp = L.beta + m;            // g*g   scratch (S W products, eigenvectors when m is large)
+  L.U = L.tmp + g * g;           // m*m   all eigenvectors (sorted, signed), U[s*m + k]
+  L.aux = L.U + (int64_t)m * m;  // Newton: constant block (m+2)^2 + weighted Gram (m+2)^2
+  L.end = L.aux + (n_newton > 0 ? 2 * g * g : 0);
+  L.end = (L.end + 7) & ~int64_t(7);
+  return L;
+}
+
+// Landmark time t_s and grid time t_i.
+__device__ inline double nyls_grid_t(const nyls_desc& d, int i) {
+  return d.uniform ? __dadd_rn(d.t0, __dmul_rn((double)i, d.dt)) : d.t[i];
+}
+
+__device__ inline bool nyls_is_condition_point(const nyls_desc& d, int i) {
+  bool c = false;
+  for (int j = 0; j < d.p; ++j) c |= (d.cond_i[j] == i);
+  return c;
+}
+
+// Kernel derivative values of K(t, t_s) in the first argument, all orders 0..NYLS_MAX_P:
+// d^q/dt^q K = (-1/sigma)^q H_q(z) exp(-z^2), z = (t - t_s) / sigma, with the physicists'
+// Hermite recurrence H_0 = 1, H_1 = 2z, H_{q+1} = 2z H_q - 2q H_{q-1}.  Every index is
+// static so the values stay in registers.
+__device__ inline void nyls_kderiv(double z, double inv_sigma, double (&kd)[NYLS_MAX_P + 1]) {
+  const double e = exp(-z * z);
+  double hm = 1.0, h = 2.0 * z, sc = -inv_sigma;
+  kd[0] = e;
+  kd[1] = sc * h * e;
+#pragma unroll
+  for (int q = 1; q < NYLS_MAX_P; ++q) {
+    const double hn = 2.0 * z * h - 2.0 * q * hm;
+    hm = h;
+    h = hn;
+    sc *= -inv_sigma;
+    kd[q + 1] = sc * h * e;
+  }
+}
+
+// Static selection kd[q] for a run-time q in 0..NYLS_MAX_P.
+template <typename T>
+__device__ inline T nyls_pick(const T (&kd)[NYLS_MAX_P + 1], int q) {
+  T v = kd[0];
+#pragma unroll
+  for (int k = 1; k <= NYLS_MAX_P; ++k) v = (q == k) ? kd[k] : v;
+  return v;
+}
+
+// Operator weights of L = d^p - sum_k f_k d^(p-k) on the derivative orders q = 0..NYLS_MAX_P:
+// w[p] = 1, w[p-k] = -f_k (k = 1..p), 0 above p.  fk(k) returns f_k at the point.
+template <typename T, typename F>
+__device__ inline void nyls_opweights(int p, F fk, T (&w)[NYLS_MAX_P + 1]) {
+#pragma unroll
+  for (int q = 0; q <= NYLS_MAX_P; ++q) w[q] = (q == p) ? T(1) : (q < p ? -T(fk(p - q)) : T(0));
+}
+
+template <typename T>
+__device__ inline T nyls_dot5(const T (&a)[NYLS_MAX_P + 1], const T (&b)[NYLS_MAX_P + 1]) {
+  T v = T(0);
+#pragma unroll
+  for (int q = 0; q <= NYLS_MAX_P; ++q) v += a[q] * b[q];
+  return v;
+}
+
+// Block-wide helpers (blockDim.x == NYLS_BLOCK).
+__device__ inline double nyls_block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < NYLS_BLOCK / 64; ++i) s += red[i];
+  return s;
+}
+
+// Host launchers (defined in the .hip files; all enqueue on `stream`).
+struct nyls_plan_view {
+  int32_t batch, mode, maxm, maxp, maxn;
+  const nyls_desc* d_desc;
+  const int32_t* d_order;   // instance order, most expensive first
+  int64_t total;
+  unsigned nt_mask;         // bit t set when some instance has ceil((m+2)/16) == t
+};
+
+// `single` >= 0 restricts a launch to that one instance (one workgroup).
+hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hipStream_t st);
+hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t st);
+hipError_t nyls_launch_gram32(const nyls_plan_view& pv, double* ws, hipStream_t st);
+hipError_t nyls_launch_kkt(const nyls_plan_view& pv, double* ws, double* kkt_out, double* rhs_out,
+                           int factor, hipStream_t st);
+hipError_t nyls_launch_points(const nyls_plan_view& pv, double* ws, int refine, double* yhat,
+                              double* omega, double* bias, double* lambda, int32_t* status,
+                              int single, hipStream_t st);
+hipError_t nyls_launch_features(const nyls_plan_view& pv, const double* ws, const double* t_eval,
+                                const int64_t* eval_off, int dmax, double* phi, double* eigval,
+                                int32_t* rank, int64_t max_eval, int single, hipStream_t st);
+hipError_t nyls_launch_predict(const nyls_plan_view& pv, const double* ws, const double* t_eval,
+                               const int64_t* eval_off, int d, double* out, int64_t max_eval,
+                               hipStream_t st);
+hipError_t nyls_launch_explicit_rows(const nyls_plan_view& pv, int inst, const double* ws,
+                                     const double* phi, double* rows, int n, int m,
+                                     hipStream_t st);
+hipError_t nyls_launch_explicit_kkt(const nyls_plan_view& pv, int inst, double* ws,
+                                    const double* phi, const double* C, hipStream_t st);

@@ -1,0 +1,283 @@
+"""Python binding of libnyls.so (C ABI in include/nyls.h).
+
+Argument marshalling only: device memory comes from torch tensors, work is enqueued
+on torch's current HIP stream, and every computation runs in the library's kernels.
+The library must be built (python -m paper_2510_04094_amd.build); nothing here falls
+back to another implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnyls.so")
+MAX_P = 4
+MAX_M = 128
+
+FP64, MIXED, FP64_EXPLICIT = 0, 1, 2
+S_TRUNCATED, S_SINGULAR, S_NONFINITE, S_EIG_NOCONV, S_SMALL_PIVOT = 1, 2, 4, 8, 16
+
+_lib = None
+
+
+class NylsError(RuntimeError):
+    pass
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("p", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+        ("uniform", ctypes.c_int32),
+        ("t0", ctypes.c_double), ("dt", ctypes.c_double),
+        ("t", ctypes.c_void_p), ("lidx", ctypes.c_void_p),
+        ("f", ctypes.c_void_p), ("r", ctypes.c_void_p), ("v", ctypes.c_void_p),
+        ("cond_d", ctypes.c_int32 * MAX_P), ("cond_i", ctypes.c_int32 * MAX_P),
+        ("sigma", ctypes.c_double), ("gamma", ctypes.c_double), ("tau", ctypes.c_double),
+    ]
+
+
+EXPORTS = {
+    "nyls_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+    "nyls_plan_destroy": (None, [ctypes.c_void_p]),
+    "nyls_workspace_size": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "nyls_total_points": (ctypes.c_int64, [ctypes.c_void_p]),
+    "nyls_max_m": (ctypes.c_int32, [ctypes.c_void_p]),
+    "nyls_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]),
+    "nyls_assemble": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]),
+    "nyls_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p]),
+    "nyls_predict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nyls_newton_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "nyls_newton_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nyls_newton_state_stride": (ctypes.c_int64, [ctypes.c_void_p]),
+    "nyls_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nyls_riccati_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nyls_error_string": (ctypes.c_char_p, [ctypes.c_int32]),
+}
+
+
+def load(path=LIB_PATH):
+    """Load the HIP library; raises if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise NylsError("libnyls.so not built: run `python -m paper_2510_04094_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise NylsError("%s failed: %d (%s)" % (what, rc, _lib.nyls_error_string(rc).decode()))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Batch:
+    """A batch of ODE instances resident on the GPU plus the library plan over them.
+
+    `instances` are dicts as produced by paper_2510_04094_amd.workloads (numpy arrays);
+    their coefficient, forcing and condition data are packed into device tensors that
+    the plan points into.  `mode` is FP64, MIXED or FP64_EXPLICIT.
+    """
+
+    def __init__(self, instances, mode=FP64, device="cuda"):
+        lib = load()
+        self.mode = mode
+        self.device = torch.device(device)
+        self.instances = instances
+        nb = len(instances)
+        ns = np.array([int(q["n"]) for q in instances], dtype=np.int64)
+        ps = np.array([int(q["p"]) for q in instances], dtype=np.int64)
+        self.n = ns
+        self.p = ps
+        self.m = np.array([int(q["m"]) for q in instances], dtype=np.int64)
+        self.goff = np.concatenate([[0], np.cumsum(ns)])
+        fo = np.concatenate([[0], np.cumsum(ns * ps)])
+        has_lin = all(("f" in q and "r" in q) for q in instances)
+        f_host = np.zeros(int(fo[-1]))
+        r_host = np.zeros(int(self.goff[-1]))
+        v_host = np.zeros(nb * MAX_P)
+        for i, q in enumerate(instances):
+            if has_lin:
+                f_host[fo[i]:fo[i + 1]] = np.asarray(q["f"], dtype=np.float64).reshape(-1)
+                r_host[self.goff[i]:self.goff[i + 1]] = np.asarray(q["r"], dtype=np.float64)
+            v_host[i * MAX_P:i * MAX_P + ps[i]] = np.asarray(q["v"], dtype=np.float64)
+        self.f = torch.tensor(f_host, dtype=torch.float64, device=self.device)
+        self.r = torch.tensor(r_host, dtype=torch.float64, device=self.device)
+        self.v = torch.tensor(v_host, dtype=torch.float64, device=self.device)
+        self._foff = fo
+        self._lidx_host = []
+        probs = (Problem * nb)()
+        for i, q in enumerate(instances):
+            pr = probs[i]
+            pr.p, pr.n, pr.m = int(q["p"]), int(q["n"]), int(q["m"])
+            pr.uniform = 1
+            pr.t0, pr.dt = float(q["t0"]), float(q["dt"])
+            pr.t = None
+            if q.get("lidx") is not None:
+                arr = (ctypes.c_int32 * pr.m)(*[int(x) for x in q["lidx"]])
+                self._lidx_host.append(arr)
+                pr.lidx = ctypes.cast(arr, ctypes.c_void_p)
+            else:
+                pr.lidx = None
+            if has_lin:
+                pr.f = self.f.data_ptr() + 8 * int(fo[i])
+                pr.r = self.r.data_ptr() + 8 * int(self.goff[i])
+            else:
+                pr.f = None
+                pr.r = None
+            pr.v = self.v.data_ptr() + 8 * i * MAX_P
+            for j in range(MAX_P):
+                pr.cond_d[j] = int(q["cond_d"][j]) if j < pr.p else 0
+                pr.cond_i[j] = int(q["cond_i"][j]) if j < pr.p else 0
+            pr.sigma, pr.gamma, pr.tau = float(q["sigma"]), float(q["gamma"]), float(q["tau"])
+        self._probs = probs
+        handle = ctypes.c_void_p()
+        _check(lib.nyls_plan_create(ctypes.cast(probs, ctypes.c_void_p), nb, mode, ctypes.byref(handle)),
+               "nyls_plan_create")
+        self.plan = handle
+        self.batch = nb
+        self.maxm = int(lib.nyls_max_m(handle))
+        self.total = int(lib.nyls_total_points(handle))
+        nbytes = int(lib.nyls_workspace_size(handle))
+        self.ws = torch.zeros(max(nbytes, 8), dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        if getattr(self, "plan", None) is not None and _lib is not None:
+            _lib.nyls_plan_destroy(self.plan)
+            self.plan = None
+
+    # --- per-instance views of flat outputs ---------------------------------------
+    def split_points(self, flat):
+        return [flat[self.goff[i]:self.goff[i + 1]] for i in range(self.batch)]
+
+    # --- work functions -------------------------------------------------------------
+    def solve(self, refine=None):
+        """nyls_solve: returns dict(yhat [total], omega [batch, maxm], bias, lam, status)."""
+        if refine is None:
+            refine = 4 if self.mode != FP64_EXPLICIT else 0
+        dev = self.device
+        out = dict(
+            yhat=torch.empty(self.total, dtype=torch.float64, device=dev),
+            omega=torch.empty(self.batch, self.maxm, dtype=torch.float64, device=dev),
+            bias=torch.empty(self.batch, dtype=torch.float64, device=dev),
+            lam=torch.empty(self.batch, MAX_P, dtype=torch.float64, device=dev),
+            status=torch.empty(self.batch, dtype=torch.int32, device=dev),
+        )
+        _check(_lib.nyls_solve(self.plan, refine, _ptr(out["omega"]), _ptr(out["bias"]), _ptr(out["lam"]),
+                               _ptr(out["yhat"]), _ptr(out["status"]), _ptr(self.ws), _stream()),
+               "nyls_solve")
+        return out
+
+    def assemble(self):
+        kn = self.maxm + 1 + MAX_P
+        kkt = torch.zeros(self.batch, kn * kn, dtype=torch.float64, device=self.device)
+        rhs = torch.zeros(self.batch, kn, dtype=torch.float64, device=self.device)
+        _check(_lib.nyls_assemble(self.plan, _ptr(kkt), _ptr(rhs), _ptr(self.ws), _stream()), "nyls_assemble")
+        return kkt, rhs
+
+    def _offsets(self, t_eval_list):
+        counts = [len(t) for t in t_eval_list]
+        off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        t = torch.tensor(np.concatenate([np.asarray(x, dtype=np.float64) for x in t_eval_list]),
+                         dtype=torch.float64, device=self.device)
+        o = torch.tensor(off, dtype=torch.int64, device=self.device)
+        return t, o, off
+
+    def features(self, t_eval_list, dmax):
+        """nyls_features at per-instance times: returns (phi [E, dmax+1, maxm], eigval, rank, offsets)."""
+        t, o, off = self._offsets(t_eval_list)
+        phi = torch.empty(int(off[-1]), dmax + 1, self.maxm, dtype=torch.float64, device=self.device)
+        eig = torch.empty(self.batch, self.maxm, dtype=torch.float64, device=self.device)
+        rank = torch.empty(self.batch, dtype=torch.int32, device=self.device)
+        _check(_lib.nyls_features(self.plan, _ptr(t), _ptr(o), dmax, _ptr(phi), _ptr(eig), _ptr(rank),
+                                  _ptr(self.ws), _stream()), "nyls_features")
+        return phi, eig, rank, off
+
+    def predict(self, t_eval_list, d=0):
+        t, o, off = self._offsets(t_eval_list)
+        out = torch.empty(int(off[-1]), dtype=torch.float64, device=self.device)
+        _check(_lib.nyls_predict(self.plan, _ptr(t), _ptr(o), d, _ptr(out), _ptr(self.ws), _stream()),
+               "nyls_predict")
+        return out, off
+
+    # --- nonlinear (Lemma 2) -----------------------------------------------------------
+    def newton_init(self):
+        """nyls_newton_init: returns the state tensor x [batch, stride]."""
+        stride = int(_lib.nyls_newton_state_stride(self.plan))
+        x = torch.zeros(self.batch, stride, dtype=torch.float64, device=self.device)
+        _check(_lib.nyls_newton_init(self.plan, _ptr(x), _ptr(self.ws), _stream()), "nyls_newton_init")
+        self._newton_bufs = [torch.empty(self.total, dtype=torch.float64, device=self.device) for _ in range(3)]
+        self._step_inf = torch.empty(self.batch, dtype=torch.float64, device=self.device)
+        self._status = torch.empty(self.batch, dtype=torch.int32, device=self.device)
+        return x
+
+    def newton_step(self, x, F, Fy, Fyy):
+        """nyls_newton_step with caller-evaluated F, Fy, Fyy [total points]; returns step_inf."""
+        _check(_lib.nyls_newton_step(self.plan, _ptr(F), _ptr(Fy), _ptr(Fyy), _ptr(x), _ptr(self._step_inf),
+                                     _ptr(self._status), _ptr(self.ws), _stream()), "nyls_newton_step")
+        return self._step_inf
+
+    def riccati_eval(self, q, x, gauss_newton):
+        F, Fy, Fyy = self._newton_bufs
+        _check(_lib.nyls_riccati_eval(self.plan, _ptr(q), _ptr(x), 1 if gauss_newton else 0, _ptr(F), _ptr(Fy),
+                                      _ptr(Fyy), _stream()), "nyls_riccati_eval")
+        return F, Fy, Fyy
+
+    def riccati_newton(self, q, max_iter=15, tol=1e-12, gauss_newton_steps=2):
+        """Newton on y' = q(t) - y^2 for every instance: the first `gauss_newton_steps`
+        steps use the Gauss-Newton y-block, then exact Newton; stops when every instance's
+        |dx|_inf <= tol * max(1, |x|_inf).  Returns (x, steps [iters, batch])."""
+        x = self.newton_init()
+        hist = []
+        for k in range(max_iter):
+            F, Fy, Fyy = self.riccati_eval(q, x, k < gauss_newton_steps)
+            si = self.newton_step(x, F, Fy, Fyy).clone()
+            hist.append(si)
+            xinf = torch.clamp(torch.max(torch.abs(x), dim=1).values, min=1.0)
+            if bool(torch.all(si <= tol * xinf)):
+                break
+        return x, torch.stack(hist)
+
+    # --- adjoint --------------------------------------------------------------------------
+    def backward(self, t_obs_list, g_obs_list):
+        """nyls_backward after solve(): gradients of a loss with dl/dy_hat(s_j) = g_j."""
+        t, o, off = self._offsets(t_obs_list)
+        g = torch.tensor(np.concatenate([np.asarray(x, dtype=np.float64) for x in g_obs_list]),
+                         dtype=torch.float64, device=self.device)
+        dev = self.device
+        out = dict(
+            dl_df=torch.zeros(MAX_P, self.total, dtype=torch.float64, device=dev),
+            dl_dr=torch.zeros(self.total, dtype=torch.float64, device=dev),
+            dl_dv=torch.zeros(self.batch, MAX_P, dtype=torch.float64, device=dev),
+            dl_dsigma=torch.zeros(self.batch, dtype=torch.float64, device=dev),
+            dl_dgamma=torch.zeros(self.batch, dtype=torch.float64, device=dev),
+        )
+        _check(_lib.nyls_backward(self.plan, _ptr(t), _ptr(o), _ptr(g), _ptr(out["dl_df"]), _ptr(out["dl_dr"]),
+                                  _ptr(out["dl_dv"]), _ptr(out["dl_dsigma"]), _ptr(out["dl_dgamma"]),
+                                  _ptr(self.ws), _stream()), "nyls_backward")
+        return out

@@ -1,0 +1,107 @@
+"""GPU parity of the adjoint (backward) kernel against the oracle gradient and against
+central finite differences of the GPU forward solve."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2510_04094_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def instances(count, n=1000, m=50):
+    return [workloads.linear_second_order(i, n=n, m=m, obs=100, config=5) for i in range(count)]
+
+
+def loss_grad_obs(yh_obs, y_obs):
+    return 2.0 * (yh_obs - y_obs) / yh_obs.size
+
+
+def gpu_gradients(gpu_lib, insts, mode):
+    b = gpu_lib.Batch(insts, mode=mode)
+    b.solve()
+    yo, off = b.predict([q["t_obs"] for q in insts], 0)
+    yo = yo.cpu().numpy()
+    g = [loss_grad_obs(yo[off[i]:off[i + 1]], q["y_obs"]) for i, q in enumerate(insts)]
+    out = b.backward([q["t_obs"] for q in insts], g)
+    torch.cuda.synchronize()
+    return b, {k: v.cpu().numpy() for k, v in out.items()}, g
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+@pytest.mark.parametrize("mode_name", ["FP64", "MIXED"])
+def test_backward_matches_oracle(gpu_lib, mode_name):
+    insts = instances(6)
+    b, out, g = gpu_gradients(gpu_lib, insts, getattr(gpu_lib, mode_name))
+    for i, q in enumerate(insts):
+        ref = oracle.adjoint.grad(q, q["t_obs"], g[i])
+        o = slice(b.goff[i], b.goff[i + 1])
+        for k in range(q["p"]):
+            gf, rf = out["dl_df"][k, o], ref["dl_df"][k]
+            assert np.max(np.abs(gf - rf)) <= 1e-5 * np.max(np.abs(rf)), ("df", i, k)
+        assert np.max(np.abs(out["dl_dr"][o] - ref["dl_dr"])) <= 1e-5 * np.max(np.abs(ref["dl_dr"]))
+        for j in range(q["p"]):
+            assert rel(out["dl_dv"][i, j], ref["dl_dv"][j]) <= 1e-5, ("dv", i, j)
+        # dl/dsigma is a sum of terms that can cancel by orders of magnitude (instances with
+        # a truncated basis): bound the error by 1e-5 of the value plus 1e-8 of its terms
+        scale = 1e-5 * abs(ref["dl_dsigma"]) + 1e-8 * np.max(np.abs(ref["sigma_terms"]))
+        assert abs(out["dl_dsigma"][i] - ref["dl_dsigma"]) <= scale, ("dsigma", i, out["dl_dsigma"][i], ref["dl_dsigma"])
+        assert rel(out["dl_dgamma"][i], ref["dl_dgamma"]) <= 1e-3, ("dgamma", i)
+
+
+def gpu_loss(gpu_lib, insts):
+    b = gpu_lib.Batch(insts, mode=gpu_lib.FP64)
+    b.solve()
+    yo, off = b.predict([q["t_obs"] for q in insts], 0)
+    yo = yo.cpu().numpy()
+    return np.array([np.mean((yo[off[i]:off[i + 1]] - q["y_obs"]) ** 2) for i, q in enumerate(insts)])
+
+
+def test_parameter_gradients_match_central_differences(gpu_lib):
+    """Config-5 style check: alpha_0, alpha_1 (a(t) = a0 + a1 cos t enters as f_2 = -a),
+    y0, y'0 with h = 1e-6, sigma with a relative step, all through GPU forward solves."""
+    insts = instances(4)
+    b, out, _ = gpu_gradients(gpu_lib, insts, gpu_lib.FP64)
+    h = 1e-6
+    for name in ["a0", "a1", "y0", "dy0", "sigma"]:
+        plus, minus = [], []
+        for q in insts:
+            qp, qm = dict(q), dict(q)
+            if name in ("a0", "a1"):
+                basis = np.ones_like(q["t"]) if name == "a0" else np.cos(q["t"])
+                for qq, sgn in ((qp, 1), (qm, -1)):
+                    f = q["f"].copy()
+                    f[1] = f[1] - sgn * h * basis
+                    qq["f"] = f
+            elif name in ("y0", "dy0"):
+                j = 0 if name == "y0" else 1
+                for qq, sgn in ((qp, 1), (qm, -1)):
+                    v = q["v"].copy()
+                    v[j] += sgn * h
+                    qq["v"] = v
+            else:
+                qp["sigma"] = q["sigma"] * (1 + h)
+                qm["sigma"] = q["sigma"] * (1 - h)
+            plus.append(qp)
+            minus.append(qm)
+        fd = (gpu_loss(gpu_lib, plus) - gpu_loss(gpu_lib, minus)) / (2 * h)
+        for i, q in enumerate(insts):
+            o = slice(b.goff[i], b.goff[i + 1])
+            if name == "a0":
+                got = -np.sum(out["dl_df"][1, o])
+            elif name == "a1":
+                got = -np.sum(np.cos(q["t"]) * out["dl_df"][1, o])
+            elif name == "y0":
+                got = out["dl_dv"][i, 0]
+            elif name == "dy0":
+                got = out["dl_dv"][i, 1]
+            else:
+                got = out["dl_dsigma"][i]
+                fd_i = fd[i] / q["sigma"]
+                assert rel(got, fd_i) <= 1e-4, (name, i, got, fd_i)
+                continue
+            assert rel(got, fd[i]) <= 1e-4, (name, i, got, fd[i])

@@ -1,0 +1,75 @@
+"""GPU parity of the Lemma 2 Newton iteration (first-order nonlinear, Riccati workload)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2510_04094_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def riccati_fun(q, gauss_newton):
+    def fun(idx, y):
+        return q[idx] - y * y, -2.0 * y, (0.0 if gauss_newton else -2.0) * np.ones_like(y)
+    return fun
+
+
+def oracle_schedule(prob, iters, gn=2):
+    st = oracle.newton.setup(prob)
+    x = oracle.newton.initial_state(st, prob)
+    steps = []
+    for k in range(iters):
+        x, dx = oracle.newton.step_schur(x, st, prob, riccati_fun(prob["q"], k < gn))
+        steps.append(np.max(np.abs(dx)))
+    r = st["r"]
+    yh = oracle.nystrom.kvec(0, st["t"], st["t_land"], prob["sigma"]) @ (st["W"] @ x[:r]) + x[r]
+    return x, yh, steps, st
+
+
+@pytest.mark.parametrize("n,count", [(300, 4), (2000, 8)])
+def test_newton_matches_oracle(gpu_lib, n, count):
+    insts = [workloads.riccati(i, n=n) for i in range(count)]
+    b = gpu_lib.Batch(insts, mode=gpu_lib.FP64)
+    q = torch.tensor(np.concatenate([p["q"] for p in insts]), dtype=torch.float64, device="cuda")
+    x, hist = b.riccati_newton(q, max_iter=15, tol=1e-12, gauss_newton_steps=2)
+    iters = hist.shape[0]
+    yh, off = b.predict([p["t"] for p in insts], 0)
+    torch.cuda.synchronize()
+    yh = yh.cpu().numpy()
+    xs = x.cpu().numpy()
+    for i, p in enumerate(insts):
+        xo, yo, steps, st = oracle_schedule(p, iters)
+        got = yh[off[i]:off[i + 1]]
+        err = np.max(np.abs(got - yo)) / np.max(np.abs(yo))
+        assert err <= 1e-10, (i, err)
+        # the slack unknowns y_i and the bias are gauge-free too
+        yg = xs[i, b.maxm + 2:b.maxm + 2 + p["n"]][st["idx"]]
+        assert np.max(np.abs(yg - xo[st["r"] + 2:])) <= 1e-10 * np.max(np.abs(xo[st["r"] + 2:]))
+        assert abs(xs[i, b.maxm] - xo[st["r"]]) <= 1e-10
+        # the manufactured solution is recovered
+        assert np.max(np.abs(got - p["ystar"])) < 2e-3
+
+
+def test_newton_first_steps_track_oracle(gpu_lib):
+    """Step by step: |dx|_inf of the first iterations agrees with the oracle (the early
+    iterates are far from the solution and ill-conditioned, hence 1e-4)."""
+    insts = [workloads.riccati(i, n=500) for i in range(3)]
+    b = gpu_lib.Batch(insts, mode=gpu_lib.FP64)
+    q = torch.tensor(np.concatenate([p["q"] for p in insts]), dtype=torch.float64, device="cuda")
+    x = b.newton_init()
+    got = []
+    for k in range(5):
+        F, Fy, Fyy = b.riccati_eval(q, x, k < 2)
+        got.append(b.newton_step(x, F, Fy, Fyy).clone())
+    got = torch.stack(got).cpu().numpy()
+    for i, p in enumerate(insts):
+        _, _, steps, _ = oracle_schedule(p, 5)
+        np.testing.assert_allclose(got[:, i], steps, rtol=1e-4)
+
+
+def test_newton_requires_first_order(gpu_lib):
+    insts = [workloads.linear_second_order(0, n=300)]
+    b = gpu_lib.Batch(insts, mode=gpu_lib.FP64)
+    with pytest.raises(gpu_lib.NylsError):
+        b.newton_init()
