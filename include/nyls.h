@@ -199,12 +199,23 @@ int nyls_riccati_eval(const nyls_plan* plan, const double* q, const double* x,
  *         (rows k > p left untouched); dl_dr [total points];
  *   dl_dv [batch][4]; dl_dsigma [batch]; dl_dgamma [batch]  (outputs may be NULL)
  * Gradients w.r.t. the data f, r, v are exact derivatives of the Lemma 1 solution;
- * sigma enters through the kernel values and through K_mm (spectral derivative).  In
- * mixed mode the adjoint solve is refined in FP64 (two matrix-free steps).  Not available
- * for NYLS_FP64_EXPLICIT plans. */
+ * sigma enters through the kernel values and through K_mm (spectral derivative).  The
+ * adjoint solve is refined in FP64 (matrix-free, up to three steps, stopping at rounding
+ * level) because the stored factors are of an approximate system.  Not available for
+ * NYLS_FP64_EXPLICIT plans. */
 int nyls_backward(const nyls_plan* plan, const double* t_obs, const int64_t* obs_off,
                   const double* dl_dyobs, double* dl_df, double* dl_dr, double* dl_dv,
                   double* dl_dsigma, double* dl_dgamma, void* ws, hipStream_t stream);
+
+/* Optional kernel timing for measurement tools: when enabled, every kernel launch of the
+ * work functions is bracketed by HIP events on its stream (a few microseconds per launch).
+ * nyls_profile_read synchronises the recorded events and returns the accumulated time
+ * and launch count of one kernel: 0 basis/eigen, 1 FP64 Gram, 2 FP32 (MFMA) Gram, 3 KKT
+ * assembly + LU, 4 refinement/output pass, 5 features, 6 predict, 7 explicit baseline,
+ * 8 Newton step, 9 adjoint.  Host-side state, not thread-safe. */
+void nyls_profile_enable(int32_t on);
+int nyls_profile_read(int32_t kernel, double* total_ms, int64_t* count);
+void nyls_profile_reset(void);
 
 /* Static text for a NYLS_E* code or a single NYLS_S* bit. */
 const char* nyls_error_string(int32_t code);

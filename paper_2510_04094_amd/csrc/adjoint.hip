@@ -5,7 +5,8 @@
 // With x = (omega, b, lambda) solving A x = rhs (A symmetric), alpha = W omega and the ODE
 // residual e_i = p_i^T alpha + c_i b - r_i:
 //   1. x_bar = (W^T kbar, sum_j g_j, 0), kbar = sum_j g_j k_m(s_j);  mu = A^{-1} x_bar
-//      (plus FP64 iterative refinement of mu when the factors are FP32-assembled);
+//      (plus FP64 iterative refinement of mu: the stored factors are of the FP32 or the
+//      kernel-space FP64 Gram, which lose accuracy for ill-conditioned K_mm);
 //   2. beta = W mu_omega, nu_i = beta^T p_i + c_i mu_b,
 //      yh^(q)_i = alpha^T k^(q)_i + [q=0] b,  zh^(q)_i = beta^T k^(q)_i + [q=0] mu_b;
 //   3. dl/df_k(t_i) = gamma (e_i zh^(p-k)_i + nu_i yh^(p-k)_i), dl/dr(t_i) = gamma nu_i,
@@ -224,8 +225,23 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_backward(
     for (int a = tid; a < N; a += NYLS_BLOCK) R[a] = part[NYLS_BLOCK + a];
     __syncthreads();
     nyls_lu_solve(LU, N, N, piv, R);
-    for (int a = tid; a < N; a += NYLS_BLOCK) mu[a] += R[a];
+    double dn = 0.0, xn = 0.0;
+    for (int a = tid; a < N; a += NYLS_BLOCK) {
+      mu[a] += R[a];
+      dn = fmax(dn, fabs(R[a]));
+      xn = fmax(xn, fabs(mu[a]));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      dn = fmax(dn, __shfl_xor(dn, o));
+      xn = fmax(xn, __shfl_xor(xn, o));
+    }
     __syncthreads();
+    if ((tid & 63) == 0) { part[tid >> 6] = dn; part[8 + (tid >> 6)] = xn; }
+    __syncthreads();
+    dn = fmax(fmax(part[0], part[1]), fmax(part[2], part[3]));
+    xn = fmax(fmax(part[8], part[9]), fmax(part[10], part[11]));
+    __syncthreads();
+    if (dn <= 1e-13 * xn) refine = step + 1;  // converged: the next iteration only forms beta
   }
   const double mub = mu[m];
 
@@ -423,12 +439,14 @@ extern "C" int nyls_backward(const nyls_plan* pl, const double* t_obs, const int
   if (!pl || !t_obs || !obs_off || !dl_dyobs || !ws) return NYLS_E_NULL;
   const nyls_plan_view pv = nyls_plan_get_view(pl);
   if (pv.mode == NYLS_FP64_EXPLICIT) return NYLS_E_MODE;
-  const int refine = pv.mode == NYLS_MIXED ? 2 : 0;
+  const int refine = 3;  // at most; stops once the correction is at rounding level
   const size_t lds = backward_lds_bytes(pv.maxm, pv.maxp);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_backward),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  nyls_prof_begin(NYLS_K_BACKWARD, stream);
   hipLaunchKernelGGL(k_backward, dim3(pv.batch), dim3(NYLS_BLOCK), lds, stream, pv.d_desc,
                      static_cast<double*>(ws), refine, t_obs, obs_off, dl_dyobs, dl_df, dl_dr, dl_dv,
                      dl_dsigma, dl_dgamma, pv.total, pv.maxm);
+  nyls_prof_end(NYLS_K_BACKWARD, stream);
   return hipGetLastError() == hipSuccess ? NYLS_OK : NYLS_E_HIP;
 }

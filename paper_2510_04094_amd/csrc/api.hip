@@ -77,7 +77,44 @@ nyls_plan_view view(const nyls_plan* pl) {
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? NYLS_OK : NYLS_E_HIP; }
 
+// --- optional kernel timing -------------------------------------------------------------
+struct ProfState {
+  int enabled = 0;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  hipEvent_t open[NYLS_K_COUNT] = {};
+  double total_ms[NYLS_K_COUNT] = {};
+  int64_t count[NYLS_K_COUNT] = {};
+};
+ProfState g_prof;
+
+hipEvent_t prof_event() {
+  if (!g_prof.pool.empty()) {
+    hipEvent_t e = g_prof.pool.back();
+    g_prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
 }  // namespace
+
+void nyls_prof_begin(int k, hipStream_t st) {
+  if (!g_prof.enabled) return;
+  hipEvent_t e = prof_event();
+  (void)hipEventRecord(e, st);
+  g_prof.open[k] = e;
+}
+
+void nyls_prof_end(int k, hipStream_t st) {
+  if (!g_prof.enabled || !g_prof.open[k]) return;
+  hipEvent_t e = prof_event();
+  (void)hipEventRecord(e, st);
+  g_prof.pending.push_back({k, {g_prof.open[k], e}});
+  g_prof.open[k] = nullptr;
+}
 
 // accessors used by the other translation units
 int64_t nyls_plan_newton_stride(const nyls_plan* pl) {
@@ -200,9 +237,13 @@ int nyls_features(const nyls_plan* pl, const double* t_eval, const int64_t* eval
   if (dmax < 0 || dmax > NYLS_MAX_P) return NYLS_E_ARG;
   const nyls_plan_view pv = view(pl);
   double* w = static_cast<double*>(ws);
+  nyls_prof_begin(NYLS_K_EIG, stream);
   hipError_t e = nyls_launch_eig(pv, w, -1, stream);
+  nyls_prof_end(NYLS_K_EIG, stream);
+  nyls_prof_begin(NYLS_K_FEATURES, stream);
   if (e == hipSuccess)
     e = nyls_launch_features(pv, w, t_eval, eval_off, dmax, phi, eigval, rank, 1 << 20, -1, stream);
+  nyls_prof_end(NYLS_K_FEATURES, stream);
   return hip_rc(e);
 }
 
@@ -253,12 +294,21 @@ int nyls_solve(const nyls_plan* pl, int32_t refine_steps, double* omega, double*
     }
     return hip_rc(e);
   }
+  const int gk = pl->mode == NYLS_MIXED ? NYLS_K_GRAM32 : NYLS_K_GRAM64;
+  nyls_prof_begin(NYLS_K_EIG, stream);
   e = nyls_launch_eig(pv, w, -1, stream);
+  nyls_prof_end(NYLS_K_EIG, stream);
+  nyls_prof_begin(gk, stream);
   if (e == hipSuccess)
     e = (pl->mode == NYLS_MIXED) ? nyls_launch_gram32(pv, w, stream) : nyls_launch_gram64(pv, w, stream);
+  nyls_prof_end(gk, stream);
+  nyls_prof_begin(NYLS_K_KKT, stream);
   if (e == hipSuccess) e = nyls_launch_kkt(pv, w, nullptr, nullptr, 1, stream);
+  nyls_prof_end(NYLS_K_KKT, stream);
+  nyls_prof_begin(NYLS_K_POINTS, stream);
   if (e == hipSuccess)
     e = nyls_launch_points(pv, w, refine_steps, yhat, omega, bias, lambda, status, -1, stream);
+  nyls_prof_end(NYLS_K_POINTS, stream);
   return hip_rc(e);
 }
 
@@ -266,8 +316,37 @@ int nyls_predict(const nyls_plan* pl, const double* t_eval, const int64_t* eval_
                  double* out, const void* ws, hipStream_t stream) {
   if (!pl || !t_eval || !eval_off || !out || !ws) return NYLS_E_NULL;
   if (d < 0 || d > NYLS_MAX_P) return NYLS_E_ARG;
-  return hip_rc(nyls_launch_predict(view(pl), static_cast<const double*>(ws), t_eval, eval_off, d,
-                                    out, 1 << 20, stream));
+  nyls_prof_begin(NYLS_K_PREDICT, stream);
+  const hipError_t e = nyls_launch_predict(view(pl), static_cast<const double*>(ws), t_eval, eval_off,
+                                           d, out, 1 << 20, stream);
+  nyls_prof_end(NYLS_K_PREDICT, stream);
+  return hip_rc(e);
+}
+
+void nyls_profile_enable(int32_t on) { g_prof.enabled = on ? 1 : 0; }
+
+int nyls_profile_read(int32_t kernel, double* total_ms, int64_t* count) {
+  if (kernel < 0 || kernel >= NYLS_K_COUNT || !total_ms || !count) return NYLS_E_ARG;
+  for (auto& pr : g_prof.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pr.second.second) != hipSuccess) return NYLS_E_HIP;
+    if (hipEventElapsedTime(&ms, pr.second.first, pr.second.second) != hipSuccess) return NYLS_E_HIP;
+    g_prof.total_ms[pr.first] += ms;
+    g_prof.count[pr.first] += 1;
+    g_prof.pool.push_back(pr.second.first);
+    g_prof.pool.push_back(pr.second.second);
+  }
+  g_prof.pending.clear();
+  *total_ms = g_prof.total_ms[kernel];
+  *count = g_prof.count[kernel];
+  return NYLS_OK;
+}
+
+void nyls_profile_reset(void) {
+  int64_t c;
+  double t;
+  nyls_profile_read(0, &t, &c);
+  for (int k = 0; k < NYLS_K_COUNT; ++k) { g_prof.total_ms[k] = 0.0; g_prof.count[k] = 0; }
 }
 
 const char* nyls_error_string(int32_t code) {

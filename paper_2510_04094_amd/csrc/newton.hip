@@ -427,8 +427,10 @@ extern "C" int nyls_newton_step(const nyls_plan* pl, const double* F, const doub
   const size_t lds = step_lds_bytes(pv.maxm);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_newton_step),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  nyls_prof_begin(NYLS_K_NEWTON, stream);
   hipLaunchKernelGGL(k_newton_step, dim3(pv.batch), dim3(NYLS_BLOCK), lds, stream, pv.d_desc,
                      static_cast<double*>(ws), F, Fy, Fyy, x, (int64_t)nyls_plan_newton_stride(pl),
                      step_inf, status, pv.maxm);
+  nyls_prof_end(NYLS_K_NEWTON, stream);
   return hipGetLastError() == hipSuccess ? NYLS_OK : NYLS_E_HIP;
 }

@@ -119,6 +119,12 @@ __device__ inline double nyls_block_sum(double v, double* red) {
   return s;
 }
 
+// Optional per-kernel timing with HIP events (off unless nyls_profile_enable(1)).
+void nyls_prof_begin(int kernel, hipStream_t st);
+void nyls_prof_end(int kernel, hipStream_t st);
+enum { NYLS_K_EIG = 0, NYLS_K_GRAM64, NYLS_K_GRAM32, NYLS_K_KKT, NYLS_K_POINTS, NYLS_K_FEATURES,
+       NYLS_K_PREDICT, NYLS_K_EXPLICIT, NYLS_K_NEWTON, NYLS_K_BACKWARD, NYLS_K_COUNT };
+
 // Host launchers (defined in the .hip files; all enqueue on `stream`).
 struct nyls_plan_view {
   int32_t batch, mode, maxm, maxp, maxn;

@@ -63,8 +63,34 @@ EXPORTS = {
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nyls_riccati_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nyls_profile_enable": (None, [ctypes.c_int32]),
+    "nyls_profile_read": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "nyls_profile_reset": (None, []),
     "nyls_error_string": (ctypes.c_char_p, [ctypes.c_int32]),
 }
+
+KERNELS = ["eig", "gram64", "gram32", "kkt", "points", "features", "predict", "explicit",
+           "newton", "backward"]
+
+
+def profile_enable(on=True):
+    load().nyls_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    load().nyls_profile_reset()
+
+
+def profile_read():
+    """{kernel name: (total ms, launches)} of the kernel timing since the last reset."""
+    lib = load()
+    out = {}
+    for k, name in enumerate(KERNELS):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check(lib.nyls_profile_read(k, ctypes.byref(ms), ctypes.byref(cnt)), "nyls_profile_read")
+        out[name] = (ms.value, cnt.value)
+    return out
 
 
 def load(path=LIB_PATH):
