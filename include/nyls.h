@@ -73,7 +73,8 @@ enum {
   NYLS_S_SINGULAR = 2,        /* a zero pivot in the KKT / Schur factorisation */
   NYLS_S_NONFINITE = 4,       /* a NaN or Inf appeared in the solution */
   NYLS_S_EIG_NOCONV = 8,      /* the Jacobi eigensolver hit its sweep limit */
-  NYLS_S_SMALL_PIVOT = 16     /* Newton: a diagonal y-block entry |d_i| < 1e-10 gamma */
+  NYLS_S_SMALL_PIVOT = 16,    /* Newton: a diagonal y-block entry |d_i| < 1e-10 gamma */
+  NYLS_S_REFINE_NOCONV = 32   /* refinement ended with a correction above 1e-12 max|y_hat| */
 };
 
 /*

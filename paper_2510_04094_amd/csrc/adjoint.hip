@@ -24,12 +24,13 @@
 namespace {
 
 constexpr int TP = 16;
+constexpr int CH = 8;                 // points per thread in the Gaussian recurrence
 constexpr int TPG = NYLS_BLOCK / TP;  // threads per point in the dot products
 
 // d/dsigma of the q-th kernel derivative:
 // (-1)^(q+1) sigma^(-q-1) e^{-z^2} (q H_q(z) - z H_{q+1}(z)), all q = 0..NYLS_MAX_P.
-__device__ inline void kderiv_dsigma(double z, double inv_sigma, double (&ds)[NYLS_MAX_P + 1]) {
-  const double e = exp(-z * z);
+__device__ inline void kderiv_dsigma_e(double z, double e, double inv_sigma,
+                                       double (&ds)[NYLS_MAX_P + 1]) {
   double hm = 1.0, h = 2.0 * z;     // H_q, H_{q+1} with q = 0
   double sc = -inv_sigma;           // (-1)^(q+1) sigma^(-q-1)
 #pragma unroll
@@ -40,6 +41,10 @@ __device__ inline void kderiv_dsigma(double z, double inv_sigma, double (&ds)[NY
     h = hn;
     sc *= -inv_sigma;
   }
+}
+
+__device__ inline void kderiv_dsigma(double z, double inv_sigma, double (&ds)[NYLS_MAX_P + 1]) {
+  kderiv_dsigma_e(z, exp(-z * z), inv_sigma, ds);
 }
 
 __global__ __launch_bounds__(NYLS_BLOCK) void k_backward(
@@ -77,7 +82,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_backward(
   double* part = ug + 2 * NYLS_MAX_M;   // [2][256]
   double* red = part + 2 * NYLS_BLOCK;  // [16]
   double* pd = red + 16;                // [TP][8] per-point scalars
-  int* piv = reinterpret_cast<int*>(pd + TP * 8);  // [136]
+  double* wq = pd + TP * 8;             // [TP][NYLS_MAX_P+1] operator weights per point
+  int* piv = reinterpret_cast<int*>(wq + TP * (NYLS_MAX_P + 1));  // [136]
   double* big = reinterpret_cast<double*>(piv + 136);
   double* P = big;                      // [TP][m]   p_i
   double* DP = P + TP * maxm;           // [TP][m]   d p_i / d sigma
@@ -153,19 +159,24 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_backward(
     double nacc = 0.0, cacc = 0.0;
     for (int i0 = 0; i0 < n; i0 += TP) {
       __syncthreads();
-      for (int e = tid; e < TP * m; e += NYLS_BLOCK) {
-        const int pt = e / m, s = e - pt * m;
-        const int i = i0 + pt;
-        double val = 0.0;
-        if (i < n && !nyls_is_condition_point(d, i)) {
-          const double z = (nyls_grid_t(d, i) - tl[s]) * inv_sigma;
-          double kd[NYLS_MAX_P + 1], w[NYLS_MAX_P + 1];
-          nyls_kderiv(z, inv_sigma, kd);
-          nyls_opweights(p, [&](int k) { return d.f[(size_t)(k - 1) * n + i]; }, w);
-          val = nyls_dot5(w, kd);
-        }
-        P[pt * m + s] = val;
+      for (int e = tid; e < TP; e += NYLS_BLOCK) {
+        const int i = i0 + e;
+        const bool ok = i < n && !nyls_is_condition_point(d, i);
+        double w[NYLS_MAX_P + 1];
+        nyls_opweights(p, [&](int k) { return ok ? d.f[(size_t)(k - 1) * n + i] : 0.0; }, w);
+#pragma unroll
+        for (int q = 0; q <= NYLS_MAX_P; ++q) wq[e * (NYLS_MAX_P + 1) + q] = w[q];
       }
+      __syncthreads();
+      nyls_gauss_tile<TP, CH>(d, i0, tl, inv_sigma, [&](int pt, int s, double zz, double ev) {
+        double kd[NYLS_MAX_P + 1];
+        nyls_kderiv_e(zz, ev, inv_sigma, kd);
+        const double* w = wq + pt * (NYLS_MAX_P + 1);
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q <= NYLS_MAX_P; ++q) v += w[q] * kd[q];
+        P[pt * m + s] = v;
+      });
       __syncthreads();
       {
         const int pt = tid / TPG, sub = tid % TPG;
@@ -249,28 +260,31 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_backward(
   double sum_nu_e = 0.0, t2 = 0.0, aeacc = 0.0, anacc = 0.0;
   for (int i0 = 0; i0 < n; i0 += TP) {
     __syncthreads();
-    for (int e = tid; e < TP * m; e += NYLS_BLOCK) {
-      const int pt = e / m, s = e - pt * m;
-      const int i = i0 + pt;
-      double pv = 0.0, dpv = 0.0;
-      double kd[NYLS_MAX_P + 1];
+    for (int e = tid; e < TP; e += NYLS_BLOCK) {
+      const int i = i0 + e;
+      double w[NYLS_MAX_P + 1];
+      nyls_opweights(p, [&](int k) { return i < n ? d.f[(size_t)(k - 1) * n + i] : 0.0; }, w);
 #pragma unroll
-      for (int q = 0; q <= NYLS_MAX_P; ++q) kd[q] = 0.0;
-      if (i < n) {
-        const double z = (nyls_grid_t(d, i) - tl[s]) * inv_sigma;
-        double ds[NYLS_MAX_P + 1], w[NYLS_MAX_P + 1];
-        nyls_kderiv(z, inv_sigma, kd);
-        kderiv_dsigma(z, inv_sigma, ds);
-        nyls_opweights(p, [&](int k) { return d.f[(size_t)(k - 1) * n + i]; }, w);
-        pv = nyls_dot5(w, kd);
-        dpv = nyls_dot5(w, ds);
+      for (int q = 0; q <= NYLS_MAX_P; ++q) wq[e * (NYLS_MAX_P + 1) + q] = w[q];
+    }
+    __syncthreads();
+    nyls_gauss_tile<TP, CH>(d, i0, tl, inv_sigma, [&](int pt, int s, double zz, double ev) {
+      double kd[NYLS_MAX_P + 1], ds[NYLS_MAX_P + 1];
+      nyls_kderiv_e(zz, ev, inv_sigma, kd);
+      kderiv_dsigma_e(zz, ev, inv_sigma, ds);
+      const double* w = wq + pt * (NYLS_MAX_P + 1);
+      double pv = 0.0, dpv = 0.0;
+#pragma unroll
+      for (int q = 0; q <= NYLS_MAX_P; ++q) {
+        pv += w[q] * kd[q];
+        dpv += w[q] * ds[q];
       }
       P[pt * m + s] = pv;
       DP[pt * m + s] = dpv;
 #pragma unroll
       for (int q = 0; q < NYLS_MAX_P; ++q)
         if (q < p) KQ[(q * TP + pt) * m + s] = kd[q];
-    }
+    });
     __syncthreads();
     {
       const int pt = tid / TPG, sub = tid % TPG;
@@ -423,7 +437,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_backward(
 
 size_t backward_lds_bytes(int maxm, int maxp) {
   const size_t common = (6 * NYLS_MAX_M + NYLS_MAX_P * NYLS_MAX_M + 3 * 136 + 2 * NYLS_MAX_M +
-                         2 * NYLS_BLOCK + 16 + TP * 8) * sizeof(double) + 136 * sizeof(int);
+                         2 * NYLS_BLOCK + 16 + TP * 8 + TP * (NYLS_MAX_P + 1)) * sizeof(double) +
+                        136 * sizeof(int);
   const size_t tiles = (size_t)(2 + maxp) * TP * maxm * sizeof(double);
   return common + tiles;
 }

@@ -369,6 +369,7 @@ const char* nyls_error_string(int32_t code) {
     case NYLS_S_NONFINITE: return "non-finite value in the solution";
     case NYLS_S_EIG_NOCONV: return "eigensolver hit its sweep limit";
     case NYLS_S_SMALL_PIVOT: return "Newton diagonal block entry below 1e-10 gamma";
+    case NYLS_S_REFINE_NOCONV: return "iterative refinement did not reach rounding level";
     default: return "unknown code";
   }
 }

@@ -59,18 +59,17 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig(const nyls_desc* __restrict_
   }
   __syncthreads();
 
+  // Cyclic sweeps until a whole sweep finds no off-diagonal entry above 1e-17 ||diag||_2
+  // (the backward-error level of a dense FP64 eigensolver).
+  int* rotflag = pos;  // reused below for the sort
   int sweep = 0;
   bool converged = false;
   for (; sweep < kMaxSweeps; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int e = tid; e < m * m; e += NYLS_BLOCK) {
-      const int a = e / m, b = e - a * m;
-      const double v = A[a * ld + b];
-      if (a == b) dia += v * v; else off += v * v;
-    }
-    off = nyls_block_sum(off, red);
-    dia = nyls_block_sum(dia, red);
-    if (!(off > 1e-32 * dia)) { converged = true; break; }
+    double dia = 0.0;
+    for (int k = tid; k < m; k += NYLS_BLOCK) dia += A[k * ld + k] * A[k * ld + k];
+    const double thresh = 1e-17 * sqrt(nyls_block_sum(dia, red));
+    if (tid == 0) rotflag[0] = 0;
+    __syncthreads();
 
     for (int rd = 0; rd < m2 - 1; ++rd) {
       if (tid < npair) {
@@ -81,11 +80,12 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig(const nyls_desc* __restrict_
         double c = 1.0, s = 0.0, t = 0.0;
         if (q < m) {
           const double apq = A[p * ld + q];
-          if (apq != 0.0) {
+          if (fabs(apq) > thresh) {
             const double theta = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
             t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
             s = t * c;
+            rotflag[0] = 1;
           }
         }
         pidx[tid] = p; qidx[tid] = q; cs[tid] = c; sn[tid] = s; tn[tid] = t;
@@ -131,6 +131,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig(const nyls_desc* __restrict_
       }
       __syncthreads();
     }
+    if (rotflag[0] == 0) { converged = true; break; }
+    __syncthreads();
   }
 
   // Sort eigenvalues descending (ties by index) and pick each eigenvector's sign.

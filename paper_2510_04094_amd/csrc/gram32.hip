@@ -16,8 +16,8 @@
 //   * the result registers feed the Gram MFMAs directly as both operands (register v of
 //     lane l holds point 4(l/16)+v, column l%16 + 16 X, which is exactly the operand
 //     layout of k-step v), accumulating only the NT(NT+1)/2 upper-triangle tiles;
-//   * FP32 accumulators are flushed into per-lane FP64 accumulators in LDS every CHUNK
-//     steps, so long sums keep FP64 range and precision.
+//   * FP32 accumulators are flushed into per-lane FP64 accumulators every CHUNK steps
+//     (registers for up to 4 tile rows, LDS beyond), so long sums keep FP64 precision.
 // Instances whose tile count differs from the template's NT leave immediately; the
 // launcher issues one launch per tile count present in the batch.
 #include "nyls_internal.h"
@@ -30,9 +30,10 @@ constexpr int CHUNK = 4;  // 16-point steps between FP64 flushes
 
 template <int NT>
 __global__ __launch_bounds__(64) void k_gram32_rot(const nyls_desc* __restrict__ desc,
-                                                   double* __restrict__ wsbase) {
+                                                   double* __restrict__ wsbase, int maxmk) {
   constexpr int T = NT * (NT + 1) / 2;
   constexpr int RN = 16 * NT;
+  constexpr bool REG = T <= 15;  // FP64 accumulators in registers when they fit
   extern __shared__ double sm[];
   const nyls_desc& d = desc[blockIdx.x];
   const int m = d.m, p = d.p, n = d.n, g = m + 2;
@@ -42,11 +43,16 @@ __global__ __launch_bounds__(64) void k_gram32_rot(const nyls_desc* __restrict__
   double* ws = wsbase + d.ws;
   const int lane = threadIdx.x;
   const int col = lane & 15, quad = lane >> 4;
-  double* acc64 = sm;                                           // [T][4][64]
-  float* U32 = reinterpret_cast<float*>(acc64 + T * 256);       // [mk][RN]
-  double* tlv = reinterpret_cast<double*>(U32 + NYLS_MAX_M * RN);  // [mk] landmark times
-
-  for (int e = lane; e < T * 256; e += 64) acc64[e] = 0.0;
+  double* tlv = sm;                                              // [maxmk] landmark times
+  float* U32 = reinterpret_cast<float*>(tlv + maxmk);            // [maxmk][RN]
+  double* acc64 = reinterpret_cast<double*>(U32 + maxmk * RN);   // [T][4][64] unless REG
+  double accr[REG ? T : 1][4];
+#pragma unroll
+  for (int t = 0; t < (REG ? T : 1); ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) accr[t][v] = 0.0;
+  if (!REG)
+    for (int e = lane; e < T * 256; e += 64) acc64[e] = 0.0;
   const double* U = ws + L.U;
   for (int e = lane; e < mk * RN; e += 64) {
     const int s = e / RN, k = e - s * RN;
@@ -131,7 +137,10 @@ __global__ __launch_bounds__(64) void k_gram32_rot(const nyls_desc* __restrict__
 #pragma unroll
       for (int tt = 0; tt < T; ++tt) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc64[(tt * 4 + v) * 64 + lane] += (double)accS[tt][v];
+        for (int v = 0; v < 4; ++v) {
+          if (REG) accr[REG ? tt : 0][v] += (double)accS[tt][v];
+          else acc64[(tt * 4 + v) * 64 + lane] += (double)accS[tt][v];
+        }
         accS[tt] = floatx4{0.f, 0.f, 0.f, 0.f};
       }
     }
@@ -146,7 +155,7 @@ __global__ __launch_bounds__(64) void k_gram32_rot(const nyls_desc* __restrict__
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int a = 16 * I + 4 * quad + v, b = 16 * J + col;
-        const double val = acc64[(t * 4 + v) * 64 + lane];
+        const double val = REG ? accr[REG ? t : 0][v] : acc64[(t * 4 + v) * 64 + lane];
         if (a < g && b < g) {
           out[a * g + b] = val;
           if (I != J) out[b * g + a] = val;
@@ -159,11 +168,12 @@ __global__ __launch_bounds__(64) void k_gram32_rot(const nyls_desc* __restrict__
 template <int NT>
 hipError_t launch_nt(const nyls_plan_view& pv, double* ws, hipStream_t st) {
   constexpr int T = NT * (NT + 1) / 2;
-  const size_t lds = (size_t)T * 256 * sizeof(double) + (size_t)NYLS_MAX_M * 16 * NT * sizeof(float) +
-                     NYLS_MAX_M * sizeof(double);
+  const int maxmk = (pv.maxm + 3) & ~3;
+  const size_t lds = (T <= 15 ? 0 : (size_t)T * 256 * sizeof(double)) +
+                     (size_t)maxmk * 16 * NT * sizeof(float) + (size_t)maxmk * sizeof(double);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram32_rot<NT>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_gram32_rot<NT>, dim3(pv.batch), dim3(64), lds, st, pv.d_desc, ws);
+  hipLaunchKernelGGL(k_gram32_rot<NT>, dim3(pv.batch), dim3(64), lds, st, pv.d_desc, ws, maxmk);
   return hipGetLastError();
 }
 

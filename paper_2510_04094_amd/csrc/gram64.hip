@@ -14,6 +14,7 @@
 namespace {
 
 constexpr int TP = 64;      // points per tile
+constexpr int CH = 16;      // points per thread in the Gaussian recurrence
 constexpr int MAXB = 3;     // 4x4 blocks per thread (m <= 128 -> at most 561 blocks)
 
 __device__ inline int instance_of(const int32_t* order) {
@@ -29,7 +30,7 @@ __device__ inline void block_coords(int blk, int nb, int& bi, int& bj) {
 
 __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restrict__ desc,
                                                        const int32_t* __restrict__ order,
-                                                       double* __restrict__ wsbase) {
+                                                       double* __restrict__ wsbase, int maxm) {
   extern __shared__ double sm[];
   const nyls_desc& d = desc[instance_of(order)];
   const int m = d.m, p = d.p, n = d.n;
@@ -42,10 +43,25 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
   double* ws = wsbase + d.ws;
   const int tid = threadIdx.x;
 
+  const int gpmax = (maxm + 2 + 3) & ~3;
   double* Q = sm;                          // [TP][gp] tile rows (also the reduction buffer)
-  double* fr = Q + (size_t)TP * gp;         // [TP][p+1] f_1..f_p, r of the tile's points
+  double* fr = Q + (size_t)TP * gp;         // [TP][NYLS_MAX_P+1] operator weights per point
   double* tl = fr + TP * (NYLS_MAX_P + 1);  // [m] landmark times
   int* okp = reinterpret_cast<int*>(tl + NYLS_MAX_M);  // [TP] residual-point flag
+  double* Q2 = reinterpret_cast<double*>(okp + TP) + (size_t)TP * (gpmax - gp);  // [TP][gp]
+  double* Ub = Q2 + (size_t)TP * gp;        // [m][m] eigenvectors (only when maxm <= 64)
+
+  // Ill-conditioned K_mm (retained eigenvalues below 1e-9 lambda_1): the kernel-space Gram
+  // would lose most digits in W^T S W, so the rows are rotated by U^T first and the Gram is
+  // accumulated in the eigenbasis (the KKT kernel then scales by Lambda^{-1/2}).
+  const int rank = (int)ws[L.info + 0];
+  const bool rotate = rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam];
+  const double* Ug = ws + L.U;
+  const bool ulds = maxm <= 64;
+  if (rotate && ulds)
+    for (int e = tid; e < m * m; e += NYLS_BLOCK) Ub[e] = Ug[e];
+  const double* Uu = ulds ? Ub : Ug;
+  double* Qa = rotate ? Q2 : Q;             // rows the Gram accumulates
 
   const double inv_sigma = 1.0 / d.sigma;
   for (int s = tid; s < m; s += NYLS_BLOCK) tl[s] = nyls_grid_t(d, d.lidx[s]);
@@ -73,38 +89,46 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
 
   for (int i0 = 0; i0 < n; i0 += TP) {
     __syncthreads();
+    // per-point operator weights w_q (L = d^p - sum f_k d^(p-k)), c_i, r_i, padding
     for (int e = tid; e < TP; e += NYLS_BLOCK) {
       const int i = i0 + e;
       const bool ok = i < n && !nyls_is_condition_point(d, i);
       okp[e] = ok;
-      for (int k = 0; k < p; ++k) fr[e * (NYLS_MAX_P + 1) + k] = ok ? d.f[(size_t)k * n + i] : 0.0;
-      fr[e * (NYLS_MAX_P + 1) + p] = ok ? d.r[i] : 0.0;
+      double w[NYLS_MAX_P + 1];
+      nyls_opweights(p, [&](int k) { return ok ? d.f[(size_t)(k - 1) * n + i] : 0.0; }, w);
+#pragma unroll
+      for (int q = 0; q <= NYLS_MAX_P; ++q) fr[e * (NYLS_MAX_P + 1) + q] = w[q];
+      Q[e * gp + m] = ok ? -d.f[(size_t)(p - 1) * n + i] : 0.0;
+      Q[e * gp + m + 1] = ok ? d.r[i] : 0.0;
+      for (int c = m + 2; c < gp; ++c) Q[e * gp + c] = 0.0;
     }
     __syncthreads();
-    for (int e = tid; e < TP * gp; e += NYLS_BLOCK) {
-      const int pt = e / gp, s = e - pt * gp;
-      const int i = i0 + pt;
-      double val = 0.0;
-      if (okp[pt]) {
-        const double* fp = fr + pt * (NYLS_MAX_P + 1);
-        if (s < m) {
-          const double z = (nyls_grid_t(d, i) - tl[s]) * inv_sigma;
-          double kd[NYLS_MAX_P + 1], w[NYLS_MAX_P + 1];
-          nyls_kderiv(z, inv_sigma, kd);
-          nyls_opweights(p, [&](int k) { return fp[k - 1]; }, w);
-          val = nyls_dot5(w, kd);
-        } else if (s == m) {
-          val = -fp[p - 1];
-        } else if (s == m + 1) {
-          val = fp[p];
+    nyls_gauss_tile<TP, CH>(d, i0, tl, inv_sigma, [&](int pt, int s, double z, double ev) {
+      double kd[NYLS_MAX_P + 1];
+      nyls_kderiv_e(z, ev, inv_sigma, kd);
+      const double* w = fr + pt * (NYLS_MAX_P + 1);
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q <= NYLS_MAX_P; ++q) v += w[q] * kd[q];
+      Q[pt * gp + s] = v;
+    });
+    __syncthreads();
+    if (rotate) {
+      for (int e = tid; e < TP * gp; e += NYLS_BLOCK) {
+        const int pt = e / gp, k = e - pt * gp;
+        double v = Q[pt * gp + k];
+        if (k < m) {
+          v = 0.0;
+          const double* q = Q + pt * gp;
+          for (int s2 = 0; s2 < m; ++s2) v += q[s2] * Uu[s2 * m + k];
         }
+        Q2[e] = v;
       }
-      Q[e] = val;
+      __syncthreads();
     }
-    __syncthreads();
     for (int pt = grp; pt < TP; pt += ngrp) {
       if (!okp[pt]) continue;
-      const double* row = Q + pt * gp;
+      const double* row = Qa + pt * gp;
 #pragma unroll
       for (int k = 0; k < MAXB; ++k) {
         if (k >= nmine) break;
@@ -144,6 +168,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
     const int blk = ia * nb - ia * (ia - 1) / 2 + (ib - ia);
     out[e] = Q[blk * 16 + (a & 3) * 4 + (b & 3)];
   }
+  if (tid == 0) ws[L.info + 4] = rotate ? 1.0 : 0.0;
 }
 
 }  // namespace
@@ -152,14 +177,20 @@ size_t nyls_gram64_lds_bytes(int maxm) {
   const int gp = (maxm + 2 + 3) & ~3;
   const int nb = gp >> 2;
   const size_t tile = (size_t)TP * gp, red = (size_t)nb * (nb + 1) / 2 * 16;
-  return (tile > red ? tile : red) * sizeof(double) + TP * (NYLS_MAX_P + 1) * sizeof(double) +
-         NYLS_MAX_M * sizeof(double) + TP * sizeof(int);
+  // the rotated-row tile Q2 sits after the point flags at an offset that is independent of
+  // the instance's own tile width; the reduction buffer may run into fr / tl / okp only
+  const size_t base = tile * sizeof(double) + TP * (NYLS_MAX_P + 1) * sizeof(double) +
+                      NYLS_MAX_M * sizeof(double) + TP * sizeof(int);
+  size_t total = base + tile * sizeof(double) + (maxm <= 64 ? (size_t)maxm * maxm * sizeof(double) : 0);
+  if (red * sizeof(double) > total) total = red * sizeof(double);
+  return total;
 }
 
 hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t st) {
   const size_t lds = nyls_gram64_lds_bytes(pv.maxm);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_gram64, dim3(pv.batch), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws);
+  hipLaunchKernelGGL(k_gram64, dim3(pv.batch), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws,
+                     pv.maxm);
   return hipGetLastError();
 }

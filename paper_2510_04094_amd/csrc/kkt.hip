@@ -48,6 +48,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
   // T = S W over the landmark block (kernel-space Gram only); with the eigenbasis Gram
   // (rows rotated by U^T) the transform is the diagonal Lambda^{-1/2}.
   const double* lamv = ws + L.lam;
+  if (!eigbasis) eigbasis = ws[L.info + 4] != 0.0 ? 1 : 0;  // per-instance choice of the FP64 Gram
   if (!eigbasis)
     for (int e = tid; e < m * m; e += NYLS_BLOCK) {
       const int a = e / m, k = e - a * m;

@@ -26,6 +26,7 @@ nyls_plan_view nyls_plan_get_view(const nyls_plan* pl);
 namespace {
 
 constexpr int TP = 32;
+constexpr int CH = 8;  // points per thread in the Gaussian recurrence
 
 __host__ __device__ inline int round4(int x) { return (x + 3) & ~3; }
 
@@ -47,30 +48,30 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_init(const nyls_desc* __r
   const double inv_sigma = 1.0 / d.sigma;
   double* tl = sm;                          // [128]
   double* kc = tl + NYLS_MAX_M;             // [128]
-  double* Q = kc + NYLS_MAX_M;              // [2*TP][gp], later the reduction buffer
+  double* okf = kc + NYLS_MAX_M;            // [TP]
+  double* Q = okf + TP;                     // [2*TP][gp], later the reduction buffer
   for (int s = tid; s < m; s += NYLS_BLOCK) tl[s] = nyls_grid_t(d, d.lidx[s]);
   __syncthreads();
   nyls_gram::Acc A;
   nyls_gram::setup(A, gp);
   for (int i0 = 0; i0 < n; i0 += TP) {
     __syncthreads();
-    for (int e = tid; e < TP * gp; e += NYLS_BLOCK) {
-      const int pt = e / gp, s = e - pt * gp;
-      const int i = i0 + pt;
-      double v0 = 0.0, v1 = 0.0;  // rows (k_i, 1) and (k'_i, 0)
-      if (i < n && !nyls_is_condition_point(d, i)) {
-        if (s < m) {
-          const double z = (nyls_grid_t(d, i) - tl[s]) * inv_sigma;
-          const double e0 = exp(-z * z);
-          v0 = e0;
-          v1 = -2.0 * z * inv_sigma * e0;
-        } else if (s == m) {
-          v0 = 1.0;
-        }
+    // rows (k_i, 1) and (k'_i, 0); zero rows at condition points and past the grid
+    for (int e = tid; e < TP; e += NYLS_BLOCK) {
+      const int i = i0 + e;
+      const bool ok = i < n && !nyls_is_condition_point(d, i);
+      okf[e] = ok ? 1.0 : 0.0;
+      for (int c = m; c < gp; ++c) {
+        Q[(2 * e) * gp + c] = (c == m && ok) ? 1.0 : 0.0;
+        Q[(2 * e + 1) * gp + c] = 0.0;
       }
-      Q[(2 * pt) * gp + s] = v0;
-      Q[(2 * pt + 1) * gp + s] = v1;
     }
+    __syncthreads();
+    nyls_gauss_tile<TP, CH>(d, i0, tl, inv_sigma, [&](int pt, int s, double z, double ev) {
+      const double e0 = okf[pt] * ev;
+      Q[(2 * pt) * gp + s] = e0;
+      Q[(2 * pt + 1) * gp + s] = -2.0 * z * inv_sigma * e0;
+    });
     __syncthreads();
     nyls_gram::accumulate(A, Q, gp, nullptr, 2 * TP);
   }
@@ -152,18 +153,10 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_step(
   int bad = 0;
   for (int i0 = 0; i0 < n; i0 += TP) {
     __syncthreads();
-    for (int e = tid; e < TP * m; e += NYLS_BLOCK) {
-      const int pt = e / m, s = e - pt * m;
-      const int i = i0 + pt;
-      double e0 = 0.0, e1 = 0.0;
-      if (i < n) {
-        const double z = (nyls_grid_t(d, i) - tl[s]) * inv_sigma;
-        e0 = exp(-z * z);
-        e1 = -2.0 * z * inv_sigma * e0;
-      }
-      K0[pt * m + s] = e0;
-      K1[pt * m + s] = e1;
-    }
+    nyls_gauss_tile<TP, CH>(d, i0, tl, inv_sigma, [&](int pt, int s, double z, double ev) {
+      K0[pt * m + s] = ev;
+      K1[pt * m + s] = -2.0 * z * inv_sigma * ev;
+    });
     __syncthreads();
     {
       constexpr int TPG = NYLS_BLOCK / TP;
@@ -370,7 +363,7 @@ size_t init_lds_bytes(int maxm) {
   size_t q = 2 * (size_t)TP * gp;
   const size_t redd = nyls_gram::red_doubles(gp);
   if (redd > q) q = redd;
-  return (2 * NYLS_MAX_M + q) * sizeof(double);
+  return (2 * NYLS_MAX_M + TP + q) * sizeof(double);
 }
 
 __global__ __launch_bounds__(NYLS_BLOCK) void k_riccati_eval(

@@ -74,3 +74,46 @@ __device__ inline void nyls_lu_solve(const double* A, int lda, int N, const int*
     __syncthreads();
   }
 }
+
+// ---- single-wavefront variants (blockDim.x == 64): no barriers needed beyond LDS order ----
+
+// Broadcast lane l's value (l uniform across the wave).
+__device__ inline double nyls_rdlane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double nyls_wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ inline double nyls_wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Solve A x = b with LU factors (row stride lda, any address space); b in LDS.
+__device__ inline void nyls_lu_solve_w(const double* A, int lda, int N, const int* piv, double* b) {
+  const int lane = threadIdx.x;
+  if (lane == 0)
+    for (int k = 0; k < N; ++k) {
+      const int pr = piv[k];
+      if (pr != k) { const double t = b[k]; b[k] = b[pr]; b[pr] = t; }
+    }
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    const double bk = b[k];
+    for (int i = k + 1 + lane; i < N; i += 64) b[i] -= A[i * lda + k] * bk;
+    __syncthreads();
+  }
+  for (int k = N - 1; k >= 0; --k) {
+    if (lane == 0) b[k] /= A[k * lda + k];
+    __syncthreads();
+    const double xk = b[k];
+    for (int i = lane; i < k; i += 64) b[i] -= A[i * lda + k] * xk;
+    __syncthreads();
+  }
+}

@@ -34,7 +34,8 @@ __host__ __device__ inline nyls_wsl nyls_layout(int m, int p, int n_newton) {
   const int64_t g = m + 2, nk = m + 1 + p;
   L.W = 0;                       // m*m   W[s*m + k] = U[s][k] / sqrt(lam_k), k < r
   L.lam = L.W + (int64_t)m * m;  // m     eigenvalues, descending
-  L.info = L.lam + m;            // 8     [0] rank r, [1] status bits, [2] sweeps
+  L.info = L.lam + m;            // 8     [0] rank r, [1] status bits, [2] sweeps,
+                                 //       [3] last refinement correction, [4] Gram basis
   L.gram = L.info + 8;           // g*g   kernel-space Gram of (p_i, c_i, r_i)
   L.lu = L.gram + g * g;         // nk*nk LU factors of the KKT system (row-major)
   L.piv = L.lu + nk * nk;        // nk    pivot rows
@@ -107,6 +108,87 @@ __device__ inline T nyls_dot5(const T (&a)[NYLS_MAX_P + 1], const T (&b)[NYLS_MA
   return v;
 }
 
+// Start of a run of `len` consecutive uniform-grid points k0 .. k0+len-1 (offsets from a
+// landmark, a = dt / sigma) for the recurrence e(k+1) = e(k) rv(k), rv(k+1) = rv(k) q2,
+// q2 = exp(-2 a^2).  Returns true when the run must use exact exponentials instead: the
+// ratio would overflow, or the run starts below exp(-700) (denormal or zero, so the
+// relative precision is gone) while approaching the landmark and rising above that level
+// inside the run.  Runs that stay below exp(-700) keep the recurrence: their values are
+// negligible in absolute terms.
+__device__ inline bool nyls_gauss_start(int k0, int len, double a, double& ev, double& rv) {
+  const double z0 = (double)k0 * a;
+  const double rexp = -a * a * (2.0 * k0 + 1.0);
+  if (rexp > 700.0) return true;
+  if (k0 < 0 && z0 * z0 > 700.0) {
+    const double ze = (double)(k0 + len - 1) * a;
+    if (k0 + len - 1 >= 0 || ze * ze < 700.0) return true;
+  }
+  ev = exp(-z0 * z0);
+  rv = exp(rexp);
+  return false;
+}
+
+// Gaussian values over a tile of TP consecutive grid points i = i0 + pt and all landmarks:
+// calls emit(pt, s, z, e) with z = (t_i - t_s)/sigma and e = exp(-z^2) (e = 0 for i >= n).
+// Work is split as thread -> (landmark s, chunk of CH points).  On a uniform grid
+// t_i - t_s = (i - i_s) dt, so along a chunk, with a = dt/sigma and k = i - i_s,
+//     e(k+1) = e(k) R(k),  R(k) = exp(-a^2 (2k+1)),  R(k+1) = R(k) exp(-2 a^2):
+// two multiplies per value after two exponentials per chunk (relative error <= ~CH^2 eps).
+// Chunks that nyls_gauss_start rejects use one exponential per point instead.
+template <int TP, int CH, typename Emit>
+__device__ inline void nyls_gauss_tile(const nyls_desc& d, int i0, const double* tl,
+                                       double inv_sigma, Emit emit) {
+  constexpr int NC = TP / CH;
+  const int m = d.m, n = d.n;
+  const double a = d.dt * inv_sigma;
+  const double q2 = exp(-2.0 * a * a);
+  for (int e = threadIdx.x; e < m * NC; e += NYLS_BLOCK) {
+    const int s = e % m, c = e / m;
+    const int ib = i0 + c * CH;
+    if (d.uniform) {
+      const int k0 = ib - d.lidx[s];
+      double ev = 0.0, rv = 0.0;
+      if (!nyls_gauss_start(k0, CH, a, ev, rv)) {
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          emit(c * CH + j, s, (double)(k0 + j) * a, (ib + j < n) ? ev : 0.0);
+          ev *= rv;
+          rv *= q2;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          const double z = (double)(k0 + j) * a;
+          emit(c * CH + j, s, z, (ib + j < n) ? exp(-z * z) : 0.0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const int i = ib + j;
+        const double z = i < n ? (d.t[i] - tl[s]) * inv_sigma : 0.0;
+        emit(c * CH + j, s, z, i < n ? exp(-z * z) : 0.0);
+      }
+    }
+  }
+}
+
+// Derivative values from z and e = exp(-z^2): kd[q] = (-1/sigma)^q H_q(z) e, q = 0..NYLS_MAX_P.
+__device__ inline void nyls_kderiv_e(double z, double e, double inv_sigma,
+                                     double (&kd)[NYLS_MAX_P + 1]) {
+  double hm = 1.0, h = 2.0 * z, sc = -inv_sigma;
+  kd[0] = e;
+  kd[1] = sc * h * e;
+#pragma unroll
+  for (int q = 1; q < NYLS_MAX_P; ++q) {
+    const double hn = 2.0 * z * h - 2.0 * q * hm;
+    hm = h;
+    h = hn;
+    sc *= -inv_sigma;
+    kd[q + 1] = sc * h * e;
+  }
+}
+
 // Block-wide helpers (blockDim.x == NYLS_BLOCK).
 __device__ inline double nyls_block_sum(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -154,3 +236,38 @@ hipError_t nyls_launch_explicit_rows(const nyls_plan_view& pv, int inst, const d
                                      hipStream_t st);
 hipError_t nyls_launch_explicit_kkt(const nyls_plan_view& pv, int inst, double* ws,
                                     const double* phi, const double* C, hipStream_t st);
+
+// Single-wavefront form of the Gaussian recurrence: the calling lane owns landmark grid
+// index `ls` and walks CP consecutive points i0..i0+CP-1, calling emit(jj, z, e) with
+// z = (t_i - t_s)/sigma and e = exp(-z^2) (0 past the grid).  Same recurrence and guards
+// as nyls_gauss_tile (two exponentials per chunk on a uniform grid).
+template <int CP, typename Emit>
+__device__ inline void nyls_wave_gauss(const nyls_desc& d, int i0, int ls, double tls, double a,
+                                       double q2, double inv_sigma, Emit emit) {
+  const int n = d.n;
+  if (d.uniform) {
+    const int k0 = i0 - ls;
+    double ev = 0.0, rv = 0.0;
+    if (!nyls_gauss_start(k0, CP, a, ev, rv)) {
+#pragma unroll
+      for (int j = 0; j < CP; ++j) {
+        emit(j, (double)(k0 + j) * a, (i0 + j < n) ? ev : 0.0);
+        ev *= rv;
+        rv *= q2;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < CP; ++j) {
+        const double z = (double)(k0 + j) * a;
+        emit(j, z, (i0 + j < n) ? exp(-z * z) : 0.0);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < CP; ++j) {
+      const int i = i0 + j;
+      const double z = i < n ? (d.t[i] - tls) * inv_sigma : 0.0;
+      emit(j, z, i < n ? exp(-z * z) : 0.0);
+    }
+  }
+}

@@ -16,7 +16,7 @@ MAX_P = 4
 MAX_M = 128
 
 FP64, MIXED, FP64_EXPLICIT = 0, 1, 2
-S_TRUNCATED, S_SINGULAR, S_NONFINITE, S_EIG_NOCONV, S_SMALL_PIVOT = 1, 2, 4, 8, 16
+S_TRUNCATED, S_SINGULAR, S_NONFINITE, S_EIG_NOCONV, S_SMALL_PIVOT, S_REFINE_NOCONV = 1, 2, 4, 8, 16, 32
 
 _lib = None
 
