@@ -37,6 +37,7 @@ extern "C" {
 
 #define NYLS_MAX_P 4   /* highest ODE order */
 #define NYLS_MAX_M 128 /* most landmarks per instance */
+#define NYLS_MAX_N (1 << 25) /* most grid points per instance */
 
 /* Arithmetic of the solve (nyls_plan_create `mode`). */
 enum {
@@ -56,7 +57,7 @@ enum {
   NYLS_E_BATCH = -2,      /* batch < 1 */
   NYLS_E_MODE = -3,       /* unknown mode, or the call does not support the plan's mode */
   NYLS_E_ORDER = -4,      /* p outside 1..NYLS_MAX_P */
-  NYLS_E_SIZE = -5,       /* n < 2, m < 2, m > n or m > NYLS_MAX_M (126 in mixed mode) */
+  NYLS_E_SIZE = -5,       /* n < 2, n > NYLS_MAX_N, m < 2, m > n or m > NYLS_MAX_M (126 in mixed mode) */
   NYLS_E_PARAM = -6,      /* sigma <= 0, gamma <= 0, tau outside [0, 1), or non-finite */
   NYLS_E_GRID = -7,       /* uniform grid with dt <= 0, or explicit grid missing */
   NYLS_E_LANDMARK = -8,   /* landmark indices not strictly ascending inside [0, n) */

@@ -18,6 +18,7 @@ struct nyls_plan {
   bool linear_ok = true;    // every instance has f and r
   bool all_first_order = true;
   unsigned nt_mask = 0;
+  unsigned p_mask = 0;
   nyls_desc* d_desc = nullptr;
   int32_t* d_lidx = nullptr;
   int32_t* d_order = nullptr;
@@ -31,7 +32,7 @@ bool finite(double x) { return std::isfinite(x); }
 
 int validate(const nyls_problem& q, std::vector<int32_t>& lidx) {
   if (q.p < 1 || q.p > NYLS_MAX_P) return NYLS_E_ORDER;
-  if (q.n < 2 || q.m < 2 || q.m > q.n || q.m > NYLS_MAX_M) return NYLS_E_SIZE;
+  if (q.n < 2 || q.n > NYLS_MAX_N || q.m < 2 || q.m > q.n || q.m > NYLS_MAX_M) return NYLS_E_SIZE;
   if (!(finite(q.sigma) && q.sigma > 0) || !(finite(q.gamma) && q.gamma > 0) ||
       !(finite(q.tau) && q.tau >= 0 && q.tau < 1))
     return NYLS_E_PARAM;
@@ -72,6 +73,7 @@ nyls_plan_view view(const nyls_plan* pl) {
   v.d_order = pl->d_order;
   v.total = pl->total;
   v.nt_mask = pl->nt_mask;
+  v.p_mask = pl->p_mask;
   return v;
 }
 
@@ -161,6 +163,7 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
     lidx_off[i] = (int64_t)all_lidx.size();
     all_lidx.insert(all_lidx.end(), lid.begin(), lid.end());
     pl->nt_mask |= 1u << ((q.m + 2 + 15) / 16);
+    pl->p_mask |= 1u << q.p;
     pl->maxm = std::max(pl->maxm, q.m);
     pl->maxp = std::max(pl->maxp, q.p);
     pl->maxn = std::max(pl->maxn, q.n);

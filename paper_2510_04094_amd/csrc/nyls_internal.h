@@ -35,7 +35,8 @@ __host__ __device__ inline nyls_wsl nyls_layout(int m, int p, int n_newton) {
   L.W = 0;                       // m*m   W[s*m + k] = U[s][k] / sqrt(lam_k), k < r
   L.lam = L.W + (int64_t)m * m;  // m     eigenvalues, descending
   L.info = L.lam + m;            // 8     [0] rank r, [1] status bits, [2] sweeps,
-                                 //       [3] last refinement correction, [4] Gram basis
+                                 //       [3] last refinement correction, [4] Gram basis,
+                                 //       [5] refinement passes over the grid
   L.gram = L.info + 8;           // g*g   kernel-space Gram of (p_i, c_i, r_i)
   L.lu = L.gram + g * g;         // nk*nk LU factors of the KKT system (row-major)
   L.piv = L.lu + nk * nk;        // nk    pivot rows
@@ -108,20 +109,32 @@ __device__ inline T nyls_dot5(const T (&a)[NYLS_MAX_P + 1], const T (&b)[NYLS_MA
   return v;
 }
 
-// Start of a run of `len` consecutive uniform-grid points k0 .. k0+len-1 (offsets from a
-// landmark, a = dt / sigma) for the recurrence e(k+1) = e(k) rv(k), rv(k+1) = rv(k) q2,
-// q2 = exp(-2 a^2).  Returns true when the run must use exact exponentials instead: the
+// Raw buffer resource over `bytes` bytes at p (gfx9 raw-buffer word 3): loads outside
+// [0, bytes) return 0 through the hardware range check, so tail chunks need no clamping.
+__device__ inline __amdgpu_buffer_rsrc_t nyls_rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+
+__device__ inline double nyls_bload(__amdgpu_buffer_rsrc_t r, int off_bytes) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off_bytes, 0, 0));
+}
+
+// Start of a run of `len` uniform-grid points k0, k0 + stride, ... (offsets from a landmark,
+// a = dt / sigma) for the recurrence e(k + stride) = e(k) rv(k), rv(k + stride) = rv(k) q,
+// q = exp(-2 a^2 stride^2).  Returns true when the run must use exact exponentials instead: the
 // ratio would overflow, or the run starts below exp(-700) (denormal or zero, so the
 // relative precision is gone) while approaching the landmark and rising above that level
 // inside the run.  Runs that stay below exp(-700) keep the recurrence: their values are
 // negligible in absolute terms.
-__device__ inline bool nyls_gauss_start(int k0, int len, double a, double& ev, double& rv) {
+__device__ inline bool nyls_gauss_start(int k0, int len, int stride, double a, double& ev,
+                                        double& rv) {
   const double z0 = (double)k0 * a;
-  const double rexp = -a * a * (2.0 * k0 + 1.0);
+  const double rexp = -a * a * (double)stride * (2.0 * k0 + stride);
   if (rexp > 700.0) return true;
+  const int ke = k0 + (len - 1) * stride;
   if (k0 < 0 && z0 * z0 > 700.0) {
-    const double ze = (double)(k0 + len - 1) * a;
-    if (k0 + len - 1 >= 0 || ze * ze < 700.0) return true;
+    const double ze = (double)ke * a;
+    if (ke >= 0 || ze * ze < 700.0) return true;
   }
   ev = exp(-z0 * z0);
   rv = exp(rexp);
@@ -148,7 +161,7 @@ __device__ inline void nyls_gauss_tile(const nyls_desc& d, int i0, const double*
     if (d.uniform) {
       const int k0 = ib - d.lidx[s];
       double ev = 0.0, rv = 0.0;
-      if (!nyls_gauss_start(k0, CH, a, ev, rv)) {
+      if (!nyls_gauss_start(k0, CH, 1, a, ev, rv)) {
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
           emit(c * CH + j, s, (double)(k0 + j) * a, (ib + j < n) ? ev : 0.0);
@@ -210,6 +223,7 @@ enum { NYLS_K_EIG = 0, NYLS_K_GRAM64, NYLS_K_GRAM32, NYLS_K_KKT, NYLS_K_POINTS, 
 // Host launchers (defined in the .hip files; all enqueue on `stream`).
 struct nyls_plan_view {
   int32_t batch, mode, maxm, maxp, maxn;
+  unsigned p_mask;          // bit p set when some instance has ODE order p
   const nyls_desc* d_desc;
   const int32_t* d_order;   // instance order, most expensive first
   int64_t total;
@@ -248,7 +262,7 @@ __device__ inline void nyls_wave_gauss(const nyls_desc& d, int i0, int ls, doubl
   if (d.uniform) {
     const int k0 = i0 - ls;
     double ev = 0.0, rv = 0.0;
-    if (!nyls_gauss_start(k0, CP, a, ev, rv)) {
+    if (!nyls_gauss_start(k0, CP, 1, a, ev, rv)) {
 #pragma unroll
       for (int j = 0; j < CP; ++j) {
         emit(j, (double)(k0 + j) * a, (i0 + j < n) ? ev : 0.0);

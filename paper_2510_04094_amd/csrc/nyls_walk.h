@@ -1,0 +1,158 @@
+// One-wavefront-per-instance passes over the collocation grid.
+//
+// Lane geometry: lane = 16 ph + sl.  A lane owns the landmarks s = 16 b + sl (b < NB) and,
+// inside a chunk of 16 consecutive grid points i0 .. i0 + 15, the four points
+// i0 + 4 j + ph (j < 4): it produces a 4 x NB block of (point, landmark) values per chunk.
+//  * Sums over the landmarks (dot products with alpha, beta) are first reduced in registers
+//    over the lane's NB landmarks, then over the 16 landmark slots through a small padded
+//    LDS tile (nyls_walk_reduce); afterwards lane l holds the totals of point l & 15.
+//  * Per-point scalars computed by those lanes go back to the lanes that own the point
+//    (nyls_walk_bcast), and sums over the points (sum_i rho_i p_i and the like) stay in
+//    registers until the pass ends, when two shuffles fold the four phases.
+// A single wavefront needs no workgroup-wide synchronisation, and the LDS footprint stays
+// at a few KiB, so many instances share a compute unit.
+//
+// Kernel values: on a uniform grid t_i - t_s = k dt with k = i - i_s.  Along one lane's
+// points k advances by 4, so with a = dt / sigma
+//     e(k + 4) = e(k) R(k),  R(k) = exp(-a^2 (8 k + 16)),  R(k + 4) = R(k) exp(-32 a^2),
+// restarted with two exponentials every 64 points (runs of 16 values per lane).
+#pragma once
+#include "nyls_internal.h"
+
+constexpr int NYLS_WALK_PAD = 18;  // LDS row stride (doubles) of the reduction tile
+
+// Hermite factors h_q = (-1/sigma)^q H_q(z), q = 0..P, so that the q-th t-derivative of
+// K(t, t_s) is h_q e.  With g = -2 z / sigma: h_0 = 1, h_1 = g,
+// h_{q+1} = g h_q - (2 q / sigma^2) h_{q-1}.
+template <int P>
+__device__ inline void nyls_hfac(double g, double inv_s2, double (&h)[P + 2]) {
+  h[0] = 1.0;
+  h[1] = g;
+#pragma unroll
+  for (int q = 1; q <= P; ++q) h[q + 1] = g * h[q] - (2.0 * q * inv_s2) * h[q - 1];
+}
+
+template <int NB>
+struct nyls_walk {
+  int sl, ph, n;
+  bool lv[NB];
+  int ls[NB];
+  double ev[NB], rv[NB], zc[NB];
+  bool exact;  // wave-uniform: this run of 64 points uses one exponential per value
+  double a4, q4, inv_sigma, a;
+  __amdgpu_buffer_rsrc_t tr;  // grid times (non-uniform grids)
+
+  __device__ void init(const nyls_desc& d, int lane) {
+    sl = lane & 15;
+    ph = lane >> 4;
+    n = d.n;
+    inv_sigma = 1.0 / d.sigma;
+    a = d.dt * inv_sigma;
+    a4 = 4.0 * a;
+    q4 = exp(-32.0 * a * a);
+    exact = !d.uniform;
+    tr = nyls_rsrc(d.uniform ? nullptr : d.t, d.uniform ? 0 : n * 8);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int s = 16 * b + sl;
+      lv[b] = s < d.m;
+      ls[b] = lv[b] ? d.lidx[s] : 0;
+      ev[b] = rv[b] = zc[b] = 0.0;
+    }
+  }
+
+  // Must be called before chunk(i0) for every chunk, in increasing order from i0 = 0:
+  // starts a new run of the recurrence every 64 points (and decides, wave-uniformly,
+  // whether that run needs one exponential per value instead).
+  __device__ void advance(const nyls_desc& d, int i0) {
+    if (d.uniform && (i0 & 63) == 0) {
+      bool any = false;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int k0 = i0 + ph - ls[b];
+        any |= nyls_gauss_start(k0, 16, 4, a, ev[b], rv[b]);
+        zc[b] = (double)k0 * a;
+      }
+      exact = __ballot(any) != 0;
+    }
+  }
+
+  // Calls emit(b, j, z, e) for every landmark slot b < NB and point j < 4 of the chunk at
+  // i0: z = (t_i - t_s) / sigma and e = exp(-z^2) for i = i0 + 4 j + ph.  Past the end of
+  // the grid the values are meaningless (but finite); callers ignore them.
+  template <class Emit>
+  __device__ void chunk(const nyls_desc& d, int i0, Emit emit) {
+    if (!exact) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          emit(b, j, zc[b], ev[b]);
+          ev[b] *= rv[b];
+          rv[b] *= q4;
+          zc[b] += a4;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = i0 + 4 * j + ph;
+        const double ti = d.uniform ? 0.0 : nyls_bload(tr, i * 8);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const double z = d.uniform ? (double)(i - ls[b]) * a
+                                     : (ti - nyls_grid_t(d, ls[b])) * inv_sigma;
+          emit(b, j, z, exp(-z * z));
+        }
+      }
+    }
+  }
+};
+
+// Totals over the 16 landmark slots of per-lane partials v[q][j] (quantity q, the lane's
+// point j).  On return every lane holds in out[q] the total of chunk point lane & 15.
+// tile: LDS, Q * 16 * NYLS_WALK_PAD doubles, 16-byte aligned.
+template <int Q>
+__device__ inline void nyls_walk_reduce(const double (&v)[Q][4], double* tile, int lane,
+                                        double (&out)[Q]) {
+  const int sl = lane & 15, ph = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tile[(q * 16 + 4 * j + ph) * NYLS_WALK_PAD + sl] = v[q][j];
+  __syncthreads();
+  const int pt = lane & 15, qq = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const double* row = tile + (q * 16 + pt) * NYLS_WALK_PAD + 4 * qq;
+    double s = (row[0] + row[1]) + (row[2] + row[3]);
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    out[q] = s;
+  }
+  __syncthreads();
+}
+
+// Per-point values w[q] held by lanes 0..15 (for chunk point lane) are returned in every lane
+// for its own points: out[q][j] = w[q] of point 4 j + ph.  buf: LDS, Q * 16 doubles.
+template <int Q>
+__device__ inline void nyls_walk_bcast(const double (&w)[Q], double* buf, int lane,
+                                       double (&out)[Q][4]) {
+  if (lane < 16)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) buf[q * 16 + (lane & 3) * 4 + (lane >> 2)] = w[q];
+  __syncthreads();
+  const int ph = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[q][j] = buf[q * 16 + ph * 4 + j];
+  __syncthreads();
+}
+
+// Sum of v over the four phases (lanes sl, sl + 16, sl + 32, sl + 48).
+__device__ inline double nyls_walk_fold(double v) {
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}

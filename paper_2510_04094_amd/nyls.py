@@ -14,6 +14,7 @@ import torch
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnyls.so")
 MAX_P = 4
 MAX_M = 128
+MAX_N = 1 << 25
 
 FP64, MIXED, FP64_EXPLICIT = 0, 1, 2
 S_TRUNCATED, S_SINGULAR, S_NONFINITE, S_EIG_NOCONV, S_SMALL_PIVOT, S_REFINE_NOCONV = 1, 2, 4, 8, 16, 32
