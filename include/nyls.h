@@ -75,7 +75,8 @@ enum {
   NYLS_S_NONFINITE = 4,       /* a NaN or Inf appeared in the solution */
   NYLS_S_EIG_NOCONV = 8,      /* the Jacobi eigensolver hit its sweep limit */
   NYLS_S_SMALL_PIVOT = 16,    /* Newton: a diagonal y-block entry |d_i| < 1e-10 gamma */
-  NYLS_S_REFINE_NOCONV = 32   /* refinement ended with a correction above 1e-12 max|y_hat| */
+  NYLS_S_REFINE_NOCONV = 32   /* refinement ended with its last change of y_hat above
+                                 1e-8 max|y_hat| */
 };
 
 /*
@@ -147,8 +148,11 @@ int nyls_assemble(const nyls_plan* plan, double* kkt, double* rhs, void* ws, hip
 
 /* Solve the Lemma 1 system and evaluate y_hat on the grid.
  *   refine_steps  most FP64 iterative-refinement steps after the solve, 0..8.  Each step
- *                 forms the exact residual matrix-free from one pass over the points and
- *                 stops early once its correction is at rounding level.  The fused modes
+ *                 forms the exact residual matrix-free from one pass over the points (and
+ *                 writes y_hat of the current solution).  The iteration stops once the
+ *                 change of y_hat (measured, or bounded by |d omega|_2 + |d b|) falls
+ *                 below 1e-11 max|y_hat|, or once a change is more than half the previous
+ *                 one (rounding floor reached).  The fused modes
  *                 factor an approximation of the system (a kernel-space FP64 Gram, or an
  *                 FP32 Gram), so >= 2 steps are recommended when K_mm is ill-conditioned;
  *                 NYLS_FP64_EXPLICIT assembles the exact system (0 steps suffice).

@@ -26,25 +26,51 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def command(out=LIB):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    return [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I" + INCLUDE, "-I" + CSRC, "-o", out] + srcs + ["-lrocblas"]
+FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build(verbose=False):
-    """Compile every source into libnyls.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = command(tmp)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libnyls.so")
-    if verbose:
-        sys.stderr.write(res.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+def command(out=LIB, csrc=CSRC):
+    """Single-invocation compile-and-link command (for reference and tools)."""
+    srcs = [os.path.join(csrc, s) for s in SOURCES]
+    return [hipcc()] + FLAGS + ["-shared", "-I" + INCLUDE, "-I" + csrc, "-o", out] + srcs + ["-lrocblas"]
+
+
+def build(verbose=False, out=LIB, csrc=CSRC, jobs=None):
+    """Compile every source (in parallel) and link libnyls.so; always recompiles."""
+    import concurrent.futures
+    import tempfile
+    cc = hipcc()
+    objdir = tempfile.mkdtemp(prefix="nyls_build_")
+    jobs = jobs or max(1, min(len(SOURCES), os.cpu_count() or 1, 16))
+
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        cmd = [cc] + FLAGS + ["-I" + INCLUDE, "-I" + csrc, "-c", os.path.join(csrc, src), "-o", obj]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        return src, obj, res
+
+    try:
+        with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+            results = list(ex.map(compile_one, SOURCES))
+        for src, _, res in results:
+            if res.returncode != 0:
+                sys.stderr.write(res.stdout + res.stderr)
+                raise RuntimeError("hipcc failed compiling " + src)
+            if verbose:
+                sys.stderr.write(res.stderr)
+        tmp = out + ".tmp"
+        link = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + [o for _, o, _ in results] + ["-lrocblas"]
+        res = subprocess.run(link, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking libnyls.so")
+        os.replace(tmp, out)
+    finally:
+        for name in os.listdir(objdir):
+            os.remove(os.path.join(objdir, name))
+        os.rmdir(objdir)
+    return out
 
 
 if __name__ == "__main__":

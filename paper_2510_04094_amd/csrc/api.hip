@@ -19,6 +19,7 @@ struct nyls_plan {
   bool all_first_order = true;
   unsigned nt_mask = 0;
   unsigned p_mask = 0;
+  unsigned rec_mask = 0;
   nyls_desc* d_desc = nullptr;
   int32_t* d_lidx = nullptr;
   int32_t* d_order = nullptr;
@@ -74,6 +75,7 @@ nyls_plan_view view(const nyls_plan* pl) {
   v.total = pl->total;
   v.nt_mask = pl->nt_mask;
   v.p_mask = pl->p_mask;
+  v.rec_mask = pl->rec_mask;
   return v;
 }
 
@@ -156,6 +158,11 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
       d.cond_i[j] = j < q.p ? q.cond_i[j] : -1;
     }
     d.sigma = q.sigma; d.gamma = q.gamma; d.tau = q.tau;
+    {
+      const double a = q.uniform ? q.dt / q.sigma : 0.0;
+      d.rec = (q.uniform && a <= 0.25) ? 1 : 0;
+      d.pad_ = 0;
+    }
     d.ws = wsd;
     d.goff = goff;
     wsd += nyls_layout(q.m, q.p, q.p == 1 ? q.n : 0).end;
@@ -164,6 +171,7 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
     all_lidx.insert(all_lidx.end(), lid.begin(), lid.end());
     pl->nt_mask |= 1u << ((q.m + 2 + 15) / 16);
     pl->p_mask |= 1u << q.p;
+    pl->rec_mask |= 1u << d.rec;
     pl->maxm = std::max(pl->maxm, q.m);
     pl->maxp = std::max(pl->maxp, q.p);
     pl->maxn = std::max(pl->maxn, q.n);

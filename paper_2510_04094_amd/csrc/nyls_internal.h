@@ -18,6 +18,9 @@ struct nyls_desc {
   const double* v;       // [p]
   int32_t cond_d[NYLS_MAX_P];
   int32_t cond_i[NYLS_MAX_P];
+  int32_t rec;           // 1: uniform grid with dt <= sigma / 4: the strided Gaussian
+                         // recurrence of the one-wave passes needs no exact exponentials
+  int32_t pad_;
   double sigma, gamma, tau;
   int64_t ws;            // first double of this instance's workspace block
   int64_t goff;          // first grid point of this instance in per-point outputs
@@ -224,6 +227,7 @@ enum { NYLS_K_EIG = 0, NYLS_K_GRAM64, NYLS_K_GRAM32, NYLS_K_KKT, NYLS_K_POINTS, 
 struct nyls_plan_view {
   int32_t batch, mode, maxm, maxp, maxn;
   unsigned p_mask;          // bit p set when some instance has ODE order p
+  unsigned rec_mask;        // bit 1: some instance has rec == 1, bit 0: some has rec == 0
   const nyls_desc* d_desc;
   const int32_t* d_order;   // instance order, most expensive first
   int64_t total;

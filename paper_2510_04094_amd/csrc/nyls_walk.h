@@ -32,7 +32,8 @@ __device__ inline void nyls_hfac(double g, double inv_s2, double (&h)[P + 2]) {
   for (int q = 1; q <= P; ++q) h[q + 1] = g * h[q] - (2.0 * q * inv_s2) * h[q - 1];
 }
 
-template <int NB>
+// EX = false: only for instances with nyls_desc::rec == 1 (no exact-exponential path).
+template <int NB, bool EX>
 struct nyls_walk {
   int sl, ph, n;
   bool lv[NB];
@@ -50,8 +51,8 @@ struct nyls_walk {
     a = d.dt * inv_sigma;
     a4 = 4.0 * a;
     q4 = exp(-32.0 * a * a);
-    exact = !d.uniform;
-    tr = nyls_rsrc(d.uniform ? nullptr : d.t, d.uniform ? 0 : n * 8);
+    exact = EX && !d.uniform;
+    tr = nyls_rsrc(EX && !d.uniform ? d.t : nullptr, EX && !d.uniform ? n * 8 : 0);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int s = 16 * b + sl;
@@ -65,24 +66,36 @@ struct nyls_walk {
   // starts a new run of the recurrence every 64 points (and decides, wave-uniformly,
   // whether that run needs one exponential per value instead).
   __device__ void advance(const nyls_desc& d, int i0) {
-    if (d.uniform && (i0 & 63) == 0) {
+    if ((!EX || d.uniform) && (i0 & 63) == 0) {
       bool any = false;
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int k0 = i0 + ph - ls[b];
-        any |= nyls_gauss_start(k0, 16, 4, a, ev[b], rv[b]);
+        if (EX) {
+          any |= nyls_gauss_start(k0, 16, 4, a, ev[b], rv[b]);
+        } else {
+          // rec == 1 (a <= 1/4): a run that starts below exp(-700) while approaching its
+          // landmark stays below exp(-132) (z falls by at most 60 a <= 15), so it is set to
+          // zero; every other run starts from normal numbers and its ratio cannot overflow.
+          const double z0 = (double)k0 * a;
+          const bool far = k0 < 0 && z0 * z0 > 700.0;
+          const double e0 = exp(-z0 * z0), r0 = exp(-a * a * 4.0 * (2.0 * k0 + 4.0));
+          ev[b] = far ? 0.0 : e0;
+          rv[b] = far ? 0.0 : r0;
+        }
         zc[b] = (double)k0 * a;
       }
-      exact = __ballot(any) != 0;
+      if (EX) exact = __ballot(any) != 0;
     }
   }
 
   // Calls emit(b, j, z, e) for every landmark slot b < NB and point j < 4 of the chunk at
-  // i0: z = (t_i - t_s) / sigma and e = exp(-z^2) for i = i0 + 4 j + ph.  Past the end of
-  // the grid the values are meaningless (but finite); callers ignore them.
-  template <class Emit>
-  __device__ void chunk(const nyls_desc& d, int i0, Emit emit) {
-    if (!exact) {
+  // i0: z = (t_i - t_s) / sigma and e = exp(-z^2) for i = i0 + 4 j + ph, then done(j) once
+  // all slots of point j were emitted.  Past the end of the grid the values are
+  // meaningless (but finite); callers ignore them.
+  template <class Emit, class Done>
+  __device__ void chunk(const nyls_desc& d, int i0, Emit emit, Done done) {
+    if (!EX || !exact) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
 #pragma unroll
@@ -92,6 +105,7 @@ struct nyls_walk {
           rv[b] *= q4;
           zc[b] += a4;
         }
+        done(j);
       }
     } else {
 #pragma unroll
@@ -104,22 +118,22 @@ struct nyls_walk {
                                      : (ti - nyls_grid_t(d, ls[b])) * inv_sigma;
           emit(b, j, z, exp(-z * z));
         }
+        done(j);
       }
     }
   }
 };
 
-// Totals over the 16 landmark slots of per-lane partials v[q][j] (quantity q, the lane's
-// point j).  On return every lane holds in out[q] the total of chunk point lane & 15.
-// tile: LDS, Q * 16 * NYLS_WALK_PAD doubles, 16-byte aligned.
+// Sums over the 16 landmark slots, in two steps: every lane stores its partial (over its NB
+// landmarks) of quantity q at its point j with nyls_walk_put; nyls_walk_sum then returns in
+// every lane the totals of chunk point lane & 15.  tile: LDS, Q * 16 * NYLS_WALK_PAD
+// doubles, 16-byte aligned.
+__device__ inline void nyls_walk_put(double* tile, int lane, int q, int j, double v) {
+  tile[(q * 16 + 4 * j + (lane >> 4)) * NYLS_WALK_PAD + (lane & 15)] = v;
+}
+
 template <int Q>
-__device__ inline void nyls_walk_reduce(const double (&v)[Q][4], double* tile, int lane,
-                                        double (&out)[Q]) {
-  const int sl = lane & 15, ph = lane >> 4;
-#pragma unroll
-  for (int q = 0; q < Q; ++q)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) tile[(q * 16 + 4 * j + ph) * NYLS_WALK_PAD + sl] = v[q][j];
+__device__ inline void nyls_walk_sum(const double* tile, int lane, double (&out)[Q]) {
   __syncthreads();
   const int pt = lane & 15, qq = lane >> 4;
 #pragma unroll

@@ -31,12 +31,12 @@ __device__ inline int instance_of(const int32_t* order, int single) {
   return single >= 0 ? single : (order ? order[blockIdx.x] : (int)blockIdx.x);
 }
 
-template <int NB, int P>
+template <int NB, int P, bool EX>
 __global__ __launch_bounds__(64) void k_points(
     const nyls_desc* __restrict__ desc, const int32_t* __restrict__ order,
     double* __restrict__ wsbase, int refine, double* __restrict__ yhat,
     double* __restrict__ omega_out, double* __restrict__ bias_out, double* __restrict__ lambda_out,
-    int32_t* __restrict__ status, int maxm, int single) {
+    int32_t* __restrict__ status, int maxm, int single, double tol_stop, double tol_flag) {
   __shared__ __align__(16) double tile[2 * 16 * NYLS_WALK_PAD];
   __shared__ double bc[16];
   __shared__ double Rv[NK], xv[NK], zs[NYLS_MAX_M];
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(64) void k_points(
 
   const int inst = instance_of(order, single);
   const nyls_desc& d = desc[inst];
-  if (d.p != P) return;  // another launch handles this order
+  if (d.p != P || d.rec != (EX ? 0 : 1)) return;  // another launch handles this instance
   const int m = d.m, n = d.n;
   const int N = m + 1 + P;
   const nyls_wsl L = nyls_layout(m, P, 0);
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(64) void k_points(
   const double gam = d.gamma;
   double* yo = yhat + d.goff;
 
-  nyls_walk<NB> wk;
+  nyls_walk<NB, EX> wk;
   wk.init(d, lane);
   const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
   const __amdgpu_buffer_rsrc_t fr = nyls_rsrc(d.f, P * n * 8), rr = nyls_rsrc(d.r, n * 8);
@@ -72,53 +72,64 @@ __global__ __launch_bounds__(64) void k_points(
   // One pass over the grid.  Always writes y_hat for the current (alpha, b); when refining
   // also forms rho_i = r_i - p_i^T alpha - c_i b and accumulates sum_i rho_i p_i (zacc, per
   // landmark slot and phase) and sum_i c_i rho_i (sacc, lanes 0..15).
-  auto pass = [&](auto REF, double b, double (&zacc)[NB], double& sacc, double& ymax) {
+  auto pass = [&](auto REF, double b, double (&zacc)[NB], double& sacc, double& ymax,
+                  bool track, double& dmax) {
     constexpr bool refining = decltype(REF)::value;
-    for (int i0 = 0; i0 < n; i0 += 16) {
-      wk.advance(d, i0);
-      double fj[P][4];
+    constexpr int Q = refining ? 2 : 1;
+    // operator data of this lane's points (and of the point it finishes), one chunk ahead
+    double fj[P][4], rp = 0.0, cp = 0.0;
+    auto load = [&](int i0, double (&f)[P][4], double& r_, double& c_) {
       if (refining) {
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) fj[k][j] = nyls_bload(fr, (k * n + i0 + 4 * j + wk.ph) * 8);
+          for (int j = 0; j < 4; ++j) f[k][j] = nyls_bload(fr, (k * n + i0 + 4 * j + wk.ph) * 8);
+        const int ip = i0 + (lane & 15);
+        r_ = nyls_bload(rr, ip * 8);
+        c_ = -nyls_bload(fr, ((P - 1) * n + ip) * 8);
       }
-      const int ip = i0 + (lane & 15);
-      double rp = 0.0, cp = 0.0;
-      if (refining) {
-        rp = nyls_bload(rr, ip * 8);
-        cp = -nyls_bload(fr, ((P - 1) * n + ip) * 8);
-      }
+    };
+    load(0, fj, rp, cp);
+    for (int i0 = 0; i0 < n; i0 += 16) {
+      wk.advance(d, i0);
+      double fn[P][4], rpn = 0.0, cpn = 0.0;
+      load(i0 + 16, fn, rpn, cpn);
       double pe[refining ? NB : 1][4];
-      double part[refining ? 2 : 1][4];
+      double acc0 = 0.0, acc1 = 0.0;
+      wk.chunk(
+          d, i0,
+          [&](int bb, int j, double z, double e) {
+            if (refining) {
+              double h[P + 2];
+              nyls_hfac<P>(-2.0 * inv_sigma * z, inv_s2, h);
+              double poly = h[P];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        part[0][j] = 0.0;
-        if (refining) part[refining ? 1 : 0][j] = 0.0;
-      }
-      wk.chunk(d, i0, [&](int bb, int j, double z, double e) {
-        if (refining) {
-          double h[P + 2];
-          nyls_hfac<P>(-2.0 * inv_sigma * z, inv_s2, h);
-          double poly = h[P];
-#pragma unroll
-          for (int k = 1; k <= P; ++k) poly -= fj[k - 1][j] * h[P - k];
-          const double pv = e * poly;
-          pe[refining ? bb : 0][j] = pv;
-          part[refining ? 1 : 0][j] += alv[bb] * pv;
-        }
-        part[0][j] += alv[bb] * e;
-      });
-      double tot[refining ? 2 : 1];
-      nyls_walk_reduce<refining ? 2 : 1>(part, tile, lane, tot);
+              for (int k = 1; k <= P; ++k) poly -= fj[k - 1][j] * h[P - k];
+              const double pv = e * poly;
+              pe[refining ? bb : 0][j] = pv;
+              acc1 += alv[bb] * pv;
+            }
+            acc0 += alv[bb] * e;
+          },
+          [&](int j) {
+            nyls_walk_put(tile, lane, 0, j, acc0);
+            if (refining) nyls_walk_put(tile, lane, 1, j, acc1);
+            acc0 = acc1 = 0.0;
+          });
+      double tot[Q];
+      nyls_walk_sum<Q>(tile, lane, tot);
+      const int ip = i0 + (lane & 15);
       const double yv = tot[0] + b;
       if (ip < n) {
-        if (lane < 16) yo[ip] = yv;
+        if (lane < 16) {
+          if (track) dmax = fmax(dmax, fabs(yv - yo[ip]));
+          yo[ip] = yv;
+        }
         ymax = fmax(ymax, fabs(yv));
       }
       if (refining) {
         const bool okp = ip < n && !nyls_is_condition_point(d, ip);
-        const double rho = okp ? rp - tot[refining ? 1 : 0] - cp * b : 0.0;
+        const double rho = okp ? rp - tot[Q - 1] - cp * b : 0.0;
         if (lane < 16) sacc += cp * rho;
         const double w1[1] = {rho};
         double rj[1][4];
@@ -128,26 +139,50 @@ __global__ __launch_bounds__(64) void k_points(
 #pragma unroll
           for (int j = 0; j < 4; ++j) zacc[bb] += rj[0][j] * pe[refining ? bb : 0][j];
       }
+#pragma unroll
+      for (int k = 0; k < P; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fj[k][j] = fn[k][j];
+      rp = rpn;
+      cp = cpn;
     }
   };
 
-  double corr = 0.0, ymax = 0.0;
+  // Each pass writes y_hat of the current solution and, from the second on, measures how
+  // far the previous correction moved it (dmax).  The iteration stops
+  //  * after a solve, when the bound |d y_hat| <= |d omega|_2 + |d b| (phi(t)^T phi(t) is
+  //    the Nystrom approximation of k(t, t) = 1 and never exceeds it) is below tol_stop:
+  //    the y_hat just written is final;
+  //  * before a solve, when the measured change is below tol_stop, or above half the
+  //    previous one (the FP64 residual has reached its rounding floor): y_hat and the
+  //    solution of this pass are kept.
+  // Otherwise the last correction is followed by an output pass (which also measures it).
+  double corr = 0.0, dprev = 0.0, ymax = 0.0;
   bool need_output = true;
   int passes = 0;
   for (int step = 0; step < refine; ++step) {
-    double zacc[NB], sacc = 0.0;
+    double zacc[NB], sacc = 0.0, dmax = 0.0;
     ymax = 0.0;
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb) zacc[bb] = 0.0;
-    pass(std::true_type{}, xv[m], zacc, sacc, ymax);
+    pass(std::true_type{}, xv[m], zacc, sacc, ymax, step > 0, dmax);
     ++passes;
+    ymax = nyls_wave_max(ymax);
+    if (step > 0) {
+      dmax = nyls_wave_max(dmax);
+      const bool stalled = step > 1 && dmax > 0.5 * dprev;
+      dprev = corr = dmax;
+      if (dmax <= tol_stop * ymax || stalled) {
+        need_output = false;
+        break;
+      }
+    }
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb) {
       const double zt = nyls_walk_fold(zacc[bb]);
       if (wk.ph == 0 && wk.lv[bb]) zs[16 * bb + wk.sl] = zt;
     }
     const double ssum = nyls_wave_sum(sacc);
-    ymax = nyls_wave_max(ymax);
     __syncthreads();
     for (int e = lane; e < N; e += 64) {
       double val = 0.0;
@@ -181,19 +216,21 @@ __global__ __launch_bounds__(64) void k_points(
         alv[bb] = acc;
       }
     }
-    // The change of y_hat(t) is phi(t)^T d_omega + d_b, and |phi(t)|_2^2 is the Nystrom
-    // approximation of k(t, t) = 1, which never exceeds it: |d_y_hat| <= |d_omega|_2 + |d_b|.
     double dsq = 0.0;
     for (int k = lane; k < r; k += 64) dsq += Rv[k] * Rv[k];
-    corr = sqrt(nyls_wave_sum(dsq)) + fabs(Rv[m]);
-    if (corr <= 1e-11 * ymax) {  // y_hat written by this pass is final to rounding level
+    const double bound = sqrt(nyls_wave_sum(dsq)) + fabs(Rv[m]);
+    if (bound <= tol_stop * ymax) {
+      corr = bound;
       need_output = false;
       break;
     }
   }
   if (need_output) {
-    double zacc[NB], sacc = 0.0, ym = 0.0;
-    pass(std::false_type{}, xv[m], zacc, sacc, ym);
+    double zacc[NB], sacc = 0.0, dmax = 0.0;
+    ymax = 0.0;
+    pass(std::false_type{}, xv[m], zacc, sacc, ymax, refine > 0, dmax);
+    ymax = nyls_wave_max(ymax);
+    corr = nyls_wave_max(dmax);
   }
 
   for (int e = lane; e < N; e += 64) ws[L.x + e] = xv[e];
@@ -208,7 +245,7 @@ __global__ __launch_bounds__(64) void k_points(
     if (bias_out) bias_out[inst] = xv[m];
     int bits = (int)ws[L.info + 1];
     if (!(fabs(xv[m]) <= 1.7976931348623157e308)) bits |= NYLS_S_NONFINITE;
-    if (refine > 0 && need_output && corr > 1e-8 * ymax) bits |= NYLS_S_REFINE_NOCONV;
+    if (refine > 0 && corr > tol_flag * ymax) bits |= NYLS_S_REFINE_NOCONV;
     ws[L.info + 1] = (double)bits;
     ws[L.info + 3] = corr;
     ws[L.info + 5] = (double)passes;
@@ -216,22 +253,37 @@ __global__ __launch_bounds__(64) void k_points(
   }
 }
 
+template <int NB, bool EX>
+void launch_nbx(const nyls_plan_view& pv, double* ws, int refine, double* yhat, double* omega,
+                double* bias, double* lambda, int32_t* status, int single, double ts, double tf,
+                hipStream_t st) {
+  const dim3 grid(single >= 0 ? 1 : pv.batch);
+  if (pv.p_mask & 2)
+    hipLaunchKernelGGL((k_points<NB, 1, EX>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
+                       refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf);
+  if (pv.p_mask & 4)
+    hipLaunchKernelGGL((k_points<NB, 2, EX>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
+                       refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf);
+  if (pv.p_mask & 8)
+    hipLaunchKernelGGL((k_points<NB, 3, EX>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
+                       refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf);
+  if (pv.p_mask & 16)
+    hipLaunchKernelGGL((k_points<NB, 4, EX>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
+                       refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf);
+}
+
 template <int NB>
 hipError_t launch_nb(const nyls_plan_view& pv, double* ws, int refine, double* yhat, double* omega,
                      double* bias, double* lambda, int32_t* status, int single, hipStream_t st) {
-  const dim3 grid(single >= 0 ? 1 : pv.batch);
-  if (pv.p_mask & 2)
-    hipLaunchKernelGGL((k_points<NB, 1>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws, refine,
-                       yhat, omega, bias, lambda, status, pv.maxm, single);
-  if (pv.p_mask & 4)
-    hipLaunchKernelGGL((k_points<NB, 2>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws, refine,
-                       yhat, omega, bias, lambda, status, pv.maxm, single);
-  if (pv.p_mask & 8)
-    hipLaunchKernelGGL((k_points<NB, 3>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws, refine,
-                       yhat, omega, bias, lambda, status, pv.maxm, single);
-  if (pv.p_mask & 16)
-    hipLaunchKernelGGL((k_points<NB, 4>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws, refine,
-                       yhat, omega, bias, lambda, status, pv.maxm, single);
+  // Refinement stops once the change of y_hat falls below tol_stop max|y_hat| and flags
+  // instances whose last change stayed above tol_flag.  Both modes refine to the same
+  // level: the adjoint's residual terms (dl/dgamma) need the forward solution to FP64
+  // accuracy, whatever precision the factorisation had.
+  const double ts = 1e-11, tf = 1e-8;
+  if (pv.rec_mask & 2)
+    launch_nbx<NB, false>(pv, ws, refine, yhat, omega, bias, lambda, status, single, ts, tf, st);
+  if (pv.rec_mask & 1)
+    launch_nbx<NB, true>(pv, ws, refine, yhat, omega, bias, lambda, status, single, ts, tf, st);
   return hipGetLastError();
 }
 

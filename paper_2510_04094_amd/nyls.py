@@ -131,7 +131,9 @@ class Batch:
     the plan points into.  `mode` is FP64, MIXED or FP64_EXPLICIT.
     """
 
-    def __init__(self, instances, mode=FP64, device="cuda"):
+    def __init__(self, instances, mode=FP64, device="cuda", explicit_grid=False):
+        """explicit_grid: pass every grid as its time array (nyls_problem.uniform = 0)
+        instead of (t0, dt)."""
         lib = load()
         self.mode = mode
         self.device = torch.device(device)
@@ -156,15 +158,23 @@ class Batch:
         self.f = torch.tensor(f_host, dtype=torch.float64, device=self.device)
         self.r = torch.tensor(r_host, dtype=torch.float64, device=self.device)
         self.v = torch.tensor(v_host, dtype=torch.float64, device=self.device)
+        self.t = None
+        if explicit_grid:
+            self.t = torch.tensor(np.concatenate([np.asarray(q["t"], dtype=np.float64) for q in instances]),
+                                  dtype=torch.float64, device=self.device)
         self._foff = fo
         self._lidx_host = []
         probs = (Problem * nb)()
         for i, q in enumerate(instances):
             pr = probs[i]
             pr.p, pr.n, pr.m = int(q["p"]), int(q["n"]), int(q["m"])
-            pr.uniform = 1
             pr.t0, pr.dt = float(q["t0"]), float(q["dt"])
-            pr.t = None
+            if explicit_grid:
+                pr.uniform = 0
+                pr.t = self.t.data_ptr() + 8 * int(self.goff[i])
+            else:
+                pr.uniform = 1
+                pr.t = None
             if q.get("lidx") is not None:
                 arr = (ctypes.c_int32 * pr.m)(*[int(x) for x in q["lidx"]])
                 self._lidx_host.append(arr)

@@ -128,6 +128,37 @@ def test_fp64_ill_conditioned_uses_eigenbasis_gram(gpu_lib):
     assert np.all(out["status"].cpu().numpy() & gpu_lib.S_REFINE_NOCONV == 0)
 
 
+@pytest.mark.parametrize("mode_name", ["FP64", "MIXED"])
+def test_explicit_time_arrays(gpu_lib, mode_name):
+    """Grids handed over as time arrays (nyls_problem.uniform = 0): every kernel value is
+    an exponential of its own, no recurrence."""
+    insts = [workloads.linear_first_order(i, n=n, m=m) for i, (n, m) in enumerate([(201, 20), (333, 25)])]
+    insts += [workloads.linear_second_order(i, n=1237 + 97 * i, m=50) for i in range(2)]
+    b = gpu_lib.Batch(insts, mode=getattr(gpu_lib, mode_name), explicit_grid=True)
+    out = b.solve()
+    torch.cuda.synchronize()
+    ys = gpu_yhat(b, out)
+    for i, sol in enumerate(oracle_solutions(insts)):
+        tol = (1e-10 if insts[i]["p"] == 1 else 1e-9) if mode_name == "FP64" else 1e-6
+        assert rel_inf(ys[i], sol["yhat"]) <= tol, (i, rel_inf(ys[i], sol["yhat"]))
+
+
+def test_fp64_coarse_grids(gpu_lib):
+    """dt > sigma / 4: the one-wave passes take their guarded path, where a run of the
+    recurrence that starts far from its landmark and approaches it is evaluated with exact
+    exponentials (spans of up to 250 sigma).  gamma = 1e4 keeps these narrow-kernel systems
+    conditioned well enough (cond <= 1e16 instead of 1e24) for the 1e-10 bar."""
+    cases = [(60, 20, 0.004), (120, 30, 0.02), (97, 12, 0.03), (400, 40, 0.01)]
+    insts = [workloads.linear_first_order(i, n=n, m=m, sigma=s, gamma=1e4)
+             for i, (n, m, s) in enumerate(cases)]
+    b = gpu_lib.Batch(insts, mode=gpu_lib.FP64)
+    out = b.solve()
+    torch.cuda.synchronize()
+    ys = gpu_yhat(b, out)
+    for i, sol in enumerate(oracle_solutions(insts)):
+        assert rel_inf(ys[i], sol["yhat"]) <= 1e-10, (i, rel_inf(ys[i], sol["yhat"]))
+
+
 @pytest.mark.parametrize("mode_name", ["FP64", "FP64_EXPLICIT"])
 def test_explicit_and_fused_agree(gpu_lib, mode_name):
     insts = config1(3) + config2(2, 800)
