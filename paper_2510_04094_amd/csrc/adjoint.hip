@@ -1,6 +1,6 @@
 // Adjoint of the Lemma 1 solve (Sec. 3.1): gradients of a loss l(y_hat(s_j)) with respect
 // to the ODE data f_k(t_i), r(t_i), the condition values v_j, gamma and sigma, reusing the
-// factorisation nyls_solve left in the workspace.  One workgroup per instance.
+// factorisation nyls_solve left in the workspace.
 //
 // With x = (omega, b, lambda) solving A x = rhs (A symmetric), alpha = W omega and the ODE
 // residual e_i = p_i^T alpha + c_i b - r_i:
@@ -19,197 +19,202 @@
 //      sum_{l < r} [ sum_{k < r} F_kl Qb_kl D_kl + 2 sum_{k >= r} F_kl Qb_kl D_kl ],
 //      Qb_kl = sqrt(lam_l)/2 ((U^T g1)_k omega_l - (U^T g2)_k mu_l),  D = U^T dK_mm/dsigma U,
 //      F_kl = -1/(lam_k lam_l) (k < r), 1/(lam_l (lam_l - lam_k)) (k >= r).
+//
+// One wavefront per instance with the lane layout of nyls_walk.h (the refinement pass of
+// the forward solve has the same structure).  The gradient pass forms, per (point, landmark)
+// pair, p_i, d p_i / d sigma and k^(q)_i (q < p) from the Hermite factors, reduces their
+// dot products with alpha and beta over the landmarks, and keeps sum_i e_i p_i and
+// sum_i nu_i p_i in registers.  d/dsigma of the q-th kernel derivative h_q e is
+// -e (q h_q / sigma + z h_{q+1}) (h_q as in nyls_hfac, z = (t - t_s) / sigma).
 #include "nyls_dense.h"
+#include "nyls_walk.h"
 
 namespace {
 
-constexpr int TP = 16;
-constexpr int CH = 8;                 // points per thread in the Gaussian recurrence
-constexpr int TPG = NYLS_BLOCK / TP;  // threads per point in the dot products
+template <int NB, int P, bool EX>
+__global__ __launch_bounds__(64) void k_backward(
+    const nyls_desc* __restrict__ desc, const int32_t* __restrict__ order,
+    double* __restrict__ wsbase, int refine, const double* __restrict__ t_obs,
+    const int64_t* __restrict__ obs_off, const double* __restrict__ gobs,
+    double* __restrict__ dl_df, double* __restrict__ dl_dr, double* __restrict__ dl_dv,
+    double* __restrict__ dl_dsigma, double* __restrict__ dl_dgamma, int64_t total) {
+  constexpr int ML = 16 * NB;   // landmark slots
+  constexpr int Q = 4 + 2 * P;  // dot products per point in the gradient pass
+  constexpr int NKL = ML + 1 + P;
+  __shared__ __align__(16) double tile[Q * 16 * NYLS_WALK_PAD];
+  __shared__ double bc[2 * 16];
+  __shared__ double tl[ML], kb[ML], ae[ML], an[ML], ug1[ML], ug2[ML];
+  __shared__ double hk[P][ML];
+  __shared__ double xv[NKL], mu[NKL], R[NKL], xb[NKL];
+  __shared__ int piv[NKL];
 
-// d/dsigma of the q-th kernel derivative:
-// (-1)^(q+1) sigma^(-q-1) e^{-z^2} (q H_q(z) - z H_{q+1}(z)), all q = 0..NYLS_MAX_P.
-__device__ inline void kderiv_dsigma_e(double z, double e, double inv_sigma,
-                                       double (&ds)[NYLS_MAX_P + 1]) {
-  double hm = 1.0, h = 2.0 * z;     // H_q, H_{q+1} with q = 0
-  double sc = -inv_sigma;           // (-1)^(q+1) sigma^(-q-1)
-#pragma unroll
-  for (int q = 0; q <= NYLS_MAX_P; ++q) {
-    ds[q] = sc * e * (q * hm - z * h);
-    const double hn = 2.0 * z * h - 2.0 * (q + 1) * hm;
-    hm = h;
-    h = hn;
-    sc *= -inv_sigma;
-  }
-}
-
-__device__ inline void kderiv_dsigma(double z, double inv_sigma, double (&ds)[NYLS_MAX_P + 1]) {
-  kderiv_dsigma_e(z, exp(-z * z), inv_sigma, ds);
-}
-
-__global__ __launch_bounds__(NYLS_BLOCK) void k_backward(
-    const nyls_desc* __restrict__ desc, double* __restrict__ wsbase, int refine,
-    const double* __restrict__ t_obs, const int64_t* __restrict__ obs_off,
-    const double* __restrict__ gobs, double* __restrict__ dl_df, double* __restrict__ dl_dr,
-    double* __restrict__ dl_dv, double* __restrict__ dl_dsigma, double* __restrict__ dl_dgamma,
-    int64_t total, int maxm) {
-  extern __shared__ double sm[];
-  const int inst = blockIdx.x;
+  const int inst = order ? order[blockIdx.x] : (int)blockIdx.x;
   const nyls_desc& d = desc[inst];
-  const int m = d.m, p = d.p, n = d.n;
-  const int N = m + 1 + p;
-  const nyls_wsl L = nyls_layout(m, p, 0);
+  if (d.p != P || d.rec != (EX ? 0 : 1)) return;  // another launch handles this instance
+  const int m = d.m, n = d.n;
+  const int N = m + 1 + P;
+  const nyls_wsl L = nyls_layout(m, P, 0);
   double* ws = wsbase + d.ws;
   const double* W = ws + L.W;
   const double* U = ws + L.U;
   const double* lamv = ws + L.lam;
   const double* LU = ws + L.lu;
-  const int tid = threadIdx.x;
+  const double* Hc = ws + L.H;
+  const int lane = threadIdx.x;
   const int r = (int)ws[L.info + 0];
-  const double gam = d.gamma, sig = d.sigma, inv_sigma = 1.0 / sig;
+  const double gam = d.gamma;
 
-  double* tl = sm;                      // [128] landmark times
-  double* al = tl + NYLS_MAX_M;         // [128] alpha
-  double* be = al + NYLS_MAX_M;         // [128] beta = W mu_omega
-  double* kb = be + NYLS_MAX_M;         // [128] kbar, later g1
-  double* ae = kb + NYLS_MAX_M;         // [128] sum e_i p_i, later g2
-  double* an = ae + NYLS_MAX_M;         // [128] sum nu_i p_i
-  double* hk = an + NYLS_MAX_M;         // [4][128] kernel-space condition vectors
-  double* xv = hk + NYLS_MAX_P * NYLS_MAX_M;  // [136] x
-  double* mu = xv + 136;                // [136]
-  double* R = mu + 136;                 // [136]
-  double* ug = R + 136;                 // [2][128] U^T g1, U^T g2
-  double* part = ug + 2 * NYLS_MAX_M;   // [2][256]
-  double* red = part + 2 * NYLS_BLOCK;  // [16]
-  double* pd = red + 16;                // [TP][8] per-point scalars
-  double* wq = pd + TP * 8;             // [TP][NYLS_MAX_P+1] operator weights per point
-  int* piv = reinterpret_cast<int*>(wq + TP * (NYLS_MAX_P + 1));  // [136]
-  double* big = reinterpret_cast<double*>(piv + 136);
-  double* P = big;                      // [TP][m]   p_i
-  double* DP = P + TP * maxm;           // [TP][m]   d p_i / d sigma
-  double* KQ = DP + TP * maxm;          // [p][TP][m] k^(q)_i, q < p
+  nyls_walk<NB, EX> wk;
+  wk.init(d, lane);
+  const int sl = wk.sl, ph = wk.ph;
+  const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
+  const __amdgpu_buffer_rsrc_t fr = nyls_rsrc(d.f, P * n * 8), rr = nyls_rsrc(d.r, n * 8);
 
-  for (int s = tid; s < m; s += NYLS_BLOCK) {
-    tl[s] = nyls_grid_t(d, d.lidx[s]);
-    al[s] = ws[L.alpha + s];
-  }
-  for (int a = tid; a < N; a += NYLS_BLOCK) {
+  for (int s = lane; s < m; s += 64) tl[s] = nyls_grid_t(d, d.lidx[s]);
+  for (int a = lane; a < N; a += 64) {
     xv[a] = ws[L.x + a];
     piv[a] = (int)ws[L.piv + a];
   }
+  double alv[NB], bev[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) alv[b] = wk.lv[b] ? ws[L.alpha + 16 * b + sl] : 0.0;
   __syncthreads();
-  const double b = xv[m];
+  const double bias = xv[m];
 
-  // 1. observations: kbar, sum g, and the direct sigma term sum g_j alpha^T dk(s_j)/dsigma
+  // 1. observations (phase ph takes every fourth one): kbar, sum g, and the direct sigma
+  //    term sum_j g_j alpha^T dk(s_j)/dsigma, dK/dsigma = K 2 z^2 / sigma
   const int64_t j0 = obs_off[inst], j1 = obs_off[inst + 1];
   double t1 = 0.0, gsum = 0.0;
-  for (int s = tid; s < m; s += NYLS_BLOCK) {
-    double acc = 0.0;
-    for (int64_t j = j0; j < j1; ++j) {
-      const double z = (t_obs[j] - tl[s]) * inv_sigma;
-      acc += gobs[j] * exp(-z * z);
+  {
+    double kba[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) kba[b] = 0.0;
+    for (int64_t j = j0 + ph; j < j1; j += 4) {
+      const double tj = t_obs[j], gj = gobs[j];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        if (!wk.lv[b]) continue;
+        const double z = (tj - tl[16 * b + sl]) * inv_sigma;
+        const double e = exp(-z * z);
+        kba[b] += gj * e;
+        t1 += gj * alv[b] * (2.0 * z * z * inv_sigma) * e;
+      }
     }
-    kb[s] = acc;
-  }
-  for (int64_t j = j0 + tid; j < j1; j += NYLS_BLOCK) {
-    gsum += gobs[j];
-    double acc = 0.0;
-    for (int s = 0; s < m; ++s) {
-      const double z = (t_obs[j] - tl[s]) * inv_sigma;
-      acc += al[s] * (2.0 * z * z * inv_sigma) * exp(-z * z);  // dK/dsigma = K 2 z^2 / sigma
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const double v = nyls_walk_fold(kba[b]);
+      if (ph == 0 && wk.lv[b]) kb[16 * b + sl] = v;
     }
-    t1 += gobs[j] * acc;
+    for (int64_t j = j0 + lane; j < j1; j += 64) gsum += gobs[j];
+    t1 = nyls_wave_sum(t1);
+    gsum = nyls_wave_sum(gsum);
   }
   // condition vectors k^(d_j)(t_{i_j}) (kernel space)
-  for (int e = tid; e < p * m; e += NYLS_BLOCK) {
+  for (int e = lane; e < P * m; e += 64) {
     const int j = e / m, s = e - j * m;
     const double z = (nyls_grid_t(d, d.cond_i[j]) - tl[s]) * inv_sigma;
-    double kd[NYLS_MAX_P + 1];
-    nyls_kderiv(z, inv_sigma, kd);
-    hk[j * NYLS_MAX_M + s] = nyls_pick(kd, d.cond_d[j]);
+    double h[P + 2];
+    nyls_hfac<P>(-2.0 * inv_sigma * z, inv_s2, h);
+    double hv = 0.0;
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+      if (q == d.cond_d[j]) hv = h[q];
+    hk[j][s] = hv * exp(-z * z);
   }
-  gsum = nyls_block_sum(gsum, red);
-  t1 = nyls_block_sum(t1, red);
   __syncthreads();
+
   // 2. x_bar and mu = A^{-1} x_bar
-  for (int a = tid; a < N; a += NYLS_BLOCK) {
+  for (int a = lane; a < N; a += 64) {
     double val = 0.0;
     if (a < r) {
       for (int s = 0; s < m; ++s) val += W[s * m + a] * kb[s];
     } else if (a == m) {
       val = gsum;
     }
-    R[a] = val;
+    xb[a] = val;
     mu[a] = val;
   }
   __syncthreads();
-  nyls_lu_solve(LU, N, N, piv, mu);
+  nyls_lu_solve_w(LU, N, N, piv, mu);
+  auto beta_from_mu = [&]() {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int s = 16 * b + sl;
+      double acc = 0.0;
+      if (wk.lv[b])
+        for (int k = 0; k < r; ++k) acc += W[s * m + k] * mu[k];
+      bev[b] = acc;
+    }
+  };
+  beta_from_mu();
 
-  const int ngc = NYLS_BLOCK / m, cs = tid % m, cg = tid / m;
-  // 2b. refinement of mu: residual x_bar - A mu from one FP64 pass over the points
-  for (int step = 0; step <= refine; ++step) {
-    for (int s = tid; s < m; s += NYLS_BLOCK) {
-      double acc = 0.0;
-      for (int k = 0; k < r; ++k) acc += W[s * m + k] * mu[k];
-      be[s] = acc;
-    }
-    __syncthreads();
-    if (step == refine) break;
+  // 2b. refinement of mu: the residual x_bar - A mu from one FP64 pass over the points
+  //     (nu_i = p_i^T beta + c_i mu_b, A mu = (mu_w + gamma W^T sum nu p + H mu_l,
+  //     gamma sum c nu + delta^T mu_l, H^T mu_w + delta mu_b)).  Stops when the correction
+  //     is below 1e-12 of mu (omega and b parts) or stops halving.
+  double dprev = 0.0;
+  for (int step = 0; step < refine; ++step) {
     const double mub = mu[m];
-    double nacc = 0.0, cacc = 0.0;
-    for (int i0 = 0; i0 < n; i0 += TP) {
-      __syncthreads();
-      for (int e = tid; e < TP; e += NYLS_BLOCK) {
-        const int i = i0 + e;
-        const bool ok = i < n && !nyls_is_condition_point(d, i);
-        double w[NYLS_MAX_P + 1];
-        nyls_opweights(p, [&](int k) { return ok ? d.f[(size_t)(k - 1) * n + i] : 0.0; }, w);
+    double zacc[NB], sacc = 0.0;
 #pragma unroll
-        for (int q = 0; q <= NYLS_MAX_P; ++q) wq[e * (NYLS_MAX_P + 1) + q] = w[q];
-      }
-      __syncthreads();
-      nyls_gauss_tile<TP, CH>(d, i0, tl, inv_sigma, [&](int pt, int s, double zz, double ev) {
-        double kd[NYLS_MAX_P + 1];
-        nyls_kderiv_e(zz, ev, inv_sigma, kd);
-        const double* w = wq + pt * (NYLS_MAX_P + 1);
-        double v = 0.0;
+    for (int b = 0; b < NB; ++b) zacc[b] = 0.0;
+    double fj[P][4], cp = 0.0;
+    auto load = [&](int i0, double (&f)[P][4], double& c_) {
 #pragma unroll
-        for (int q = 0; q <= NYLS_MAX_P; ++q) v += w[q] * kd[q];
-        P[pt * m + s] = v;
-      });
-      __syncthreads();
-      {
-        const int pt = tid / TPG, sub = tid % TPG;
-        const int i = i0 + pt;
-        double acc = 0.0;
-        for (int s = sub; s < m; s += TPG) acc += P[pt * m + s] * be[s];
-        for (int o = TPG / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (sub == 0) {
-          double nu = 0.0;
-          if (i < n && !nyls_is_condition_point(d, i)) {
-            const double c = -d.f[(size_t)(p - 1) * n + i];
-            nu = acc + c * mub;
-            cacc += c * nu;
-          }
-          pd[pt * 8] = nu;
-        }
-      }
-      __syncthreads();
-      if (cg < ngc)
-        for (int pt = cg; pt < TP; pt += ngc) nacc += pd[pt * 8] * P[pt * m + cs];
-    }
-    part[tid] = cg < ngc ? nacc : 0.0;
-    const double csum = nyls_block_sum(cacc, red);
-    __syncthreads();
-    for (int s = tid; s < m; s += NYLS_BLOCK) {
+      for (int k = 0; k < P; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) f[k][j] = nyls_bload(fr, (k * n + i0 + 4 * j + ph) * 8);
+      c_ = -nyls_bload(fr, ((P - 1) * n + i0 + (lane & 15)) * 8);
+    };
+    load(0, fj, cp);
+    for (int i0 = 0; i0 < n; i0 += 16) {
+      wk.advance(d, i0);
+      double fn[P][4], cpn;
+      load(i0 + 16, fn, cpn);
+      double pe[NB][4];
       double acc = 0.0;
-      for (int gi = 0; gi < ngc; ++gi) acc += part[gi * m + s];
-      an[s] = acc;
+      wk.chunk(
+          d, i0,
+          [&](int b, int j, double z, double e) {
+            double h[P + 2];
+            nyls_hfac<P>(-2.0 * inv_sigma * z, inv_s2, h);
+            double poly = h[P];
+#pragma unroll
+            for (int k = 1; k <= P; ++k) poly -= fj[k - 1][j] * h[P - k];
+            pe[b][j] = e * poly;
+            acc += bev[b] * pe[b][j];
+          },
+          [&](int j) {
+            nyls_walk_put(tile, lane, 0, j, acc);
+            acc = 0.0;
+          });
+      double tot[1];
+      nyls_walk_sum<1>(tile, lane, tot);
+      const int ip = i0 + (lane & 15);
+      const bool okp = ip < n && !nyls_is_condition_point(d, ip);
+      const double nu = okp ? tot[0] + cp * mub : 0.0;
+      if (lane < 16) sacc += cp * nu;
+      const double w1[1] = {nu};
+      double nj[1][4];
+      nyls_walk_bcast<1>(w1, bc, lane, nj);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) zacc[b] += nj[0][j] * pe[b][j];
+#pragma unroll
+      for (int k = 0; k < P; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fj[k][j] = fn[k][j];
+      cp = cpn;
     }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const double v = nyls_walk_fold(zacc[b]);
+      if (ph == 0 && wk.lv[b]) an[16 * b + sl] = v;
+    }
+    const double csum = nyls_wave_sum(sacc);
     __syncthreads();
-    // R = x_bar - A mu (A mu: mu_w + gamma W^T sum nu p + H mu_l ; gamma sum c nu + d^T mu_l ;
-    //                         H^T mu_w + d mu_b)
-    for (int a = tid; a < N; a += NYLS_BLOCK) {
+    for (int a = lane; a < N; a += 64) {
       double amu;
       if (a < m) {
         amu = mu[a];
@@ -217,230 +222,249 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_backward(
           double acc = 0.0;
           for (int s = 0; s < m; ++s) acc += W[s * m + a] * an[s];
           amu += gam * acc;
-          for (int j = 0; j < p; ++j) amu += ws[L.H + j * m + a] * mu[m + 1 + j];
+          for (int j = 0; j < P; ++j) amu += Hc[j * m + a] * mu[m + 1 + j];
         }
       } else if (a == m) {
         amu = gam * csum;
-        for (int j = 0; j < p; ++j) amu += (d.cond_d[j] == 0 ? 1.0 : 0.0) * mu[m + 1 + j];
+        for (int j = 0; j < P; ++j) amu += (d.cond_d[j] == 0 ? 1.0 : 0.0) * mu[m + 1 + j];
       } else {
         const int j = a - m - 1;
         amu = d.cond_d[j] == 0 ? mu[m] : 0.0;
-        for (int k = 0; k < r; ++k) amu += ws[L.H + j * m + k] * mu[k];
+        for (int k = 0; k < r; ++k) amu += Hc[j * m + k] * mu[k];
       }
-      double xb = 0.0;
-      if (a < r) { for (int s = 0; s < m; ++s) xb += W[s * m + a] * kb[s]; }
-      else if (a == m) xb = gsum;
-      part[NYLS_BLOCK + a] = xb - amu;
+      R[a] = xb[a] - amu;
     }
     __syncthreads();
-    for (int a = tid; a < N; a += NYLS_BLOCK) R[a] = part[NYLS_BLOCK + a];
-    __syncthreads();
-    nyls_lu_solve(LU, N, N, piv, R);
-    double dn = 0.0, xn = 0.0;
-    for (int a = tid; a < N; a += NYLS_BLOCK) {
-      mu[a] += R[a];
-      dn = fmax(dn, fabs(R[a]));
-      xn = fmax(xn, fabs(mu[a]));
+    nyls_lu_solve_w(LU, N, N, piv, R);
+    double dsq = 0.0, xsq = 0.0;
+    for (int k = lane; k < r; k += 64) {
+      dsq += R[k] * R[k];
+      xsq += mu[k] * mu[k];
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      dn = fmax(dn, __shfl_xor(dn, o));
-      xn = fmax(xn, __shfl_xor(xn, o));
-    }
+    const double dn = sqrt(nyls_wave_sum(dsq)) + fabs(R[m]);
+    const double xn = sqrt(nyls_wave_sum(xsq)) + fabs(mu[m]);
+    for (int a = lane; a < N; a += 64) mu[a] += R[a];
     __syncthreads();
-    if ((tid & 63) == 0) { part[tid >> 6] = dn; part[8 + (tid >> 6)] = xn; }
-    __syncthreads();
-    dn = fmax(fmax(part[0], part[1]), fmax(part[2], part[3]));
-    xn = fmax(fmax(part[8], part[9]), fmax(part[10], part[11]));
-    __syncthreads();
-    if (dn <= 1e-13 * xn) refine = step + 1;  // converged: the next iteration only forms beta
+    beta_from_mu();
+    const bool stalled = step > 0 && dn > 0.5 * dprev;
+    dprev = dn;
+    if (dn <= 1e-12 * xn || stalled) break;
   }
   const double mub = mu[m];
 
-  // 3. gradient pass over the points
-  double sum_nu_e = 0.0, t2 = 0.0, aeacc = 0.0, anacc = 0.0;
-  for (int i0 = 0; i0 < n; i0 += TP) {
-    __syncthreads();
-    for (int e = tid; e < TP; e += NYLS_BLOCK) {
-      const int i = i0 + e;
-      double w[NYLS_MAX_P + 1];
-      nyls_opweights(p, [&](int k) { return i < n ? d.f[(size_t)(k - 1) * n + i] : 0.0; }, w);
+  // 3. gradient pass
+  double aeacc[NB], anacc[NB], sne = 0.0, t2 = 0.0;
 #pragma unroll
-      for (int q = 0; q <= NYLS_MAX_P; ++q) wq[e * (NYLS_MAX_P + 1) + q] = w[q];
-    }
-    __syncthreads();
-    nyls_gauss_tile<TP, CH>(d, i0, tl, inv_sigma, [&](int pt, int s, double zz, double ev) {
-      double kd[NYLS_MAX_P + 1], ds[NYLS_MAX_P + 1];
-      nyls_kderiv_e(zz, ev, inv_sigma, kd);
-      kderiv_dsigma_e(zz, ev, inv_sigma, ds);
-      const double* w = wq + pt * (NYLS_MAX_P + 1);
-      double pv = 0.0, dpv = 0.0;
+  for (int b = 0; b < NB; ++b) aeacc[b] = anacc[b] = 0.0;
+  {
+    double fj[P][4], rp = 0.0, cp = 0.0;
+    auto load = [&](int i0, double (&f)[P][4], double& r_, double& c_) {
 #pragma unroll
-      for (int q = 0; q <= NYLS_MAX_P; ++q) {
-        pv += w[q] * kd[q];
-        dpv += w[q] * ds[q];
-      }
-      P[pt * m + s] = pv;
-      DP[pt * m + s] = dpv;
+      for (int k = 0; k < P; ++k)
 #pragma unroll
-      for (int q = 0; q < NYLS_MAX_P; ++q)
-        if (q < p) KQ[(q * TP + pt) * m + s] = kd[q];
-    });
-    __syncthreads();
-    {
-      const int pt = tid / TPG, sub = tid % TPG;
-      const int i = i0 + pt;
-      double ap = 0.0, bp = 0.0, adp = 0.0, bdp = 0.0;
-      double ak[NYLS_MAX_P], bk[NYLS_MAX_P];
+        for (int j = 0; j < 4; ++j) f[k][j] = nyls_bload(fr, (k * n + i0 + 4 * j + ph) * 8);
+      const int ip = i0 + (lane & 15);
+      r_ = nyls_bload(rr, ip * 8);
+      c_ = -nyls_bload(fr, ((P - 1) * n + ip) * 8);
+    };
+    load(0, fj, rp, cp);
+    for (int i0 = 0; i0 < n; i0 += 16) {
+      wk.advance(d, i0);
+      double fn[P][4], rpn, cpn;
+      load(i0 + 16, fn, rpn, cpn);
+      double pe[NB][4];
+      double acc[Q];
 #pragma unroll
-      for (int q = 0; q < NYLS_MAX_P; ++q) { ak[q] = 0.0; bk[q] = 0.0; }
-      for (int s = sub; s < m; s += TPG) {
-        const double pv = P[pt * m + s], dpv = DP[pt * m + s];
-        ap += al[s] * pv;
-        bp += be[s] * pv;
-        adp += al[s] * dpv;
-        bdp += be[s] * dpv;
+      for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+      wk.chunk(
+          d, i0,
+          [&](int b, int j, double z, double e) {
+            double h[P + 2];
+            nyls_hfac<P>(-2.0 * inv_sigma * z, inv_s2, h);
+            // w_P = 1, w_q = -f_{P-q}:  poly = sum w_q h_q, sa = sum q w_q h_q,
+            // sb = sum w_q h_{q+1}
+            double poly = h[P], sa = P * h[P], sb = h[P + 1];
 #pragma unroll
-        for (int q = 0; q < NYLS_MAX_P; ++q)
-          if (q < p) {
-            const double kv = KQ[(q * TP + pt) * m + s];
-            ak[q] += al[s] * kv;
-            bk[q] += be[s] * kv;
-          }
-      }
-      for (int o = TPG / 2; o > 0; o >>= 1) {
-        ap += __shfl_xor(ap, o);
-        bp += __shfl_xor(bp, o);
-        adp += __shfl_xor(adp, o);
-        bdp += __shfl_xor(bdp, o);
+            for (int k = 1; k <= P; ++k) {
+              const double fk = fj[k - 1][j];
+              poly -= fk * h[P - k];
+              sa -= (double)(P - k) * fk * h[P - k];
+              sb -= fk * h[P - k + 1];
+            }
+            const double pv = e * poly;
+            const double dpv = -e * (inv_sigma * sa + z * sb);
+            pe[b][j] = pv;
+            acc[0] += alv[b] * pv;
+            acc[1] += bev[b] * pv;
+            acc[2] += alv[b] * dpv;
+            acc[3] += bev[b] * dpv;
 #pragma unroll
-        for (int q = 0; q < NYLS_MAX_P; ++q) {
-          ak[q] += __shfl_xor(ak[q], o);
-          bk[q] += __shfl_xor(bk[q], o);
-        }
-      }
-      if (sub == 0 && i < n) {
-        const bool ok = !nyls_is_condition_point(d, i);
-        double e = 0.0, nu = 0.0;
-        if (ok) {
-          const double c = -d.f[(size_t)(p - 1) * n + i];
-          e = ap + c * b - d.r[i];
-          nu = bp + c * mub;
-          sum_nu_e += nu * e;
-          t2 += e * bdp + nu * adp;
-        }
-        pd[pt * 8 + 0] = e;
-        pd[pt * 8 + 1] = nu;
-        if (dl_dr) dl_dr[d.goff + i] = ok ? gam * nu : 0.0;
+            for (int q = 0; q < P; ++q) {
+              const double kq = e * h[q];
+              acc[4 + q] += alv[b] * kq;
+              acc[4 + P + q] += bev[b] * kq;
+            }
+          },
+          [&](int j) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+              nyls_walk_put(tile, lane, q, j, acc[q]);
+              acc[q] = 0.0;
+            }
+          });
+      double tot[Q];
+      nyls_walk_sum<Q>(tile, lane, tot);
+      const int ip = i0 + (lane & 15);
+      const bool okp = ip < n && !nyls_is_condition_point(d, ip);
+      const double ei = okp ? tot[0] + cp * bias - rp : 0.0;
+      const double nui = okp ? tot[1] + cp * mub : 0.0;
+      if (lane < 16 && ip < n) {
+        sne += nui * ei;
+        t2 += ei * tot[3] + nui * tot[2];
+        if (dl_dr) dl_dr[d.goff + ip] = gam * nui;
         if (dl_df) {
 #pragma unroll
-          for (int k = 1; k <= NYLS_MAX_P; ++k) {
-            if (k > p) break;
-            const int q = p - k;
-            double yq = 0.0, zq = 0.0;
-#pragma unroll
-            for (int qq = 0; qq < NYLS_MAX_P; ++qq)
-              if (qq == q) { yq = ak[qq]; zq = bk[qq]; }
-            if (q == 0) { yq += b; zq += mub; }
-            dl_df[(size_t)(k - 1) * total + d.goff + i] = ok ? gam * (e * zq + nu * yq) : 0.0;
+          for (int k = 1; k <= P; ++k) {
+            const int q = P - k;
+            const double yq = tot[4 + q] + (q == 0 ? bias : 0.0);
+            const double zq = tot[4 + P + q] + (q == 0 ? mub : 0.0);
+            dl_df[(size_t)(k - 1) * total + d.goff + ip] = gam * (ei * zq + nui * yq);
           }
         }
-      } else if (sub == 0) {
-        pd[pt * 8 + 0] = 0.0;
-        pd[pt * 8 + 1] = 0.0;
       }
+      const double w2[2] = {ei, nui};
+      double en[2][4];
+      nyls_walk_bcast<2>(w2, bc, lane, en);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          aeacc[b] += en[0][j] * pe[b][j];
+          anacc[b] += en[1][j] * pe[b][j];
+        }
+#pragma unroll
+      for (int k = 0; k < P; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fj[k][j] = fn[k][j];
+      rp = rpn;
+      cp = cpn;
     }
-    __syncthreads();
-    if (cg < ngc)
-      for (int pt = cg; pt < TP; pt += ngc) {
-        aeacc += pd[pt * 8 + 0] * P[pt * m + cs];
-        anacc += pd[pt * 8 + 1] * P[pt * m + cs];
-      }
   }
-  part[tid] = cg < ngc ? aeacc : 0.0;
-  part[NYLS_BLOCK + tid] = cg < ngc ? anacc : 0.0;
-  sum_nu_e = nyls_block_sum(sum_nu_e, red);
-  t2 = nyls_block_sum(t2, red);
-  __syncthreads();
-  for (int s = tid; s < m; s += NYLS_BLOCK) {
-    double a1 = 0.0, a2 = 0.0;
-    for (int gi = 0; gi < ngc; ++gi) {
-      a1 += part[gi * m + s];
-      a2 += part[NYLS_BLOCK + gi * m + s];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const double va = nyls_walk_fold(aeacc[b]), vn = nyls_walk_fold(anacc[b]);
+    if (ph == 0 && wk.lv[b]) {
+      ae[16 * b + sl] = va;
+      an[16 * b + sl] = vn;
     }
-    ae[s] = a1;
-    an[s] = a2;
   }
+  const double sum_nu_e = nyls_wave_sum(sne);
+  t2 = nyls_wave_sum(t2);
   __syncthreads();
 
-  // 4. sigma: condition-row term, then the K_mm term
+  // 4. sigma: condition-row term (phase-0 lanes own the landmarks), then the K_mm term
   double t3 = 0.0;
-  for (int e = tid; e < p * m; e += NYLS_BLOCK) {
-    const int j = e / m, s = e - j * m;
-    const double z = (nyls_grid_t(d, d.cond_i[j]) - tl[s]) * inv_sigma;
-    double ds[NYLS_MAX_P + 1];
-    kderiv_dsigma(z, inv_sigma, ds);
-    t3 += (xv[m + 1 + j] * be[s] + mu[m + 1 + j] * al[s]) * nyls_pick(ds, d.cond_d[j]);
+  if (ph == 0) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (!wk.lv[b]) continue;
+      const int s = 16 * b + sl;
+      for (int j = 0; j < P; ++j) {
+        const double z = (nyls_grid_t(d, d.cond_i[j]) - tl[s]) * inv_sigma;
+        const double e = exp(-z * z);
+        double h[P + 2];
+        nyls_hfac<P>(-2.0 * inv_sigma * z, inv_s2, h);
+        double ds = 0.0;
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+          if (q == d.cond_d[j]) ds = -e * (q * inv_sigma * h[q] + z * h[q + 1]);
+        t3 += (xv[m + 1 + j] * bev[b] + mu[m + 1 + j] * alv[b]) * ds;
+      }
+    }
   }
-  t3 = nyls_block_sum(t3, red);
+  t3 = nyls_wave_sum(t3);
   // g1 = kbar - gamma sum nu p - H_k mu_lambda ; g2 = gamma sum e p + H_k lambda
-  for (int s = tid; s < m; s += NYLS_BLOCK) {
+  for (int s = lane; s < m; s += 64) {
     double g1 = kb[s] - gam * an[s], g2 = gam * ae[s];
-    for (int j = 0; j < p; ++j) {
-      g1 -= hk[j * NYLS_MAX_M + s] * mu[m + 1 + j];
-      g2 += hk[j * NYLS_MAX_M + s] * xv[m + 1 + j];
+    for (int j = 0; j < P; ++j) {
+      g1 -= hk[j][s] * mu[m + 1 + j];
+      g2 += hk[j][s] * xv[m + 1 + j];
     }
     kb[s] = g1;
     ae[s] = g2;
   }
   __syncthreads();
-  for (int k = tid; k < m; k += NYLS_BLOCK) {
+  for (int k = lane; k < m; k += 64) {
     double u1 = 0.0, u2 = 0.0;
     for (int s = 0; s < m; ++s) {
       u1 += U[s * m + k] * kb[s];
       u2 += U[s * m + k] * ae[s];
     }
-    ug[k] = u1;
-    ug[NYLS_MAX_M + k] = u2;
+    ug1[k] = u1;
+    ug2[k] = u2;
+  }
+  // dK_mm/dsigma into the (no longer needed) Gram block, then E = dK U[:, :r] into tmp
+  double* dK = ws + L.gram;
+  double* E = ws + L.tmp;
+  for (int e = lane; e < m * m; e += 64) {
+    const int a = e / m, s = e - a * m;
+    const double z = (tl[a] - tl[s]) * inv_sigma;
+    dK[e] = (2.0 * z * z * inv_sigma) * exp(-z * z);
   }
   __syncthreads();
-  // E = dK/dsigma U[:, :r] (global scratch), then D_kl = U[:, k]^T E[:, l]
-  double* E = ws + L.tmp;
-  for (int e = tid; e < m * r; e += NYLS_BLOCK) {
+  for (int e = lane; e < m * r; e += 64) {
     const int a = e / r, l = e - a * r;
     double acc = 0.0;
-    for (int s = 0; s < m; ++s) {
-      const double z = (tl[a] - tl[s]) * inv_sigma;
-      acc += (2.0 * z * z * inv_sigma) * exp(-z * z) * U[s * m + l];
-    }
+    for (int s = 0; s < m; ++s) acc += dK[a * m + s] * U[s * m + l];
     E[a * m + l] = acc;
   }
   __syncthreads();
   double tk = 0.0;
-  for (int e = tid; e < m * r; e += NYLS_BLOCK) {
+  for (int e = lane; e < m * r; e += 64) {
     const int k = e / r, l = e - k * r;
     double dkl = 0.0;
     for (int a = 0; a < m; ++a) dkl += U[a * m + k] * E[a * m + l];
     const double ll = lamv[l], lk = lamv[k];
-    const double qb = 0.5 * sqrt(ll) * (ug[k] * xv[l] - ug[NYLS_MAX_M + k] * mu[l]);
+    const double qb = 0.5 * sqrt(ll) * (ug1[k] * xv[l] - ug2[k] * mu[l]);
     const double fkl = (k < r) ? -1.0 / (lk * ll) : 1.0 / (ll * (ll - lk));
     tk += (k < r ? 1.0 : 2.0) * fkl * qb * dkl;
   }
-  tk = nyls_block_sum(tk, red);
-  if (tid == 0) {
+  tk = nyls_wave_sum(tk);
+  if (lane == 0) {
     if (dl_dgamma) dl_dgamma[inst] = -sum_nu_e;
     if (dl_dsigma) dl_dsigma[inst] = t1 - gam * t2 - t3 + tk;
   }
-  if (dl_dv)
-    for (int j = tid; j < NYLS_MAX_P; j += NYLS_BLOCK) dl_dv[inst * NYLS_MAX_P + j] = j < p ? mu[m + 1 + j] : 0.0;
-  for (int a = tid; a < N; a += NYLS_BLOCK) ws[L.mu + a] = mu[a];
+  if (dl_dv && lane < NYLS_MAX_P) dl_dv[inst * NYLS_MAX_P + lane] = lane < P ? mu[m + 1 + lane] : 0.0;
+  for (int a = lane; a < N; a += 64) ws[L.mu + a] = mu[a];
 }
 
-size_t backward_lds_bytes(int maxm, int maxp) {
-  const size_t common = (6 * NYLS_MAX_M + NYLS_MAX_P * NYLS_MAX_M + 3 * 136 + 2 * NYLS_MAX_M +
-                         2 * NYLS_BLOCK + 16 + TP * 8 + TP * (NYLS_MAX_P + 1)) * sizeof(double) +
-                        136 * sizeof(int);
-  const size_t tiles = (size_t)(2 + maxp) * TP * maxm * sizeof(double);
-  return common + tiles;
+template <int NB, bool EX>
+void launch_nbx(const nyls_plan_view& pv, double* ws, int refine, const double* t_obs,
+                const int64_t* obs_off, const double* g, double* dl_df, double* dl_dr,
+                double* dl_dv, double* dl_ds, double* dl_dg, hipStream_t st) {
+  const dim3 grid(pv.batch), block(64);
+  if (pv.p_mask & 2)
+    hipLaunchKernelGGL((k_backward<NB, 1, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws,
+                       refine, t_obs, obs_off, g, dl_df, dl_dr, dl_dv, dl_ds, dl_dg, pv.total);
+  if (pv.p_mask & 4)
+    hipLaunchKernelGGL((k_backward<NB, 2, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws,
+                       refine, t_obs, obs_off, g, dl_df, dl_dr, dl_dv, dl_ds, dl_dg, pv.total);
+  if (pv.p_mask & 8)
+    hipLaunchKernelGGL((k_backward<NB, 3, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws,
+                       refine, t_obs, obs_off, g, dl_df, dl_dr, dl_dv, dl_ds, dl_dg, pv.total);
+  if (pv.p_mask & 16)
+    hipLaunchKernelGGL((k_backward<NB, 4, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws,
+                       refine, t_obs, obs_off, g, dl_df, dl_dr, dl_dv, dl_ds, dl_dg, pv.total);
+}
+
+template <int NB>
+void launch_nb(const nyls_plan_view& pv, double* ws, int refine, const double* t_obs,
+               const int64_t* obs_off, const double* g, double* dl_df, double* dl_dr,
+               double* dl_dv, double* dl_ds, double* dl_dg, hipStream_t st) {
+  if (pv.rec_mask & 2)
+    launch_nbx<NB, false>(pv, ws, refine, t_obs, obs_off, g, dl_df, dl_dr, dl_dv, dl_ds, dl_dg, st);
+  if (pv.rec_mask & 1)
+    launch_nbx<NB, true>(pv, ws, refine, t_obs, obs_off, g, dl_df, dl_dr, dl_dv, dl_ds, dl_dg, st);
 }
 
 }  // namespace
@@ -455,13 +479,14 @@ extern "C" int nyls_backward(const nyls_plan* pl, const double* t_obs, const int
   const nyls_plan_view pv = nyls_plan_get_view(pl);
   if (pv.mode == NYLS_FP64_EXPLICIT) return NYLS_E_MODE;
   const int refine = 3;  // at most; stops once the correction is at rounding level
-  const size_t lds = backward_lds_bytes(pv.maxm, pv.maxp);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_backward),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  double* w = static_cast<double*>(ws);
   nyls_prof_begin(NYLS_K_BACKWARD, stream);
-  hipLaunchKernelGGL(k_backward, dim3(pv.batch), dim3(NYLS_BLOCK), lds, stream, pv.d_desc,
-                     static_cast<double*>(ws), refine, t_obs, obs_off, dl_dyobs, dl_df, dl_dr, dl_dv,
-                     dl_dsigma, dl_dgamma, pv.total, pv.maxm);
+  if (pv.maxm <= 32)
+    launch_nb<2>(pv, w, refine, t_obs, obs_off, dl_dyobs, dl_df, dl_dr, dl_dv, dl_dsigma, dl_dgamma, stream);
+  else if (pv.maxm <= 64)
+    launch_nb<4>(pv, w, refine, t_obs, obs_off, dl_dyobs, dl_df, dl_dr, dl_dv, dl_dsigma, dl_dgamma, stream);
+  else
+    launch_nb<8>(pv, w, refine, t_obs, obs_off, dl_dyobs, dl_df, dl_dr, dl_dv, dl_dsigma, dl_dgamma, stream);
   nyls_prof_end(NYLS_K_BACKWARD, stream);
   return hipGetLastError() == hipSuccess ? NYLS_OK : NYLS_E_HIP;
 }
