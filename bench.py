@@ -26,6 +26,35 @@ if ROOT not in sys.path:
 
 PEAK = {"fp64": 78.6e12, "fp32_mfma": 157.3e12, "hbm": 8.0e12}
 
+# HBM traffic of the dominant kernel per launch on this workload, from two rocprofv3 --pmc
+# passes (FETCH_SIZE, WRITE_SIZE in KiB) scaled by what the counters read for a 1 GiB device
+# copy (fetch x2, write x1); reported only while the kernel's sources are unchanged.
+TRAFFIC = {
+    "backward": {
+        "sources": ["paper_2510_04094_amd/csrc/adjoint.hip", "paper_2510_04094_amd/csrc/nyls_walk.h",
+                    "paper_2510_04094_amd/csrc/nyls_dense.h", "paper_2510_04094_amd/csrc/nyls_internal.h"],
+        "sha1": "f24043723264ef1e02a7a564a3877ac41f0175f5",
+        "kib": {"mixed": (2076942.4, 1119803.2), "fp64": (1865787.9, 1118494.6)},
+        "scale": (2.0, 1.0),
+    },
+}
+
+
+def measured_traffic(kernel, mode, batch):
+    """Calibrated HBM bytes per launch, or None when not measured for this kernel/source."""
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None or batch != 4096 or mode not in t["kib"]:
+        return None
+    h = hashlib.sha1()
+    for f in t["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != t["sha1"]:
+        return None
+    fk, wk = t["kib"][mode]
+    return (fk * t["scale"][0] + wk * t["scale"][1]) * 1024.0
+
 
 def make_instances(count, n, m, seed_config):
     from paper_2510_04094_amd import workloads
@@ -87,7 +116,6 @@ def run_mode(nyls, insts, mode, steps, warmup):
     tt, oo, off = b._offsets(t_obs)
     cnt = torch.tensor(np.diff(off), dtype=torch.float64, device="cuda")
     inst_of = torch.repeat_interleave(torch.arange(b.batch, device="cuda"), torch.tensor(np.diff(off), device="cuda"))
-    import ctypes
     lib = nyls.load()
     dl = dict(
         dl_df=torch.zeros(nyls.MAX_P, b.total, dtype=torch.float64, device="cuda"),
@@ -121,7 +149,41 @@ def run_mode(nyls, insts, mode, steps, warmup):
     t1 = time.perf_counter()
     nyls.profile_enable(False)
     prof = nyls.profile_read()
-    return b, out, (t1 - t0) / steps, prof
+    info = b.info().cpu().numpy()
+    return b, out, (t1 - t0) / steps, prof, info
+
+
+def work_model(kernel, n, m, p, r, passes_fw, passes_bw, n_obs):
+    """Algorithmic work of one instance in one launch of `kernel`: (flops, bound, peak).
+
+    Only the multiply-adds the method needs once kernel-derivative values exist are counted
+    (exponentials, Hermite factors and reductions are not): per (point, landmark) pair,
+      refinement pass   p + 3 FMA   (operator contraction, p^T alpha, k^T alpha, rho p),
+      adjoint pass      p + 2 FMA   (contraction, p^T beta, nu p) per refinement pass of mu,
+                        4p + 6 FMA  (contraction of p and dp/dsigma, 2(p + 2) dot products
+                                     with alpha and beta, e p and nu p) for the gradients,
+      FP64 Gram         (m+2)(m+3)/2 + m p FMA per residual point,
+      FP32 Gram         m^2 (eigenbasis rotation) + (m+2)(m+3)/2 + m p FMA per residual point;
+    eigen 9 m^3 flop, KKT 2 m^2 r + (2/3) (m+1+p)^3 flop, predict 2 m flop per time."""
+    pairs = n * m
+    g = m + 2
+    nk = m + 1 + p
+    fp64 = (PEAK["fp64"], "alu")
+    if kernel == "backward":
+        return 2.0 * pairs * ((4 * p + 6) + (p + 2) * passes_bw), fp64
+    if kernel == "points":
+        return 2.0 * pairs * (p + 3) * passes_fw, fp64
+    if kernel == "gram64":
+        return 2.0 * (n - p) * (g * (g + 1) / 2 + m * p), fp64
+    if kernel == "gram32":
+        return 2.0 * (n - p) * (m * m + g * (g + 1) / 2 + m * p), (PEAK["fp32_mfma"], "mfma")
+    if kernel == "eig":
+        return 9.0 * m ** 3, fp64
+    if kernel == "kkt":
+        return 2.0 * m * m * r + 2.0 / 3.0 * nk ** 3, fp64
+    if kernel == "predict":
+        return 2.0 * m * n_obs, fp64
+    return 0.0, fp64
 
 
 def plain_fp64_rate(nyls, insts):
@@ -149,6 +211,8 @@ def main():
     ap.add_argument("--plain", type=int, default=32, help="instances for the plain FP64 comparator")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle instances timed (0: 4 per core)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the batch is data-parallel over independent "
@@ -160,12 +224,18 @@ def main():
     nyls.load()
     torch.cuda.set_device(0)
     seed_config = 2
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     insts = make_instances(args.batch, args.n, args.m, seed_config)
 
     results = {}
     for name in args.modes.split(","):
         mode = {"fp64": nyls.FP64, "mixed": nyls.MIXED}[name]
-        b, out, sec, prof = run_mode(nyls, insts, mode, args.steps, args.warmup)
+        b, out, sec, prof, info = run_mode(nyls, insts, mode, args.steps, args.warmup)
         # verification on a deterministic sample
         idx = np.unique(np.linspace(0, args.batch - 1, min(args.check, args.batch)).astype(int))
         y = out["yhat"].cpu().numpy()
@@ -177,34 +247,30 @@ def main():
         errs = np.array(errs)
         ok = float(np.mean(errs <= 1e-6))
         results[name] = dict(sec=sec, prof=prof, max_err=float(errs.max()), frac_ok=ok,
-                             rate=args.batch * ok / sec)
+                             rate=args.batch * ok / sec, rank=float(info[:, 0].mean()),
+                             passes_fw=float(info[:, 5].mean()), passes_bw=float(info[:, 6].mean()),
+                             sweeps=float(info[:, 2].mean()))
         del b, out
         torch.cuda.empty_cache()
 
     best = max(results, key=lambda k: results[k]["rate"])
     r = results[best]
     prof = r["prof"]
-    # dominant kernel of the step and its algorithmic work per launch
-    kname = max(prof, key=lambda k: prof[k][0])
+    # dominant kernel of the step: algorithmic work of one launch / its average duration
+    # (HIP events on the stream the kernels run on)
+    kname = max(prof, key=lambda k: prof[k][0] / max(prof[k][1], 1) * (prof[k][1] > 0))
     kms, kcnt = prof[kname]
     avg_s = kms / max(kcnt, 1) / 1e3
-    n_i = args.n - 1
-    g = args.m + 2
-    work = {
-        # symmetric Gram of (p_i, c_i, r_i): |I| g(g+1)/2 FMAs per instance
-        "gram64": (args.batch * n_i * g * (g + 1), "alu", PEAK["fp64"], "fp64 VALU"),
-        # rotation U^T p_i (m^2 FMAs) plus the Gram of the rotated rows
-        "gram32": (args.batch * n_i * (2 * args.m * args.m + g * (g + 1)), "mfma", PEAK["fp32_mfma"], "fp32 MFMA"),
-    }
-    if kname in work:
-        flops, bound, peak, what = work[kname]
-    else:
-        # per-point FP64 passes: kernel values, operator contraction and dot products
-        flops, bound, peak, what = (args.batch * args.n * args.m * 30, "alu", PEAK["fp64"], "fp64 VALU")
+    n_obs = 100
+    flops_inst, (peak, bound) = work_model(kname, args.n, args.m, 2, r["rank"], r["passes_fw"],
+                                           r["passes_bw"], n_obs)
+    flops = flops_inst * args.batch
     achieved = flops / avg_s
     roofline = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "kernel": kname,
-                "kernel_ms": avg_s * 1e3, "flops_per_launch": flops, "peak_kind": what}
+                "frac": achieved / peak, "traffic": measured_traffic(kname, best, args.batch),
+                "kernel": kname,
+                "kernel_ms": avg_s * 1e3, "flops_per_launch": flops,
+                "passes": {"refinement": r["passes_fw"], "adjoint_refinement": r["passes_bw"]}}
 
     line = {
         "metric": "ODE solves/s at n=1e4,m=50 (batched+adjoint vs plain FP64) at rel err<=1e-6",
@@ -225,7 +291,8 @@ def main():
                    "mode": best},
         "roofline": roofline,
         "modes": {k: {"solves_per_s": v["rate"], "ms_per_step": v["sec"] * 1e3, "max_rel_err": v["max_err"],
-                      "frac_ok": v["frac_ok"],
+                      "frac_ok": v["frac_ok"], "mean_rank": v["rank"], "mean_sweeps": v["sweeps"],
+                      "refinement_passes": v["passes_fw"], "adjoint_passes": v["passes_bw"],
                       "kernel_ms": {kk: vv[0] / max(vv[1], 1) for kk, vv in v["prof"].items() if vv[1]}}
                   for k, v in results.items()},
     }

@@ -75,8 +75,10 @@ enum {
   NYLS_S_NONFINITE = 4,       /* a NaN or Inf appeared in the solution */
   NYLS_S_EIG_NOCONV = 8,      /* the Jacobi eigensolver hit its sweep limit */
   NYLS_S_SMALL_PIVOT = 16,    /* Newton: a diagonal y-block entry |d_i| < 1e-10 gamma */
-  NYLS_S_REFINE_NOCONV = 32   /* refinement ended with its last change of y_hat above
+  NYLS_S_REFINE_NOCONV = 32,  /* refinement ended with its last change of y_hat above
                                  1e-8 max|y_hat| */
+  NYLS_S_FP64_RESOLVED = 64   /* NYLS_MIXED: refinement on the FP32 Gram did not converge, the
+                                 instance was solved again with the FP64 Gram */
 };
 
 /*
@@ -127,6 +129,13 @@ size_t nyls_workspace_size(const nyls_plan* plan);
 int64_t nyls_total_points(const nyls_plan* plan);
 /* MAXM of the batch (the padded stride of omega, eigval and phi). */
 int32_t nyls_max_m(const nyls_plan* plan);
+/* Copy each instance's diagnostics block from `ws` into info [batch][8] (device, FP64):
+ *   [0] retained rank r, [1] status bits, [2] eigensolver sweeps, [3] last change of
+ *   y_hat measured by the refinement, [4] 1 if the FP64 Gram was accumulated in the
+ *   eigenbasis, [5] refinement passes of the last nyls_solve, [6] refinement passes of the
+ *   last nyls_backward, [7] unused (0).  Values are those of the work functions enqueued
+ *   before it on `stream`. */
+int nyls_instance_info(const nyls_plan* plan, const void* ws, double* info, hipStream_t stream);
 
 /* Feature map (App. A.2 eq32, Sec. 3): eigendecompose K_mm and evaluate
  * phi^(d)(t) for d = 0..dmax (dmax <= 4) at caller times.

@@ -50,7 +50,8 @@ __global__ __launch_bounds__(64) void k_backward(
 
   const int inst = order ? order[blockIdx.x] : (int)blockIdx.x;
   const nyls_desc& d = desc[inst];
-  if (d.p != P || d.rec != (EX ? 0 : 1)) return;  // another launch handles this instance
+  if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB)
+    return;  // another launch handles this instance
   const int m = d.m, n = d.n;
   const int N = m + 1 + P;
   const nyls_wsl L = nyls_layout(m, P, 0);
@@ -153,7 +154,9 @@ __global__ __launch_bounds__(64) void k_backward(
   //     gamma sum c nu + delta^T mu_l, H^T mu_w + delta mu_b)).  Stops when the correction
   //     is below 1e-12 of mu (omega and b parts) or stops halving.
   double dprev = 0.0;
+  int passes = 0;
   for (int step = 0; step < refine; ++step) {
+    ++passes;
     const double mub = mu[m];
     double zacc[NB], sacc = 0.0;
 #pragma unroll
@@ -431,6 +434,7 @@ __global__ __launch_bounds__(64) void k_backward(
   }
   tk = nyls_wave_sum(tk);
   if (lane == 0) {
+    ws[L.info + 6] = (double)passes;
     if (dl_dgamma) dl_dgamma[inst] = -sum_nu_e;
     if (dl_dsigma) dl_dsigma[inst] = t1 - gam * t2 - t3 + tk;
   }
@@ -481,11 +485,11 @@ extern "C" int nyls_backward(const nyls_plan* pl, const double* t_obs, const int
   const int refine = 3;  // at most; stops once the correction is at rounding level
   double* w = static_cast<double*>(ws);
   nyls_prof_begin(NYLS_K_BACKWARD, stream);
-  if (pv.maxm <= 32)
+  if (pv.nb_mask & 4)
     launch_nb<2>(pv, w, refine, t_obs, obs_off, dl_dyobs, dl_df, dl_dr, dl_dv, dl_dsigma, dl_dgamma, stream);
-  else if (pv.maxm <= 64)
+  if (pv.nb_mask & 16)
     launch_nb<4>(pv, w, refine, t_obs, obs_off, dl_dyobs, dl_df, dl_dr, dl_dv, dl_dsigma, dl_dgamma, stream);
-  else
+  if (pv.nb_mask & 256)
     launch_nb<8>(pv, w, refine, t_obs, obs_off, dl_dyobs, dl_df, dl_dr, dl_dv, dl_dsigma, dl_dgamma, stream);
   nyls_prof_end(NYLS_K_BACKWARD, stream);
   return hipGetLastError() == hipSuccess ? NYLS_OK : NYLS_E_HIP;

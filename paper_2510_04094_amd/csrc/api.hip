@@ -20,6 +20,7 @@ struct nyls_plan {
   unsigned nt_mask = 0;
   unsigned p_mask = 0;
   unsigned rec_mask = 0;
+  unsigned nb_mask = 0;
   nyls_desc* d_desc = nullptr;
   int32_t* d_lidx = nullptr;
   int32_t* d_order = nullptr;
@@ -76,6 +77,8 @@ nyls_plan_view view(const nyls_plan* pl) {
   v.nt_mask = pl->nt_mask;
   v.p_mask = pl->p_mask;
   v.rec_mask = pl->rec_mask;
+  v.nb_mask = pl->nb_mask;
+  v.only = 0;
   return v;
 }
 
@@ -172,6 +175,7 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
     pl->nt_mask |= 1u << ((q.m + 2 + 15) / 16);
     pl->p_mask |= 1u << q.p;
     pl->rec_mask |= 1u << d.rec;
+    pl->nb_mask |= 1u << nyls_slot_blocks(q.m);
     pl->maxm = std::max(pl->maxm, q.m);
     pl->maxp = std::max(pl->maxp, q.p);
     pl->maxn = std::max(pl->maxn, q.n);
@@ -241,6 +245,25 @@ size_t nyls_workspace_size(const nyls_plan* pl) {
 int64_t nyls_total_points(const nyls_plan* pl) { return pl ? pl->total : 0; }
 
 int32_t nyls_max_m(const nyls_plan* pl) { return pl ? pl->maxm : 0; }
+
+namespace {
+__global__ void k_instance_info(const nyls_desc* __restrict__ desc, const double* __restrict__ ws,
+                                double* __restrict__ info, int batch) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= batch * 8) return;
+  const int i = e >> 3, k = e & 7;
+  const nyls_desc& d = desc[i];
+  info[e] = ws[d.ws + nyls_layout(d.m, d.p, 0).info + k];
+}
+}  // namespace
+
+int nyls_instance_info(const nyls_plan* pl, const void* ws, double* info, hipStream_t stream) {
+  if (!pl || !ws || !info) return NYLS_E_NULL;
+  const int threads = 256, blocks = (pl->batch * 8 + threads - 1) / threads;
+  hipLaunchKernelGGL(k_instance_info, dim3(blocks), dim3(threads), 0, stream, pl->d_desc,
+                     static_cast<const double*>(ws), info, pl->batch);
+  return hip_rc(hipGetLastError());
+}
 
 int nyls_features(const nyls_plan* pl, const double* t_eval, const int64_t* eval_off, int32_t dmax,
                   double* phi, double* eigval, int32_t* rank, void* ws, hipStream_t stream) {
@@ -320,6 +343,23 @@ int nyls_solve(const nyls_plan* pl, int32_t refine_steps, double* omega, double*
   if (e == hipSuccess)
     e = nyls_launch_points(pv, w, refine_steps, yhat, omega, bias, lambda, status, -1, stream);
   nyls_prof_end(NYLS_K_POINTS, stream);
+  if (pl->mode == NYLS_MIXED && refine_steps > 0 && e == hipSuccess) {
+    // Instances whose refinement on the FP32 Gram did not converge (K_mm too ill-conditioned
+    // for FP32 features) are solved again with the FP64 Gram in the eigenbasis; the kernels
+    // of this second round leave every other instance untouched.
+    nyls_plan_view rv = pv;
+    rv.only = NYLS_S_REFINE_NOCONV;
+    nyls_prof_begin(NYLS_K_GRAM64, stream);
+    e = nyls_launch_gram64(rv, w, stream);
+    nyls_prof_end(NYLS_K_GRAM64, stream);
+    nyls_prof_begin(NYLS_K_KKT, stream);
+    if (e == hipSuccess) e = nyls_launch_kkt(rv, w, nullptr, nullptr, 1, stream);
+    nyls_prof_end(NYLS_K_KKT, stream);
+    nyls_prof_begin(NYLS_K_POINTS, stream);
+    if (e == hipSuccess)
+      e = nyls_launch_points(rv, w, refine_steps, yhat, omega, bias, lambda, status, -1, stream);
+    nyls_prof_end(NYLS_K_POINTS, stream);
+  }
   return hip_rc(e);
 }
 

@@ -30,9 +30,11 @@ __device__ inline void block_coords(int blk, int nb, int& bi, int& bj) {
 
 __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restrict__ desc,
                                                        const int32_t* __restrict__ order,
-                                                       double* __restrict__ wsbase, int maxm) {
+                                                       double* __restrict__ wsbase, int maxm,
+                                                       int only) {
   extern __shared__ double sm[];
   const nyls_desc& d = desc[instance_of(order)];
+  if (only && !((int)wsbase[d.ws + nyls_layout(d.m, d.p, 0).info + 1] & only)) return;
   const int m = d.m, p = d.p, n = d.n;
   const int g = m + 2;
   const int gp = (g + 3) & ~3;
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
   // would lose most digits in W^T S W, so the rows are rotated by U^T first and the Gram is
   // accumulated in the eigenbasis (the KKT kernel then scales by Lambda^{-1/2}).
   const int rank = (int)ws[L.info + 0];
-  const bool rotate = rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam];
+  const bool rotate = only || (rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam]);
   const double* Ug = ws + L.U;
   const bool ulds = maxm <= 64;
   if (rotate && ulds)
@@ -191,6 +193,6 @@ hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t 
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_gram64, dim3(pv.batch), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws,
-                     pv.maxm);
+                     pv.maxm, pv.only);
   return hipGetLastError();
 }

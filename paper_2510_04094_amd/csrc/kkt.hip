@@ -24,10 +24,12 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
                                                     double* __restrict__ wsbase,
                                                     double* __restrict__ kkt_out,
                                                     double* __restrict__ rhs_out, int kn,
-                                                    int factor, int single, int eigbasis) {
+                                                    int factor, int single, int eigbasis,
+                                                    int only) {
   extern __shared__ double sm[];
   const int inst = single >= 0 ? single : instance_of(order);
   const nyls_desc& d = desc[inst];
+  if (only && !((int)wsbase[d.ws + nyls_layout(d.m, d.p, 0).info + 1] & only)) return;
   const int m = d.m, p = d.p;
   const int g = m + 2, N = m + 1 + p, lda = N + 1;
   const nyls_wsl L = nyls_layout(m, p, 0);
@@ -174,6 +176,7 @@ hipError_t nyls_launch_kkt(const nyls_plan_view& pv, double* ws, double* kkt_out
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const int kn = pv.maxm + 1 + NYLS_MAX_P;
   hipLaunchKernelGGL(k_kkt, dim3(pv.batch), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws,
-                     kkt_out, rhs_out, kn, factor, -1, pv.mode == NYLS_MIXED ? 1 : 0);
+                     kkt_out, rhs_out, kn, factor, -1, (pv.mode == NYLS_MIXED && !pv.only) ? 1 : 0,
+                     pv.only);
   return hipGetLastError();
 }

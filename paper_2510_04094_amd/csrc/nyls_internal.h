@@ -223,11 +223,18 @@ void nyls_prof_end(int kernel, hipStream_t st);
 enum { NYLS_K_EIG = 0, NYLS_K_GRAM64, NYLS_K_GRAM32, NYLS_K_KKT, NYLS_K_POINTS, NYLS_K_FEATURES,
        NYLS_K_PREDICT, NYLS_K_EXPLICIT, NYLS_K_NEWTON, NYLS_K_BACKWARD, NYLS_K_COUNT };
 
+// 16-landmark slot blocks per lane of the one-wave passes for an instance with m landmarks.
+__host__ __device__ inline int nyls_slot_blocks(int m) { return m <= 32 ? 2 : (m <= 64 ? 4 : 8); }
+
 // Host launchers (defined in the .hip files; all enqueue on `stream`).
 struct nyls_plan_view {
   int32_t batch, mode, maxm, maxp, maxn;
   unsigned p_mask;          // bit p set when some instance has ODE order p
   unsigned rec_mask;        // bit 1: some instance has rec == 1, bit 0: some has rec == 0
+  unsigned nb_mask;         // bit b set when some instance has nyls_slot_blocks(m) == b
+  int32_t only;             // nonzero: the Gram / KKT / refinement kernels process only the
+                            // instances whose status (info[1]) has one of these bits, with
+                            // the FP64 Gram in the eigenbasis (re-solve of a failed FP32 Gram)
   const nyls_desc* d_desc;
   const int32_t* d_order;   // instance order, most expensive first
   int64_t total;

@@ -36,7 +36,8 @@ __global__ __launch_bounds__(64) void k_points(
     const nyls_desc* __restrict__ desc, const int32_t* __restrict__ order,
     double* __restrict__ wsbase, int refine, double* __restrict__ yhat,
     double* __restrict__ omega_out, double* __restrict__ bias_out, double* __restrict__ lambda_out,
-    int32_t* __restrict__ status, int maxm, int single, double tol_stop, double tol_flag) {
+    int32_t* __restrict__ status, int maxm, int single, double tol_stop, double tol_flag,
+    int only) {
   __shared__ __align__(16) double tile[2 * 16 * NYLS_WALK_PAD];
   __shared__ double bc[16];
   __shared__ double Rv[NK], xv[NK], zs[NYLS_MAX_M];
@@ -44,7 +45,9 @@ __global__ __launch_bounds__(64) void k_points(
 
   const int inst = instance_of(order, single);
   const nyls_desc& d = desc[inst];
-  if (d.p != P || d.rec != (EX ? 0 : 1)) return;  // another launch handles this instance
+  if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB)
+    return;  // another launch handles this instance
+  if (only && !((int)wsbase[d.ws + nyls_layout(d.m, P, 0).info + 1] & only)) return;
   const int m = d.m, n = d.n;
   const int N = m + 1 + P;
   const nyls_wsl L = nyls_layout(m, P, 0);
@@ -243,7 +246,8 @@ __global__ __launch_bounds__(64) void k_points(
     lambda_out[(size_t)inst * NYLS_MAX_P + lane] = lane < P ? xv[m + 1 + lane] : 0.0;
   if (lane == 0) {
     if (bias_out) bias_out[inst] = xv[m];
-    int bits = (int)ws[L.info + 1];
+    int bits = (int)ws[L.info + 1] & ~NYLS_S_REFINE_NOCONV;
+    if (only) bits |= NYLS_S_FP64_RESOLVED;
     if (!(fabs(xv[m]) <= 1.7976931348623157e308)) bits |= NYLS_S_NONFINITE;
     if (refine > 0 && corr > tol_flag * ymax) bits |= NYLS_S_REFINE_NOCONV;
     ws[L.info + 1] = (double)bits;
@@ -260,16 +264,16 @@ void launch_nbx(const nyls_plan_view& pv, double* ws, int refine, double* yhat, 
   const dim3 grid(single >= 0 ? 1 : pv.batch);
   if (pv.p_mask & 2)
     hipLaunchKernelGGL((k_points<NB, 1, EX>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
-                       refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf);
+                       refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf, pv.only);
   if (pv.p_mask & 4)
     hipLaunchKernelGGL((k_points<NB, 2, EX>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
-                       refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf);
+                       refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf, pv.only);
   if (pv.p_mask & 8)
     hipLaunchKernelGGL((k_points<NB, 3, EX>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
-                       refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf);
+                       refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf, pv.only);
   if (pv.p_mask & 16)
     hipLaunchKernelGGL((k_points<NB, 4, EX>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
-                       refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf);
+                       refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf, pv.only);
 }
 
 template <int NB>
@@ -292,7 +296,8 @@ hipError_t launch_nb(const nyls_plan_view& pv, double* ws, int refine, double* y
 hipError_t nyls_launch_points(const nyls_plan_view& pv, double* ws, int refine, double* yhat,
                               double* omega, double* bias, double* lambda, int32_t* status,
                               int single, hipStream_t st) {
-  if (pv.maxm <= 32) return launch_nb<2>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
-  if (pv.maxm <= 64) return launch_nb<4>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
-  return launch_nb<8>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
+  if (pv.nb_mask & 4) launch_nb<2>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
+  if (pv.nb_mask & 16) launch_nb<4>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
+  if (pv.nb_mask & 256) launch_nb<8>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
+  return hipGetLastError();
 }

@@ -18,6 +18,7 @@ MAX_N = 1 << 25
 
 FP64, MIXED, FP64_EXPLICIT = 0, 1, 2
 S_TRUNCATED, S_SINGULAR, S_NONFINITE, S_EIG_NOCONV, S_SMALL_PIVOT, S_REFINE_NOCONV = 1, 2, 4, 8, 16, 32
+S_FP64_RESOLVED = 64
 
 _lib = None
 
@@ -44,6 +45,7 @@ EXPORTS = {
     "nyls_workspace_size": (ctypes.c_size_t, [ctypes.c_void_p]),
     "nyls_total_points": (ctypes.c_int64, [ctypes.c_void_p]),
     "nyls_max_m": (ctypes.c_int32, [ctypes.c_void_p]),
+    "nyls_instance_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nyls_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p]),
@@ -301,6 +303,13 @@ class Batch:
         return x, torch.stack(hist)
 
     # --- adjoint --------------------------------------------------------------------------
+    def info(self):
+        """[batch][8] diagnostics (rank, status, sweeps, last refinement change, Gram basis,
+        refinement passes of solve and of backward), as a float64 device tensor."""
+        out = torch.zeros(self.batch, 8, dtype=torch.float64, device=self.device)
+        _check(_lib.nyls_instance_info(self.plan, _ptr(self.ws), _ptr(out), _stream()), "nyls_instance_info")
+        return out
+
     def backward(self, t_obs_list, g_obs_list):
         """nyls_backward after solve(): gradients of a loss with dl/dy_hat(s_j) = g_j."""
         t, o, off = self._offsets(t_obs_list)
