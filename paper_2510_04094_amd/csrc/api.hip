@@ -21,6 +21,7 @@ struct nyls_plan {
   unsigned p_mask = 0;
   unsigned rec_mask = 0;
   unsigned nb_mask = 0;
+  unsigned gnb_mask = 0;
   nyls_desc* d_desc = nullptr;
   int32_t* d_lidx = nullptr;
   int32_t* d_order = nullptr;
@@ -78,6 +79,7 @@ nyls_plan_view view(const nyls_plan* pl) {
   v.p_mask = pl->p_mask;
   v.rec_mask = pl->rec_mask;
   v.nb_mask = pl->nb_mask;
+  v.gnb_mask = pl->gnb_mask;
   v.only = 0;
   return v;
 }
@@ -176,6 +178,7 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
     pl->p_mask |= 1u << q.p;
     pl->rec_mask |= 1u << d.rec;
     pl->nb_mask |= 1u << nyls_slot_blocks(q.m);
+    pl->gnb_mask |= 1u << nyls_slot_blocks(q.m + 2);
     pl->maxm = std::max(pl->maxm, q.m);
     pl->maxp = std::max(pl->maxp, q.p);
     pl->maxn = std::max(pl->maxn, q.n);

@@ -8,11 +8,12 @@
 // global scratch block.  Afterwards eigenvalues are sorted descending, each eigenvector is
 // signed so its largest-magnitude entry (first on ties) is positive, and eigenpairs with
 // lambda_k <= tau * lambda_1 are dropped (the retained rank r goes to info[0]).
-#include "nyls_internal.h"
+#include "nyls_dense.h"
 
 namespace {
 
 constexpr int kMaxSweeps = 40;
+constexpr int kQlMaxM = 64;       // bases up to this size use k_eig_ql
 constexpr int kVldsMaxM = 96;
 
 __device__ inline int instance_of(const int32_t* order, int single) {
@@ -27,6 +28,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig(const nyls_desc* __restrict_
   const int inst = instance_of(order, single);
   const nyls_desc& d = desc[inst];
   const int m = d.m;
+  if (m <= kQlMaxM) return;  // k_eig_ql handles it
   const nyls_wsl L = nyls_layout(m, d.p, 0);
   double* ws = wsbase + d.ws;
   const int tid = threadIdx.x;
@@ -179,6 +181,232 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig(const nyls_desc* __restrict_
   }
 }
 
+// ---- one wavefront per instance, m <= 64: Householder tridiagonalisation + implicit QL ----
+//
+// Lane i owns row i of the landmark matrix A in LDS (odd row stride: row-per-lane accesses
+// are conflict-free, a row read by all lanes at once is a broadcast) and the entries d_i, e_i
+// of the tridiagonal matrix in registers.
+//  1. For k = 0 .. m-3 the reflector H_k = I - beta v v^T maps A[k+1:, k] onto alpha e_1;
+//     the trailing block becomes B - v w^T - w v^T with p = beta B v,
+//     w = p - (beta/2)(v^T p) v.  v is kept in column k below the diagonal.
+//  2. Q = H_0 ... H_{m-3} is formed in place, last reflector first: each step applies H_k
+//     to the trailing block from the left and sets row and column k to e_k.
+//  3. Implicit QL on (d, e) with the shift from the leading 2 x 2 block of the active part;
+//     each sweep chases the bulge from the bottom of the unreduced block upwards with plane
+//     rotations, applied to the columns of Z = Q as they are formed (the column shared by
+//     consecutive rotations stays in a register).  The split test |e_i| <= eps (|d_i| +
+//     |d_{i+1}|) is evaluated by all lanes at once; the scalar recurrences read d and e with
+//     lane broadcasts and are evaluated by every lane (they are uniform).
+constexpr int kQlMaxIter = 60;  // QL sweeps per eigenvalue
+
+__device__ inline double sel_lane(double x, int lane, int i, double v) { return lane == i ? v : x; }
+
+__global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ desc,
+                                               const int32_t* __restrict__ order,
+                                               double* __restrict__ wsbase, int single, int lda) {
+  extern __shared__ double sm[];
+  const int inst = instance_of(order, single);
+  const nyls_desc& d = desc[inst];
+  const int m = d.m;
+  if (m > kQlMaxM) return;  // k_eig handles larger bases
+  const nyls_wsl L = nyls_layout(m, d.p, 0);
+  double* ws = wsbase + d.ws;
+  const int lane = threadIdx.x;
+  double* A = sm;                   // [kQlMaxM][lda]: K_mm, then Q, then Z
+  double* vv = A + kQlMaxM * lda;   // [64] reflector, broadcast copy
+  double* tt = vv + 64;             // [64] column sums / sign / sorted eigenvalues
+  double* tl = tt + 64;             // [64] landmark times
+  int* pos = reinterpret_cast<int*>(tl + 64);  // [64] sorted position
+  const bool own = lane < m;
+  double* Ar = A + lane * lda;
+
+  const double inv_sigma = 1.0 / d.sigma;
+  if (own) tl[lane] = nyls_grid_t(d, d.lidx[lane]);
+  __syncthreads();
+  if (own) {
+    const double ti = tl[lane];
+    for (int j = 0; j < m; ++j) {
+      const double z = (ti - tl[j]) * inv_sigma;
+      Ar[j] = exp(-z * z);
+    }
+  }
+  __syncthreads();
+
+  double dl = 0.0, el = 0.0, bl = 0.0;  // d_lane, e_lane, beta_lane
+  // 1. tridiagonalisation
+  for (int k = 0; k + 2 < m; ++k) {
+    const bool act = own && lane > k;
+    const double x = act ? Ar[k] : 0.0;
+    const double sig2 = nyls_wave_sum(x * x);
+    const double x1 = nyls_rdlane(x, k + 1);
+    dl = sel_lane(dl, lane, k, A[k * lda + k]);
+    if (!(sig2 - x1 * x1 > 0.0)) {  // already tridiagonal in this column: H_k = I
+      el = sel_lane(el, lane, k, x1);
+      if (act) Ar[k] = 0.0;
+      __syncthreads();
+      continue;
+    }
+    const double alpha = x1 >= 0.0 ? -sqrt(sig2) : sqrt(sig2);
+    const double beta = 1.0 / (sig2 - alpha * x1);  // 2 / v^T v
+    const double v = act ? (lane == k + 1 ? x - alpha : x) : 0.0;
+    el = sel_lane(el, lane, k, alpha);
+    bl = sel_lane(bl, lane, k, beta);
+    vv[lane] = v;
+    if (act) Ar[k] = v;
+    __syncthreads();
+    double pl = 0.0;
+    if (act)
+      for (int j = k + 1; j < m; ++j) pl += Ar[j] * vv[j];
+    pl *= beta;
+    const double K = 0.5 * beta * nyls_wave_sum(v * pl);
+    const double w = pl - K * v;
+    // w goes to row k right of the diagonal (never read again as matrix data)
+    if (act) A[k * lda + lane] = w;
+    __syncthreads();
+    if (act)
+      for (int j = k + 1; j < m; ++j) Ar[j] -= v * A[k * lda + j] + w * vv[j];
+    __syncthreads();
+  }
+  {
+    const double a22 = A[(m - 2) * lda + m - 2], a32 = A[(m - 1) * lda + m - 2],
+                 a33 = A[(m - 1) * lda + m - 1];
+    dl = sel_lane(dl, lane, m - 2, a22);
+    el = sel_lane(el, lane, m - 2, a32);
+    dl = sel_lane(dl, lane, m - 1, a33);
+    el = sel_lane(el, lane, m - 1, 0.0);
+  }
+  __syncthreads();
+
+  // 2. Q in place: the trailing 2 x 2 block starts as the identity
+  if (own && lane >= m - 2) {
+    Ar[m - 2] = lane == m - 2 ? 1.0 : 0.0;
+    Ar[m - 1] = lane == m - 1 ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = m - 3; k >= 0; --k) {
+    const bool act = own && lane > k;
+    const double v = act ? Ar[k] : 0.0;
+    const double beta = nyls_rdlane(bl, k);
+    if (beta != 0.0) {
+      vv[lane] = v;
+      __syncthreads();
+      // t_j = sum_i v_i Q[i][j] (lane j owns column j)
+      double t = 0.0;
+      if (act)
+        for (int i = k + 1; i < m; ++i) t += vv[i] * A[i * lda + lane];
+      tt[lane] = beta * t;
+      __syncthreads();
+      if (act)
+        for (int j = k + 1; j < m; ++j) Ar[j] -= v * tt[j];
+    }
+    // row and column k of Q: e_k
+    if (lane == k)
+      for (int j = k; j < m; ++j) Ar[j] = j == k ? 1.0 : 0.0;
+    if (act) Ar[k] = 0.0;
+    __syncthreads();
+  }
+
+  // 3. implicit QL on (d, e), rotations accumulated into Z (rows in A)
+  const double eps = 2.220446049250313e-16;
+  int iters = 0;
+  bool converged = true;
+  for (int l = 0; l < m; ++l) {
+    int it = 0;
+    for (;;) {
+      const double dn = __shfl_down(dl, 1);
+      const bool small = lane == m - 1 ||
+                         (lane >= l && lane < m - 1 && fabs(el) <= eps * (fabs(dl) + fabs(dn)));
+      const unsigned long long mask = __ballot(small && lane >= l);
+      const int mm = __ffsll((long long)mask) - 1;
+      if (mm == l) break;
+      if (++it > kQlMaxIter) { converged = false; break; }
+      ++iters;
+      const double dL = nyls_rdlane(dl, l), eL = nyls_rdlane(el, l);
+      double g = (nyls_rdlane(dl, l + 1) - dL) / (2.0 * eL);
+      double r = sqrt(g * g + 1.0);
+      g = nyls_rdlane(dl, mm) - dL + eL / (g + (g >= 0.0 ? r : -r));
+      double sn = 1.0, cs = 1.0, pp = 0.0;
+      double carry = own ? Ar[mm] : 0.0;
+      bool split = false;
+      for (int i = mm - 1; i >= l; --i) {
+        const double ei = nyls_rdlane(el, i);
+        const double f = sn * ei, b = cs * ei;
+        r = sqrt(f * f + g * g);
+        el = sel_lane(el, lane, i + 1, r);
+        if (r == 0.0) {  // exact deflation: the chase stops here
+          dl = sel_lane(dl, lane, i + 1, nyls_rdlane(dl, i + 1) - pp);
+          el = sel_lane(el, lane, mm, 0.0);
+          if (own) Ar[i + 1] = carry;
+          split = true;
+          break;
+        }
+        const double inv = 1.0 / r;
+        sn = f * inv;
+        cs = g * inv;
+        g = nyls_rdlane(dl, i + 1) - pp;
+        r = (nyls_rdlane(dl, i) - g) * sn + 2.0 * cs * b;
+        pp = sn * r;
+        dl = sel_lane(dl, lane, i + 1, g + pp);
+        g = cs * r - b;
+        if (own) {
+          const double z0 = Ar[i];
+          Ar[i + 1] = sn * z0 + cs * carry;
+          carry = cs * z0 - sn * carry;
+        }
+      }
+      if (split) continue;
+      if (own) Ar[l] = carry;
+      dl = sel_lane(dl, lane, l, nyls_rdlane(dl, l) - pp);
+      el = sel_lane(el, lane, l, g);
+      el = sel_lane(el, lane, mm, 0.0);
+    }
+  }
+  __syncthreads();
+
+  // 4. sort descending (ties by index), sign each eigenvector (largest |entry| positive,
+  //    first on ties), cut-off, W = U_r Lambda_r^{-1/2}
+  int ps = 0;
+  for (int j = 0; j < m; ++j) {
+    const double lj = nyls_rdlane(dl, j);
+    ps += (lj > dl) || (lj == dl && j < lane);
+  }
+  double sg = 1.0;
+  if (own) {
+    int jmax = 0;
+    double vmax = -1.0;
+    for (int s2 = 0; s2 < m; ++s2) {
+      const double a = fabs(A[s2 * lda + lane]);
+      if (a > vmax) { vmax = a; jmax = s2; }
+    }
+    sg = A[jmax * lda + lane] < 0.0 ? -1.0 : 1.0;
+    pos[lane] = ps;
+    vv[lane] = sg;
+    tt[ps] = dl;  // sorted eigenvalues
+  }
+  __syncthreads();
+  const double lam1 = tt[0];
+  int rank = 0;
+  for (int k = 0; k < m; ++k) rank += (tt[k] > d.tau * lam1) ? 1 : 0;
+  if (own) {
+    for (int k = 0; k < m; ++k) {  // row s = lane of U and W
+      const int pk = pos[k];
+      const double u = vv[k] * Ar[k];
+      ws[L.U + lane * m + pk] = u;
+      ws[L.W + lane * m + pk] = pk < rank ? u / sqrt(tt[pk]) : 0.0;
+    }
+    ws[L.lam + lane] = tt[lane];
+  }
+  if (lane == 0) {
+    int bits = 0;
+    if (rank < m) bits |= NYLS_S_TRUNCATED;
+    if (!converged) bits |= NYLS_S_EIG_NOCONV;
+    if (!(lam1 == lam1) || rank == 0) bits |= NYLS_S_NONFINITE;
+    ws[L.info + 0] = (double)rank;
+    ws[L.info + 1] = (double)bits;
+    ws[L.info + 2] = (double)iters;
+  }
+}
+
 size_t eig_lds_bytes(int maxm, bool vlds) {
   const size_t mats = (size_t)(vlds ? 2 : 1) * maxm * (maxm + 1) * sizeof(double);
   const size_t tail = (64 * 3 + 8 + NYLS_MAX_M) * sizeof(double) + (64 * 2 + NYLS_MAX_M) * sizeof(int) +
@@ -189,6 +417,17 @@ size_t eig_lds_bytes(int maxm, bool vlds) {
 }  // namespace
 
 hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hipStream_t st) {
+  if (pv.nb_mask & (4 | 16)) {  // some instance has m <= 64
+    const int mq = pv.maxm < kQlMaxM ? pv.maxm : kQlMaxM;
+    const int lda = mq | 1;
+    const size_t lds = (size_t)kQlMaxM * lda * sizeof(double) + 3 * 64 * sizeof(double) +
+                       64 * sizeof(int);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_ql),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_eig_ql, dim3(single >= 0 ? 1 : pv.batch), dim3(64), lds, st, pv.d_desc,
+                       pv.d_order, ws, single, lda);
+  }
+  if (!(pv.nb_mask & 256)) return hipGetLastError();
   const bool vlds = pv.maxm <= kVldsMaxM;
   const size_t lds = eig_lds_bytes(pv.maxm, vlds);
   const int grid = single >= 0 ? 1 : pv.batch;

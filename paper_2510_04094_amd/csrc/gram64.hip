@@ -1,15 +1,26 @@
-// FP64 operator Gram of Lemma 1 (Sec. 3.1), one workgroup per instance.
+// FP64 operator Gram of Lemma 1 (Sec. 3.1).
 //
 // For every residual point i the kernel-space row
 //     q_i = ( p_i[0..m-1], c_i, r_i ),  p_i = k_m^(p)(t_i) - sum_k f_k(t_i) k_m^(p-k)(t_i),
 //     c_i = -f_p(t_i),
-// is evaluated in registers/LDS (never written to HBM) and the symmetric Gram
+// is evaluated in registers (never written to HBM) and the symmetric Gram
 //     S~ = sum_i q_i q_i^T   ((m+2) x (m+2): S, u = sum c_i p_i, z = sum r_i p_i, ...)
-// is accumulated.  Points are processed in tiles of TP: the tile's rows are built in LDS,
-// then each thread owns 4 x 4 output blocks of the upper triangle and accumulates them
-// in registers; when few blocks exist the tile's points are split over thread groups.
-// Group partials are summed in a fixed order, so the result is bitwise reproducible.
-#include "nyls_internal.h"
+// is accumulated.
+//
+// k_gram64_mfma (kernel-space Gram, the common case): one wavefront per instance with the
+// lane layout of nyls_walk.h, where lane (sl, ph) holds q_i[16 b + sl] for the points
+// 4 j + ph of each 16-point chunk (columns m and m+1 carry c_i and r_i).  That is exactly the
+// operand layout of v_mfma_f64_16x16x4f64 with the four points of one j as the k dimension
+// (A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k), so every tile pair (I <= J) of the
+// Gram takes one FP64 MFMA per j: A = q[16 I + sl], B = q[16 J + sl], FP64 accumulation.
+//
+// k_gram64 (ill-conditioned K_mm: retained eigenvalues below 1e-9 lambda_1, or the FP64
+// re-solve of a mixed-precision instance): the rows are rotated by U^T first and the Gram is
+// accumulated in the eigenbasis (the KKT kernel then scales by Lambda^{-1/2}).  It also takes
+// the kernel-space Grams of m + 2 > 64, whose 36 MFMA tiles would not fit in registers.  256
+// threads per instance: 64-point tiles of rows in LDS, 4 x 4 register blocks per thread,
+// group partials summed in a fixed order.
+#include "nyls_walk.h"
 
 namespace {
 
@@ -58,6 +69,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
   // accumulated in the eigenbasis (the KKT kernel then scales by Lambda^{-1/2}).
   const int rank = (int)ws[L.info + 0];
   const bool rotate = only || (rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam]);
+  if (!rotate && nyls_slot_blocks(m + 2) <= 4) return;  // k_gram64_mfma handles it
   const double* Ug = ws + L.U;
   const bool ulds = maxm <= 64;
   if (rotate && ulds)
@@ -173,6 +185,122 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
   if (tid == 0) ws[L.info + 4] = rotate ? 1.0 : 0.0;
 }
 
+
+typedef double nyls_d4 __attribute__((ext_vector_type(4)));
+
+template <int NB, int P, bool EX>
+__global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict__ desc,
+                                                    const int32_t* __restrict__ order,
+                                                    double* __restrict__ wsbase, int only) {
+  constexpr int T = NB * (NB + 1) / 2;
+  const nyls_desc& d = desc[instance_of(order)];
+  if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m + 2) != NB) return;
+  const int m = d.m, n = d.n, g = m + 2;
+  const nyls_wsl L = nyls_layout(m, P, 0);
+  double* ws = wsbase + d.ws;
+  const int rank = (int)ws[L.info + 0];
+  if (only || (rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam])) return;  // k_gram64
+  const int lane = threadIdx.x;
+
+  nyls_walk<NB, EX> wk;
+  wk.init(d, lane);
+  const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
+  const __amdgpu_buffer_rsrc_t fr = nyls_rsrc(d.f, P * n * 8), rr = nyls_rsrc(d.r, n * 8);
+  // what this lane's slot b carries: 0 landmark, 1 c_i, 2 r_i, 3 nothing
+  int kind[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int s = 16 * b + wk.sl;
+    kind[b] = s < m ? 0 : (s == m ? 1 : (s == m + 1 ? 2 : 3));
+  }
+  nyls_d4 acc[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = nyls_d4{0.0, 0.0, 0.0, 0.0};
+
+  double fj[P][4], rj[4];
+  auto load = [&](int i0, double (&f)[P][4], double (&r_)[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = i0 + 4 * j + wk.ph;
+#pragma unroll
+      for (int k = 0; k < P; ++k) f[k][j] = nyls_bload(fr, (k * n + i) * 8);
+      r_[j] = nyls_bload(rr, i * 8);
+    }
+  };
+  load(0, fj, rj);
+  for (int i0 = 0; i0 < n; i0 += 16) {
+    wk.advance(d, i0);
+    double fn[P][4], rn[4];
+    load(i0 + 16, fn, rn);
+    double q[NB];
+    wk.chunk(
+        d, i0,
+        [&](int b, int j, double z, double e) {
+          double h[P + 2];
+          nyls_hfac<P>(-2.0 * inv_sigma * z, inv_s2, h);
+          double poly = h[P];
+#pragma unroll
+          for (int k = 1; k <= P; ++k) poly -= fj[k - 1][j] * h[P - k];
+          const double v = kind[b] == 0 ? e * poly
+                                         : (kind[b] == 1 ? -fj[P - 1][j] : (kind[b] == 2 ? rj[j] : 0.0));
+          q[b] = v;
+        },
+        [&](int j) {
+          const int i = i0 + 4 * j + wk.ph;
+          const bool ok = i < n && !nyls_is_condition_point(d, i);
+#pragma unroll
+          for (int b = 0; b < NB; ++b) q[b] = ok ? q[b] : 0.0;
+          int t = 0;
+#pragma unroll
+          for (int I = 0; I < NB; ++I)
+#pragma unroll
+            for (int J = I; J < NB; ++J) {
+              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(q[I], q[J], acc[t], 0, 0, 0);
+              ++t;
+            }
+        });
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) fj[k][j] = fn[k][j];
+      rj[j] = rn[j];
+    }
+  }
+  // tile (I, J): register v of lane l holds row 16 I + 4 v + l / 16, column 16 J + l % 16
+  double* out = ws + L.gram;
+  int t = 0;
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int J = I; J < NB; ++J) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = 16 * I + 4 * v + (lane >> 4), b = 16 * J + (lane & 15);
+        if (a < g && b < g) {
+          out[a * g + b] = acc[t][v];
+          if (I != J) out[b * g + a] = acc[t][v];
+        }
+      }
+      ++t;
+    }
+  if (lane == 0) ws[L.info + 4] = 0.0;
+}
+
+template <int NB, bool EX>
+void launch_mfma_nbx(const nyls_plan_view& pv, double* ws, hipStream_t st) {
+  const dim3 grid(pv.batch), block(64);
+  if (pv.p_mask & 2) hipLaunchKernelGGL((k_gram64_mfma<NB, 1, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
+  if (pv.p_mask & 4) hipLaunchKernelGGL((k_gram64_mfma<NB, 2, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
+  if (pv.p_mask & 8) hipLaunchKernelGGL((k_gram64_mfma<NB, 3, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
+  if (pv.p_mask & 16) hipLaunchKernelGGL((k_gram64_mfma<NB, 4, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
+}
+
+template <int NB>
+void launch_mfma_nb(const nyls_plan_view& pv, double* ws, hipStream_t st) {
+  if (pv.rec_mask & 2) launch_mfma_nbx<NB, false>(pv, ws, st);
+  if (pv.rec_mask & 1) launch_mfma_nbx<NB, true>(pv, ws, st);
+}
+
 }  // namespace
 
 size_t nyls_gram64_lds_bytes(int maxm) {
@@ -189,6 +317,10 @@ size_t nyls_gram64_lds_bytes(int maxm) {
 }
 
 hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t st) {
+  if (!pv.only) {
+    if (pv.gnb_mask & 4) launch_mfma_nb<2>(pv, ws, st);
+    if (pv.gnb_mask & 16) launch_mfma_nb<4>(pv, ws, st);
+  }
   const size_t lds = nyls_gram64_lds_bytes(pv.maxm);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

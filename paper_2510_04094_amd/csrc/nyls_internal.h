@@ -232,6 +232,7 @@ struct nyls_plan_view {
   unsigned p_mask;          // bit p set when some instance has ODE order p
   unsigned rec_mask;        // bit 1: some instance has rec == 1, bit 0: some has rec == 0
   unsigned nb_mask;         // bit b set when some instance has nyls_slot_blocks(m) == b
+  unsigned gnb_mask;        // bit b set when some instance has nyls_slot_blocks(m + 2) == b
   int32_t only;             // nonzero: the Gram / KKT / refinement kernels process only the
                             // instances whose status (info[1]) has one of these bits, with
                             // the FP64 Gram in the eigenbasis (re-solve of a failed FP32 Gram)

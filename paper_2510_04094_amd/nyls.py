@@ -303,6 +303,38 @@ class Batch:
         return x, torch.stack(hist)
 
     # --- adjoint --------------------------------------------------------------------------
+    def set_params(self, sigma=None, gamma=None):
+        """Change per-instance sigma and/or gamma ([batch] arrays): rebuilds the plan (host
+        validation and descriptor upload); the workspace keeps its size."""
+        lib = load()
+        for i in range(self.batch):
+            if sigma is not None:
+                self._probs[i].sigma = float(sigma[i])
+            if gamma is not None:
+                self._probs[i].gamma = float(gamma[i])
+        handle = ctypes.c_void_p()
+        _check(lib.nyls_plan_create(ctypes.cast(self._probs, ctypes.c_void_p), self.batch, self.mode,
+                                    ctypes.byref(handle)), "nyls_plan_create")
+        lib.nyls_plan_destroy(self.plan)
+        self.plan = handle
+
+    def params(self):
+        """Current per-instance (sigma, gamma) as numpy arrays."""
+        return (np.array([self._probs[i].sigma for i in range(self.batch)]),
+                np.array([self._probs[i].gamma for i in range(self.batch)]))
+
+    def f_index(self):
+        """Index of every entry of the flat coefficient array f (instance blocks [p][n]) in the
+        flattened [4][total points] layout of nyls_backward's dl/df."""
+        if getattr(self, "_fidx", None) is None:
+            parts = []
+            for i in range(self.batch):
+                p, n, g0 = int(self.p[i]), int(self.n[i]), int(self.goff[i])
+                k = np.arange(p)[:, None]
+                parts.append((k * self.total + g0 + np.arange(n)[None, :]).reshape(-1))
+            self._fidx = torch.tensor(np.concatenate(parts), dtype=torch.int64, device=self.device)
+        return self._fidx
+
     def info(self):
         """[batch][8] diagnostics (rank, status, sweeps, last refinement change, Gram basis,
         refinement passes of solve and of backward), as a float64 device tensor."""
@@ -313,8 +345,11 @@ class Batch:
     def backward(self, t_obs_list, g_obs_list):
         """nyls_backward after solve(): gradients of a loss with dl/dy_hat(s_j) = g_j."""
         t, o, off = self._offsets(t_obs_list)
-        g = torch.tensor(np.concatenate([np.asarray(x, dtype=np.float64) for x in g_obs_list]),
-                         dtype=torch.float64, device=self.device)
+        if torch.is_tensor(g_obs_list):
+            g = g_obs_list.to(device=self.device, dtype=torch.float64).contiguous()
+        else:
+            g = torch.tensor(np.concatenate([np.asarray(x, dtype=np.float64) for x in g_obs_list]),
+                             dtype=torch.float64, device=self.device)
         dev = self.device
         out = dict(
             dl_df=torch.zeros(MAX_P, self.total, dtype=torch.float64, device=dev),
@@ -327,3 +362,47 @@ class Batch:
                                   _ptr(out["dl_dv"]), _ptr(out["dl_dsigma"]), _ptr(out["dl_dgamma"]),
                                   _ptr(self.ws), _stream()), "nyls_backward")
         return out
+
+
+class SolveAtObservations(torch.autograd.Function):
+    """y_hat at observation times as a differentiable function of the ODE data.
+
+    forward(batch, t_obs_list, f, r, v, sigma, gamma) -> y_obs [sum of observation counts]
+      f [sum p_i n_i] (instance blocks [p][n], the layout of Batch.f), r [total points],
+      v [batch, 4] (condition values, zero-padded), sigma [batch], gamma [batch].
+    The values are written into the batch's device arrays (sigma / gamma changes rebuild the
+    plan), then nyls_solve and nyls_predict run; backward calls nyls_backward, which reuses
+    the factorisation, and maps dl/df, dl/dr, dl/dv, dl/dsigma, dl/dgamma onto the inputs.
+    """
+
+    @staticmethod
+    def forward(ctx, batch, t_obs_list, f, r, v, sigma, gamma):
+        with torch.no_grad():
+            batch.f.copy_(f.detach().reshape(-1))
+            batch.r.copy_(r.detach().reshape(-1))
+            batch.v.copy_(v.detach().reshape(-1))
+            s_new = sigma.detach().cpu().numpy()
+            g_new = gamma.detach().cpu().numpy()
+            s_old, g_old = batch.params()
+            if not (np.array_equal(s_new, s_old) and np.array_equal(g_new, g_old)):
+                batch.set_params(sigma=s_new, gamma=g_new)
+            batch.solve()
+            y, _ = batch.predict(t_obs_list, 0)
+        ctx.batch = batch
+        ctx.t_obs_list = t_obs_list
+        ctx.shapes = (f.shape, r.shape, v.shape)
+        return y
+
+    @staticmethod
+    def backward(ctx, grad_y):
+        b = ctx.batch
+        out = b.backward(ctx.t_obs_list, grad_y.detach())
+        fs, rs, vs = ctx.shapes
+        df = out["dl_df"].reshape(-1)[b.f_index()].reshape(fs)
+        dv = out["dl_dv"].reshape(vs)
+        return (None, None, df, out["dl_dr"].reshape(rs), dv, out["dl_dsigma"], out["dl_dgamma"])
+
+
+def solve_at_observations(batch, t_obs_list, f, r, v, sigma, gamma):
+    """Functional form of SolveAtObservations (see there)."""
+    return SolveAtObservations.apply(batch, t_obs_list, f, r, v, sigma, gamma)

@@ -105,3 +105,49 @@ def test_parameter_gradients_match_central_differences(gpu_lib):
                 assert rel(got, fd_i) <= 1e-4, (name, i, got, fd_i)
                 continue
             assert rel(got, fd[i]) <= 1e-4, (name, i, got, fd[i])
+
+
+def test_autograd_function_matches_directional_differences(gpu_lib):
+    """SolveAtObservations: loss.backward() through the adjoint kernel agrees with central
+    differences of the GPU forward along random directions in f, r, v and in sigma, gamma
+    (h = 1e-6 relative to the data scale)."""
+    insts = instances(3)
+    b = gpu_lib.Batch(insts, mode=gpu_lib.FP64)
+    dev = b.f.device
+    t_obs = [q["t_obs"] for q in insts]
+    y_obs = torch.tensor(np.concatenate([q["y_obs"] for q in insts]), device=dev)
+    f0, r0, v0 = b.f.clone(), b.r.clone(), b.v.clone().reshape(b.batch, gpu_lib.MAX_P)
+    s0 = torch.tensor([q["sigma"] for q in insts], dtype=torch.float64, device=dev)
+    g0 = torch.tensor([q["gamma"] for q in insts], dtype=torch.float64, device=dev)
+
+    def loss(f, r, v, s, g):
+        y = gpu_lib.solve_at_observations(b, t_obs, f, r, v, s, g)
+        return torch.mean((y - y_obs) ** 2)
+
+    xs = [t.clone().requires_grad_(True) for t in (f0, r0, v0, s0, g0)]
+    L = loss(*xs)
+    L.backward()
+    grads = [x.grad.clone() for x in xs]
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    # gamma: dl/dlog(gamma) is ~1e-11 here, so a small step drowns in the forward solve's
+    # rounding; a 1% step and a 1% bar check the plumbing instead
+    for which, rel_h in ((0, 1e-6), (1, 1e-6), (2, 1e-6), (3, 1e-5), (4, 1e-2)):
+        base = [f0, r0, v0, s0, g0]
+        direction = torch.randn(base[which].shape, generator=gen, dtype=torch.float64).to(dev)
+        if which == 2:
+            mask = torch.zeros_like(direction)
+            mask[:, :2] = 1.0  # second-order instances: two condition values each
+            direction = direction * mask
+        if which >= 3:
+            direction = direction * base[which]  # relative steps for sigma and gamma
+        h = rel_h
+        with torch.no_grad():
+            plus = [t.clone() for t in base]
+            minus = [t.clone() for t in base]
+            plus[which] = plus[which] + h * direction
+            minus[which] = minus[which] - h * direction
+            fd = (loss(*plus) - loss(*minus)).item() / (2 * h)
+        ad = float(torch.sum(grads[which] * direction))
+        tol = 1e-2 if which == 4 else 1e-4
+        scale = float(torch.sum(torch.abs(grads[which] * direction)))
+        assert abs(ad - fd) <= tol * max(abs(fd), 1e-12) + 1e-9 * scale, (which, ad, fd)
