@@ -21,6 +21,16 @@
 
 constexpr int NYLS_WALK_PAD = 18;  // LDS row stride (doubles) of the reduction tile
 
+// Exchange through LDS among the lanes of one wavefront (every kernel using these helpers
+// runs one wavefront per workgroup).  The LDS operations of a wavefront execute in program
+// order, so only compiler reordering has to be prevented; a workgroup barrier would also
+// wait for the outstanding global loads of the next chunk.
+__device__ inline void nyls_wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Hermite factors h_q = (-1/sigma)^q H_q(z), q = 0..P, so that the q-th t-derivative of
 // K(t, t_s) is h_q e.  With g = -2 z / sigma: h_0 = 1, h_1 = g,
 // h_{q+1} = g h_q - (2 q / sigma^2) h_{q-1}.
@@ -124,6 +134,27 @@ struct nyls_walk {
   }
 };
 
+// v + (v of lane l ^ 32), and v + (v of lane l ^ 16): the gfx950 lane-swap instructions
+// exchange halves of the wavefront in the VALU (no LDS round trip).  Both lanes of a pair
+// add the lower lane's value first, so they hold bitwise equal sums.
+__device__ inline double nyls_add_xor32(double v) {
+  const long long u = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+  const double a = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+  const double b = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+  return a + b;
+}
+
+__device__ inline double nyls_add_xor16(double v) {
+  const long long u = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+  const double a = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+  const double b = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+  return a + b;
+}
+
 // Sums over the 16 landmark slots, in two steps: every lane stores its partial (over its NB
 // landmarks) of quantity q at its point j with nyls_walk_put; nyls_walk_sum then returns in
 // every lane the totals of chunk point lane & 15.  tile: LDS, Q * 16 * NYLS_WALK_PAD
@@ -134,17 +165,15 @@ __device__ inline void nyls_walk_put(double* tile, int lane, int q, int j, doubl
 
 template <int Q>
 __device__ inline void nyls_walk_sum(const double* tile, int lane, double (&out)[Q]) {
-  __syncthreads();
+  nyls_wave_lds_sync();
   const int pt = lane & 15, qq = lane >> 4;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const double* row = tile + (q * 16 + pt) * NYLS_WALK_PAD + 4 * qq;
-    double s = (row[0] + row[1]) + (row[2] + row[3]);
-    s += __shfl_xor(s, 16);
-    s += __shfl_xor(s, 32);
-    out[q] = s;
+    const double s = (row[0] + row[1]) + (row[2] + row[3]);
+    out[q] = nyls_add_xor32(nyls_add_xor16(s));
   }
-  __syncthreads();
+  nyls_wave_lds_sync();
 }
 
 // Per-point values w[q] held by lanes 0..15 (for chunk point lane) are returned in every lane
@@ -155,18 +184,14 @@ __device__ inline void nyls_walk_bcast(const double (&w)[Q], double* buf, int la
   if (lane < 16)
 #pragma unroll
     for (int q = 0; q < Q; ++q) buf[q * 16 + (lane & 3) * 4 + (lane >> 2)] = w[q];
-  __syncthreads();
+  nyls_wave_lds_sync();
   const int ph = lane >> 4;
 #pragma unroll
   for (int q = 0; q < Q; ++q)
 #pragma unroll
     for (int j = 0; j < 4; ++j) out[q][j] = buf[q * 16 + ph * 4 + j];
-  __syncthreads();
+  nyls_wave_lds_sync();
 }
 
 // Sum of v over the four phases (lanes sl, sl + 16, sl + 32, sl + 48).
-__device__ inline double nyls_walk_fold(double v) {
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 32);
-  return v;
-}
+__device__ inline double nyls_walk_fold(double v) { return nyls_add_xor32(nyls_add_xor16(v)); }

@@ -63,6 +63,7 @@ __global__ __launch_bounds__(64) void k_points(
   wk.init(d, lane);
   const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
   const __amdgpu_buffer_rsrc_t fr = nyls_rsrc(d.f, P * n * 8), rr = nyls_rsrc(d.r, n * 8);
+  const __amdgpu_buffer_rsrc_t yr = nyls_rsrc(yhat + d.goff, n * 8);
   double alv[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) alv[b] = wk.lv[b] ? ws[L.alpha + 16 * b + wk.sl] : 0.0;
@@ -79,24 +80,26 @@ __global__ __launch_bounds__(64) void k_points(
                   bool track, double& dmax) {
     constexpr bool refining = decltype(REF)::value;
     constexpr int Q = refining ? 2 : 1;
-    // operator data of this lane's points (and of the point it finishes), one chunk ahead
-    double fj[P][4], rp = 0.0, cp = 0.0;
-    auto load = [&](int i0, double (&f)[P][4], double& r_, double& c_) {
+    // operator data of this lane's points (and of the point it finishes), and the previous
+    // pass's y_hat of that point, one chunk ahead
+    double fj[P][4], rp = 0.0, cp = 0.0, yp = 0.0;
+    auto load = [&](int i0, double (&f)[P][4], double& r_, double& c_, double& y_) {
+      const int ip = i0 + (lane & 15);
       if (refining) {
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
           for (int j = 0; j < 4; ++j) f[k][j] = nyls_bload(fr, (k * n + i0 + 4 * j + wk.ph) * 8);
-        const int ip = i0 + (lane & 15);
         r_ = nyls_bload(rr, ip * 8);
         c_ = -nyls_bload(fr, ((P - 1) * n + ip) * 8);
       }
+      y_ = track ? nyls_bload(yr, ip * 8) : 0.0;
     };
-    load(0, fj, rp, cp);
+    load(0, fj, rp, cp, yp);
     for (int i0 = 0; i0 < n; i0 += 16) {
       wk.advance(d, i0);
-      double fn[P][4], rpn = 0.0, cpn = 0.0;
-      load(i0 + 16, fn, rpn, cpn);
+      double fn[P][4], rpn = 0.0, cpn = 0.0, ypn = 0.0;
+      load(i0 + 16, fn, rpn, cpn, ypn);
       double pe[refining ? NB : 1][4];
       double acc0 = 0.0, acc1 = 0.0;
       wk.chunk(
@@ -125,7 +128,7 @@ __global__ __launch_bounds__(64) void k_points(
       const double yv = tot[0] + b;
       if (ip < n) {
         if (lane < 16) {
-          if (track) dmax = fmax(dmax, fabs(yv - yo[ip]));
+          if (track) dmax = fmax(dmax, fabs(yv - yp));
           yo[ip] = yv;
         }
         ymax = fmax(ymax, fabs(yv));
@@ -148,6 +151,7 @@ __global__ __launch_bounds__(64) void k_points(
         for (int j = 0; j < 4; ++j) fj[k][j] = fn[k][j];
       rp = rpn;
       cp = cpn;
+      yp = ypn;
     }
   };
 
