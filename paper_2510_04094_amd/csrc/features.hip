@@ -60,28 +60,35 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_features(
   }
 }
 
-__global__ __launch_bounds__(NYLS_BLOCK) void k_predict(
+__global__ __launch_bounds__(64) void k_predict(
     const nyls_desc* __restrict__ desc, const double* __restrict__ wsbase,
     const double* __restrict__ t_eval, const int64_t* __restrict__ eval_off, int dd,
     double* __restrict__ out) {
+  __shared__ double tl[NYLS_MAX_M], al[NYLS_MAX_M];
   const int inst = blockIdx.y;
   const nyls_desc& d = desc[inst];
   const int m = d.m;
   const nyls_wsl L = nyls_layout(m, d.p, 0);
   const double* ws = wsbase + d.ws;
+  const int64_t e0 = eval_off[inst], e1 = eval_off[inst + 1];
+  if (e0 + (int64_t)blockIdx.x * 64 >= e1) return;
+  for (int s = threadIdx.x; s < m; s += 64) {
+    tl[s] = nyls_grid_t(d, d.lidx[s]);
+    al[s] = ws[L.alpha + s];
+  }
+  __syncthreads();
   const double inv_sigma = 1.0 / d.sigma;
-  const int64_t e1 = eval_off[inst + 1];
-  for (int64_t e = eval_off[inst] + (int64_t)blockIdx.x * NYLS_BLOCK + threadIdx.x; e < e1;
-       e += (int64_t)gridDim.x * NYLS_BLOCK) {
+  const double bias = dd == 0 ? ws[L.x + m] : 0.0;
+  for (int64_t e = e0 + (int64_t)blockIdx.x * 64 + threadIdx.x; e < e1; e += (int64_t)gridDim.x * 64) {
     const double t = t_eval[e];
     double acc = 0.0;
     for (int s = 0; s < m; ++s) {
-      const double z = (t - nyls_grid_t(d, d.lidx[s])) * inv_sigma;
+      const double z = (t - tl[s]) * inv_sigma;
       double v[NYLS_MAX_P + 1];
       nyls_kderiv(z, inv_sigma, v);
-      acc += ws[L.alpha + s] * nyls_pick(v, dd);
+      acc += al[s] * nyls_pick(v, dd);
     }
-    out[e] = acc + (dd == 0 ? ws[L.x + m] : 0.0);
+    out[e] = acc + bias;
   }
 }
 
@@ -105,10 +112,9 @@ hipError_t nyls_launch_features(const nyls_plan_view& pv, const double* ws, cons
 hipError_t nyls_launch_predict(const nyls_plan_view& pv, const double* ws, const double* t_eval,
                                const int64_t* eval_off, int d, double* out, int64_t max_eval,
                                hipStream_t st) {
-  int64_t gx = (max_eval + NYLS_BLOCK - 1) / NYLS_BLOCK;
-  gx = gx < 1 ? 1 : (gx > 16 ? 16 : gx);
+  int64_t gx = (max_eval + 63) / 64;
+  gx = gx < 1 ? 1 : (gx > 64 ? 64 : gx);
   dim3 grid((unsigned)gx, pv.batch);
-  hipLaunchKernelGGL(k_predict, grid, dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, t_eval, eval_off, d,
-                     out);
+  hipLaunchKernelGGL(k_predict, grid, dim3(64), 0, st, pv.d_desc, ws, t_eval, eval_off, d, out);
   return hipGetLastError();
 }
