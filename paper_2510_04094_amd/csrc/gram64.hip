@@ -69,7 +69,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
   // accumulated in the eigenbasis (the KKT kernel then scales by Lambda^{-1/2}).
   const int rank = (int)ws[L.info + 0];
   const bool rotate = only || (rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam]);
-  if (!rotate && nyls_slot_blocks(m + 2) <= 4) return;  // k_gram64_mfma handles it
+  if (nyls_slot_blocks(m + 2) <= 4) return;  // the one-wave MFMA kernels handle it
   const double* Ug = ws + L.U;
   const bool ulds = maxm <= 64;
   if (rotate && ulds)
@@ -188,6 +188,15 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
 
 typedef double nyls_d4 __attribute__((ext_vector_type(4)));
 
+// Eigenbasis Gram when the smallest retained eigenvalue is below kRotate lambda_1 (the
+// kernel-space Gram would lose most digits in W^T S W) or when re-solving with FP64.
+constexpr double kRotate = 1e-9;
+
+__device__ inline bool use_eigenbasis(const double* ws, const nyls_wsl& L, int only) {
+  const int rank = (int)ws[L.info + 0];
+  return only || (rank > 0 && ws[L.lam + rank - 1] < kRotate * ws[L.lam]);
+}
+
 template <int NB, int P, bool EX>
 __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict__ desc,
                                                     const int32_t* __restrict__ order,
@@ -198,8 +207,7 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
   const int m = d.m, n = d.n, g = m + 2;
   const nyls_wsl L = nyls_layout(m, P, 0);
   double* ws = wsbase + d.ws;
-  const int rank = (int)ws[L.info + 0];
-  if (only || (rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam])) return;  // k_gram64
+  if (use_eigenbasis(ws, L, only)) return;  // k_gram64_rot_mfma
   const int lane = threadIdx.x;
 
   nyls_walk<NB, EX> wk;
@@ -286,9 +294,149 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
   if (lane == 0) ws[L.info + 4] = 0.0;
 }
 
+// Eigenbasis Gram on the matrix cores: per 16-point chunk the kernel-space rows are staged in
+// LDS (X[point][landmark]) and rotated, D = X U, with v_mfma_f64_16x16x4f64 (A = X in the
+// operand layout row = point, k = 4 landmarks; B = U, kept in registers).  The result
+// register v of lane l holds point 4 v + l / 16 and eigen-direction l % 16 of its block,
+// which is again the operand layout of the Gram MFMAs with the four points of register v
+// as the k dimension; columns m and m+1 take c_i and r_i before the Gram step.
+template <int NB, int P, bool EX>
+__global__ __launch_bounds__(64) void k_gram64_rot_mfma(const nyls_desc* __restrict__ desc,
+                                                        const int32_t* __restrict__ order,
+                                                        double* __restrict__ wsbase, int only) {
+  constexpr int T = NB * (NB + 1) / 2;
+  constexpr int KS = 4 * NB;        // k-steps of four landmarks
+  constexpr int LDX = 16 * NB + 2;  // row stride of the staged rows
+  __shared__ double X[16 * LDX];
+  const nyls_desc& d = desc[instance_of(order)];
+  if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m + 2) != NB) return;
+  const int m = d.m, n = d.n, g = m + 2;
+  const nyls_wsl L = nyls_layout(m, P, 0);
+  double* ws = wsbase + d.ws;
+  if (only && !((int)ws[L.info + 1] & only)) return;
+  if (!use_eigenbasis(ws, L, only)) return;  // k_gram64_mfma
+  const int lane = threadIdx.x;
+  const int ks_end = (m + 3) >> 2;
+
+  nyls_walk<NB, EX> wk;
+  wk.init(d, lane);
+  const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
+  const __amdgpu_buffer_rsrc_t fr = nyls_rsrc(d.f, P * n * 8), rr = nyls_rsrc(d.r, n * 8);
+  const double* U = ws + L.U;
+  double ub[NB][KS];
+#pragma unroll
+  for (int kb = 0; kb < NB; ++kb)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int s = 4 * ks + (lane >> 4), kk = 16 * kb + (lane & 15);
+      ub[kb][ks] = (s < m && kk < m) ? U[s * m + kk] : 0.0;
+    }
+  nyls_d4 acc[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = nyls_d4{0.0, 0.0, 0.0, 0.0};
+
+  double fj[P][4], rj[4];
+  auto load = [&](int i0, double (&f)[P][4], double (&r_)[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = i0 + 4 * j + wk.ph;
+#pragma unroll
+      for (int k = 0; k < P; ++k) f[k][j] = nyls_bload(fr, (k * n + i) * 8);
+      r_[j] = nyls_bload(rr, i * 8);
+    }
+  };
+  load(0, fj, rj);
+  for (int i0 = 0; i0 < n; i0 += 16) {
+    wk.advance(d, i0);
+    double fn[P][4], rn[4];
+    load(i0 + 16, fn, rn);
+    bool okj[4];
+    double q[NB];
+    wk.chunk(
+        d, i0,
+        [&](int b, int j, double z, double e) {
+          double h[P + 2];
+          nyls_hfac<P>(-2.0 * inv_sigma * z, inv_s2, h);
+          double poly = h[P];
+#pragma unroll
+          for (int k = 1; k <= P; ++k) poly -= fj[k - 1][j] * h[P - k];
+          q[b] = wk.lv[b] ? e * poly : 0.0;
+        },
+        [&](int j) {
+          const int i = i0 + 4 * j + wk.ph;
+          okj[j] = i < n && !nyls_is_condition_point(d, i);
+#pragma unroll
+          for (int b = 0; b < NB; ++b) X[(4 * j + wk.ph) * LDX + 16 * b + wk.sl] = okj[j] ? q[b] : 0.0;
+        });
+    nyls_wave_lds_sync();
+    nyls_d4 D[NB];
+#pragma unroll
+    for (int kb = 0; kb < NB; ++kb) D[kb] = nyls_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      if (ks < ks_end) {
+        const double a = X[(lane & 15) * LDX + 4 * ks + (lane >> 4)];
+#pragma unroll
+        for (int kb = 0; kb < NB; ++kb)
+          D[kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ub[kb][ks], D[kb], 0, 0, 0);
+      }
+    }
+    nyls_wave_lds_sync();
+    // columns m (c_i) and m + 1 (r_i); register v holds point 4 v + ph
+#pragma unroll
+    for (int kb = 0; kb < NB; ++kb) {
+      const int kk = 16 * kb + (lane & 15);
+      if (kk == m || kk == m + 1) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          D[kb][v] = okj[v] ? (kk == m ? -fj[P - 1][v] : rj[v]) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int t = 0;
+#pragma unroll
+      for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = I; J < NB; ++J) {
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[I][v], D[J][v], acc[t], 0, 0, 0);
+          ++t;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) fj[k][j] = fn[k][j];
+      rj[j] = rn[j];
+    }
+  }
+  double* out = ws + L.gram;
+  int t = 0;
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int J = I; J < NB; ++J) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = 16 * I + 4 * v + (lane >> 4), b = 16 * J + (lane & 15);
+        if (a < g && b < g) {
+          out[a * g + b] = acc[t][v];
+          if (I != J) out[b * g + a] = acc[t][v];
+        }
+      }
+      ++t;
+    }
+  if (lane == 0) ws[L.info + 4] = 1.0;
+}
+
 template <int NB, bool EX>
 void launch_mfma_nbx(const nyls_plan_view& pv, double* ws, hipStream_t st) {
   const dim3 grid(pv.batch), block(64);
+  if (pv.p_mask & 2) hipLaunchKernelGGL((k_gram64_rot_mfma<NB, 1, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
+  if (pv.p_mask & 4) hipLaunchKernelGGL((k_gram64_rot_mfma<NB, 2, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
+  if (pv.p_mask & 8) hipLaunchKernelGGL((k_gram64_rot_mfma<NB, 3, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
+  if (pv.p_mask & 16) hipLaunchKernelGGL((k_gram64_rot_mfma<NB, 4, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
+  if (pv.only) return;
   if (pv.p_mask & 2) hipLaunchKernelGGL((k_gram64_mfma<NB, 1, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
   if (pv.p_mask & 4) hipLaunchKernelGGL((k_gram64_mfma<NB, 2, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
   if (pv.p_mask & 8) hipLaunchKernelGGL((k_gram64_mfma<NB, 3, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
@@ -317,10 +465,8 @@ size_t nyls_gram64_lds_bytes(int maxm) {
 }
 
 hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t st) {
-  if (!pv.only) {
-    if (pv.gnb_mask & 4) launch_mfma_nb<2>(pv, ws, st);
-    if (pv.gnb_mask & 16) launch_mfma_nb<4>(pv, ws, st);
-  }
+  if (pv.gnb_mask & 4) launch_mfma_nb<2>(pv, ws, st);
+  if (pv.gnb_mask & 16) launch_mfma_nb<4>(pv, ws, st);
   const size_t lds = nyls_gram64_lds_bytes(pv.maxm);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
