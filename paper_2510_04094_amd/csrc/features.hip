@@ -2,6 +2,8 @@
 //   phi^(d)(t) = W^T k_m^(d)(t),   y_hat^(d)(t) = alpha^T k_m^(d)(t) + [d = 0] b.
 // Grid: (instance, tile of evaluation points).  A tile's kernel-derivative values are
 // built once in LDS and contracted with W (read from the workspace, L2-resident).
+#include <algorithm>
+
 #include "nyls_internal.h"
 
 namespace {
@@ -100,8 +102,9 @@ hipError_t nyls_launch_features(const nyls_plan_view& pv, const double* ws, cons
   const size_t lds = ((size_t)TE * (dmax + 1) * pv.maxm + NYLS_MAX_M) * sizeof(double);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_features),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  // grid-stride over each instance's points; max_eval only sizes the grid
-  int64_t gx = (max_eval + TE - 1) / TE;
+  // grid-stride over each instance's points; the grid is sized for about n evaluations
+  // per instance (max_eval caps it)
+  int64_t gx = (std::min<int64_t>(max_eval, pv.maxn) + TE - 1) / TE;
   gx = gx < 1 ? 1 : (gx > 64 ? 64 : gx);
   dim3 grid((unsigned)gx, single >= 0 ? 1 : pv.batch);
   hipLaunchKernelGGL(k_features, grid, dim3(NYLS_BLOCK), lds, st, pv.d_desc, ws, t_eval, eval_off,
@@ -112,8 +115,10 @@ hipError_t nyls_launch_features(const nyls_plan_view& pv, const double* ws, cons
 hipError_t nyls_launch_predict(const nyls_plan_view& pv, const double* ws, const double* t_eval,
                                const int64_t* eval_off, int d, double* out, int64_t max_eval,
                                hipStream_t st) {
+  // grid-stride over each instance's times: four one-wave blocks per instance (blocks past the
+  // instance's count exit at once); max_eval, when known, caps it lower
   int64_t gx = (max_eval + 63) / 64;
-  gx = gx < 1 ? 1 : (gx > 64 ? 64 : gx);
+  gx = gx < 1 ? 1 : (gx > 4 ? 4 : gx);
   dim3 grid((unsigned)gx, pv.batch);
   hipLaunchKernelGGL(k_predict, grid, dim3(64), 0, st, pv.d_desc, ws, t_eval, eval_off, d, out);
   return hipGetLastError();
