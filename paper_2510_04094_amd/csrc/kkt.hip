@@ -11,9 +11,68 @@
 // system is optionally written out, then LU-factorised with partial pivoting in LDS; the
 // factors stay in the workspace for refinement and the adjoint, and the solution x and
 // alpha = W omega are stored.
+//
+// Kernel-space Gram with m + 2 <= 64: the whole (omega, b) block and the right-hand side come
+// from one product K~ = W~^T S~ W~ on the matrix cores, with W~ = diag(W[:, :r], 1, 1)
+// zero-padded to 64 x 64: K~[:m+1, :m+1] is the (omega, b) block before scaling by gamma and
+// K~[:m+1, m+1] the right-hand side.  Wave J of the workgroup owns column block J: it forms
+// T = S~ W~[:, 16J:16J+16] with v_mfma_f64_16x16x4f64 and keeps it in its accumulators,
+// which are then exactly the B operands of W~^T T (register v of tile I holds rows
+// 16 I + 4 v + lane / 16), so T never leaves the registers.
 #include "nyls_dense.h"
 
 namespace {
+
+typedef double nyls_d4 __attribute__((ext_vector_type(4)));
+
+// W~[s][k] of the padded transform (see above).
+__device__ inline double wext(const double* W, int m, int r, int g, int s, int k) {
+  if (s < m) return (k < r) ? W[s * m + k] : 0.0;
+  return (s == k && s < g) ? 1.0 : 0.0;
+}
+
+// Writes gamma K~ (+ identity on the landmark diagonal) into K[a][b], a, b <= m, and
+// gamma K~[a][m + 1] into rhs[a], a <= m.  256 threads; wave J takes column block J.
+__device__ inline void kkt_transform_mfma(const double* __restrict__ S, const double* __restrict__ W,
+                                          int m, int r, double gam, double* K, int lda,
+                                          double* rhs) {
+  const int g = m + 2;
+  const int lane = threadIdx.x & 63, J = threadIdx.x >> 6;
+  if (16 * J >= g) return;
+  const int row = lane & 15, kq = lane >> 4;
+  nyls_d4 t[4];
+#pragma unroll
+  for (int I = 0; I < 4; ++I) t[I] = nyls_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) {
+    const int s = 4 * ks + kq;
+    const double bop = wext(W, m, r, g, s, 16 * J + row);
+#pragma unroll
+    for (int I = 0; I < 4; ++I) {
+      const int a = 16 * I + row;
+      const double aop = (a < g && s < g) ? S[a * g + s] : 0.0;
+      t[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, t[I], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int I = 0; I < 4; ++I) {
+    if (16 * I >= g) break;
+    nyls_d4 k4 = nyls_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const double aop = wext(W, m, r, g, 4 * ks + kq, 16 * I + row);
+      k4 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, t[ks >> 2][ks & 3], k4, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = 16 * I + 4 * v + kq, b = 16 * J + row;
+      if (a <= m) {
+        if (b <= m) K[a * lda + b] = gam * k4[v] + ((a == b && a < m) ? 1.0 : 0.0);
+        else if (b == m + 1) rhs[a] = gam * k4[v];
+      }
+    }
+  }
+}
 
 __device__ inline int instance_of(const int32_t* order) {
   return order ? order[blockIdx.x] : (int)blockIdx.x;
@@ -51,7 +110,9 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
   // (rows rotated by U^T) the transform is the diagonal Lambda^{-1/2}.
   const double* lamv = ws + L.lam;
   if (!eigbasis) eigbasis = ws[L.info + 4] != 0.0 ? 1 : 0;  // per-instance choice of the FP64 Gram
-  if (!eigbasis)
+  const bool mx = !eigbasis && g <= 64;  // (omega, b) block and rhs from the MFMA product
+  if (mx) kkt_transform_mfma(S, W, m, r, gam, K, lda, rhs);
+  else if (!eigbasis)
     for (int e = tid; e < m * m; e += NYLS_BLOCK) {
       const int a = e / m, k = e - a * m;
       double acc = 0.0;
@@ -71,6 +132,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
   __syncthreads();
   for (int e = tid; e < N * N; e += NYLS_BLOCK) {
     const int a = e / N, b = e - a * N;
+    if (mx && a <= m && b <= m) continue;
     double val = 0.0;
     if (a < m && b < m) {
       if (a < r && b < r) {
@@ -108,7 +170,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
     }
     K[a * lda + b] = val;
   }
-  for (int a = tid; a < N; a += NYLS_BLOCK) {
+  for (int a = (mx ? m + 1 : 0) + tid; a < N; a += NYLS_BLOCK) {
     double val;
     if (a < m) {
       double acc = 0.0;
