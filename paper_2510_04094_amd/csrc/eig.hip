@@ -201,6 +201,20 @@ constexpr int kQlMaxIter = 60;  // QL sweeps per eigenvalue
 
 __device__ inline double sel_lane(double x, int lane, int i, double v) { return lane == i ? v : x; }
 
+// 1/sqrt(x) for normal or subnormal x > 0: the hardware estimate followed by two Newton
+// steps y <- y (3 - x y^2) / 2 (each one roughly squares the relative error), so that the
+// rotation c = g y, s = f y (x = f^2 + g^2) has c^2 + s^2 = 1 to a few ulp.  The dependency
+// chain is far shorter than that of a square root followed by a division.
+__device__ inline double nyls_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double h = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, h, y);
+  }
+  return y;
+}
+
 __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ desc,
                                                const int32_t* __restrict__ order,
                                                double* __restrict__ wsbase, int single, int lda) {
@@ -212,8 +226,8 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
   const nyls_wsl L = nyls_layout(m, d.p, 0);
   double* ws = wsbase + d.ws;
   const int lane = threadIdx.x;
-  double* A = sm;                   // [kQlMaxM][lda]: K_mm, then Q, then Z
-  double* vv = A + kQlMaxM * lda;   // [64] reflector, broadcast copy
+  double* A = sm;                   // [lda][lda] (lda >= m): K_mm, then Q, then Z
+  double* vv = A + lda * lda;       // [64] reflector, broadcast copy
   double* tt = vv + 64;             // [64] column sums / sign / sorted eigenvalues
   double* tl = tt + 64;             // [64] landmark times
   int* pos = reinterpret_cast<int*>(tl + 64);  // [64] sorted position
@@ -222,7 +236,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
 
   const double inv_sigma = 1.0 / d.sigma;
   if (own) tl[lane] = nyls_grid_t(d, d.lidx[lane]);
-  __syncthreads();
+  nyls_wave_lds_sync();
   if (own) {
     const double ti = tl[lane];
     for (int j = 0; j < m; ++j) {
@@ -230,7 +244,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
       Ar[j] = exp(-z * z);
     }
   }
-  __syncthreads();
+  nyls_wave_lds_sync();
 
   double dl = 0.0, el = 0.0, bl = 0.0;  // d_lane, e_lane, beta_lane
   // 1. tridiagonalisation
@@ -243,7 +257,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
     if (!(sig2 - x1 * x1 > 0.0)) {  // already tridiagonal in this column: H_k = I
       el = sel_lane(el, lane, k, x1);
       if (act) Ar[k] = 0.0;
-      __syncthreads();
+      nyls_wave_lds_sync();
       continue;
     }
     const double alpha = x1 >= 0.0 ? -sqrt(sig2) : sqrt(sig2);
@@ -253,7 +267,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
     bl = sel_lane(bl, lane, k, beta);
     vv[lane] = v;
     if (act) Ar[k] = v;
-    __syncthreads();
+    nyls_wave_lds_sync();
     double pl = 0.0;
     if (act)
       for (int j = k + 1; j < m; ++j) pl += Ar[j] * vv[j];
@@ -262,10 +276,10 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
     const double w = pl - K * v;
     // w goes to row k right of the diagonal (never read again as matrix data)
     if (act) A[k * lda + lane] = w;
-    __syncthreads();
+    nyls_wave_lds_sync();
     if (act)
       for (int j = k + 1; j < m; ++j) Ar[j] -= v * A[k * lda + j] + w * vv[j];
-    __syncthreads();
+    nyls_wave_lds_sync();
   }
   {
     const double a22 = A[(m - 2) * lda + m - 2], a32 = A[(m - 1) * lda + m - 2],
@@ -275,27 +289,27 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
     dl = sel_lane(dl, lane, m - 1, a33);
     el = sel_lane(el, lane, m - 1, 0.0);
   }
-  __syncthreads();
+  nyls_wave_lds_sync();
 
   // 2. Q in place: the trailing 2 x 2 block starts as the identity
   if (own && lane >= m - 2) {
     Ar[m - 2] = lane == m - 2 ? 1.0 : 0.0;
     Ar[m - 1] = lane == m - 1 ? 1.0 : 0.0;
   }
-  __syncthreads();
+  nyls_wave_lds_sync();
   for (int k = m - 3; k >= 0; --k) {
     const bool act = own && lane > k;
     const double v = act ? Ar[k] : 0.0;
     const double beta = nyls_rdlane(bl, k);
     if (beta != 0.0) {
       vv[lane] = v;
-      __syncthreads();
+      nyls_wave_lds_sync();
       // t_j = sum_i v_i Q[i][j] (lane j owns column j)
       double t = 0.0;
       if (act)
         for (int i = k + 1; i < m; ++i) t += vv[i] * A[i * lda + lane];
       tt[lane] = beta * t;
-      __syncthreads();
+      nyls_wave_lds_sync();
       if (act)
         for (int j = k + 1; j < m; ++j) Ar[j] -= v * tt[j];
     }
@@ -303,7 +317,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
     if (lane == k)
       for (int j = k; j < m; ++j) Ar[j] = j == k ? 1.0 : 0.0;
     if (act) Ar[k] = 0.0;
-    __syncthreads();
+    nyls_wave_lds_sync();
   }
 
   // 3. implicit QL on (d, e), rotations accumulated into Z (rows in A)
@@ -328,23 +342,29 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
       double sn = 1.0, cs = 1.0, pp = 0.0;
       double carry = own ? Ar[mm] : 0.0;
       bool split = false;
+      // rotation i reads d_i, d_{i+1} and e_i, which no earlier rotation of this sweep has
+      // rewritten (rotation i rewrites d_{i+1} and e_{i+1}): read them from copies taken
+      // before the sweep, off the dependency chain of g, sn, cs
+      const double d0 = dl, e0 = el;
       for (int i = mm - 1; i >= l; --i) {
-        const double ei = nyls_rdlane(el, i);
+        const double ei = nyls_rdlane(e0, i);
+        const double di = nyls_rdlane(d0, i), di1 = nyls_rdlane(d0, i + 1);
         const double f = sn * ei, b = cs * ei;
-        r = sqrt(f * f + g * g);
-        el = sel_lane(el, lane, i + 1, r);
-        if (r == 0.0) {  // exact deflation: the chase stops here
-          dl = sel_lane(dl, lane, i + 1, nyls_rdlane(dl, i + 1) - pp);
+        const double x = f * f + g * g;
+        if (x == 0.0) {  // exact deflation: the chase stops here
+          el = sel_lane(el, lane, i + 1, 0.0);
+          dl = sel_lane(dl, lane, i + 1, di1 - pp);
           el = sel_lane(el, lane, mm, 0.0);
           if (own) Ar[i + 1] = carry;
           split = true;
           break;
         }
-        const double inv = 1.0 / r;
-        sn = f * inv;
-        cs = g * inv;
-        g = nyls_rdlane(dl, i + 1) - pp;
-        r = (nyls_rdlane(dl, i) - g) * sn + 2.0 * cs * b;
+        const double y = nyls_rsqrt(x);
+        el = sel_lane(el, lane, i + 1, x * y);
+        sn = f * y;
+        cs = g * y;
+        g = di1 - pp;
+        r = (di - g) * sn + 2.0 * cs * b;
         pp = sn * r;
         dl = sel_lane(dl, lane, i + 1, g + pp);
         g = cs * r - b;
@@ -361,7 +381,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
       el = sel_lane(el, lane, mm, 0.0);
     }
   }
-  __syncthreads();
+  nyls_wave_lds_sync();
 
   // 4. sort descending (ties by index), sign each eigenvector (largest |entry| positive,
   //    first on ties), cut-off, W = U_r Lambda_r^{-1/2}
@@ -383,7 +403,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
     vv[lane] = sg;
     tt[ps] = dl;  // sorted eigenvalues
   }
-  __syncthreads();
+  nyls_wave_lds_sync();
   const double lam1 = tt[0];
   int rank = 0;
   for (int k = 0; k < m; ++k) rank += (tt[k] > d.tau * lam1) ? 1 : 0;
@@ -420,7 +440,7 @@ hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hip
   if (pv.nb_mask & (4 | 16)) {  // some instance has m <= 64
     const int mq = pv.maxm < kQlMaxM ? pv.maxm : kQlMaxM;
     const int lda = mq | 1;
-    const size_t lds = (size_t)kQlMaxM * lda * sizeof(double) + 3 * 64 * sizeof(double) +
+    const size_t lds = (size_t)lda * lda * sizeof(double) + 3 * 64 * sizeof(double) +
                        64 * sizeof(int);
     hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_ql),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -13,6 +13,11 @@
 // operand layout of v_mfma_f64_16x16x4f64 with the four points of one j as the k dimension
 // (A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k), so every tile pair (I <= J) of the
 // Gram takes one FP64 MFMA per j: A = q[16 I + sl], B = q[16 J + sl], FP64 accumulation.
+// Only the ceil((m+2)/16) blocks that carry data get tiles, and when the last of them holds at
+// most four columns (m = 50: landmarks 48, 49, c_i, r_i) those columns are accumulated on the
+// VALU instead of a mostly-empty MFMA tile row: each column value is broadcast along its
+// 16-lane row (one DPP move) and multiplied into per-lane sums, which overlap with the
+// matrix-core work of the full blocks.
 //
 // k_gram64 (ill-conditioned K_mm: retained eigenvalues below 1e-9 lambda_1, or the FP64
 // re-solve of a mixed-precision instance): the rows are rotated by U^T first and the Gram is
@@ -197,6 +202,12 @@ __device__ inline bool use_eigenbasis(const double* ws, const nyls_wsl& L, int o
   return only || (rank > 0 && ws[L.lam + rank - 1] < kRotate * ws[L.lam]);
 }
 
+// Value of lane 16 (lane / 16) + T (the same column of this lane's point).
+template <int T>
+__device__ inline double row_bcast(double v) {
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + T, 0xf, 0xf, false);
+}
+
 template <int NB, int P, bool EX>
 __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict__ desc,
                                                     const int32_t* __restrict__ order,
@@ -209,6 +220,10 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
   double* ws = wsbase + d.ws;
   if (use_eigenbasis(ws, L, only)) return;  // k_gram64_rot_mfma
   const int lane = threadIdx.x;
+  // blocks with data; the last one goes to the VALU when it has at most four columns
+  const int nbu = (g + 15) >> 4;
+  const bool tl = nbu > 1 && g - 16 * (nbu - 1) <= 4;
+  const int nf = tl ? nbu - 1 : nbu;  // blocks on the matrix cores
 
   nyls_walk<NB, EX> wk;
   wk.init(d, lane);
@@ -224,6 +239,11 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
   nyls_d4 acc[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) acc[t] = nyls_d4{0.0, 0.0, 0.0, 0.0};
+  double tacc[NB][4];  // tail: sum_i q_i[16 b + sl] q_i[16 (nbu - 1) + c]
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) tacc[b][c] = 0.0;
 
   double fj[P][4], rj[4];
   auto load = [&](int i0, double (&f)[P][4], double (&r_)[4]) {
@@ -263,9 +283,24 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
           for (int I = 0; I < NB; ++I)
 #pragma unroll
             for (int J = I; J < NB; ++J) {
-              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(q[I], q[J], acc[t], 0, 0, 0);
+              if (J < nf) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(q[I], q[J], acc[t], 0, 0, 0);
               ++t;
             }
+          if (tl) {
+            double qt = 0.0;
+#pragma unroll
+            for (int b = 1; b < NB; ++b)
+              if (b == nbu - 1) qt = q[b];
+            const double c0 = row_bcast<0>(qt), c1 = row_bcast<1>(qt), c2 = row_bcast<2>(qt),
+                         c3 = row_bcast<3>(qt);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              tacc[b][0] += q[b] * c0;
+              tacc[b][1] += q[b] * c1;
+              tacc[b][2] += q[b] * c2;
+              tacc[b][3] += q[b] * c3;
+            }
+          }
         });
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -281,16 +316,33 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
   for (int I = 0; I < NB; ++I)
 #pragma unroll
     for (int J = I; J < NB; ++J) {
+      if (J < nf) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int a = 16 * I + 4 * v + (lane >> 4), b = 16 * J + (lane & 15);
-        if (a < g && b < g) {
-          out[a * g + b] = acc[t][v];
-          if (I != J) out[b * g + a] = acc[t][v];
+        for (int v = 0; v < 4; ++v) {
+          const int a = 16 * I + 4 * v + (lane >> 4), b = 16 * J + (lane & 15);
+          if (a < g && b < g) {
+            out[a * g + b] = acc[t][v];
+            if (I != J) out[b * g + a] = acc[t][v];
+          }
         }
       }
       ++t;
     }
+  if (tl) {
+    // fold the four phases (points); phase-0 lanes own row 16 b + sl.  Entries inside the
+    // tail block are written once per (row, column) by the lane of that row.
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double v = nyls_walk_fold(tacc[b][c]);
+        const int a = 16 * b + wk.sl, x = 16 * (nbu - 1) + c;
+        if (wk.ph == 0 && b < nbu && a < g && x < g) {
+          out[a * g + x] = v;
+          if (b < nbu - 1) out[x * g + a] = v;
+        }
+      }
+  }
   if (lane == 0) ws[L.info + 4] = 0.0;
 }
 

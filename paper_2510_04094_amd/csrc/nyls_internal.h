@@ -57,6 +57,16 @@ __host__ __device__ inline nyls_wsl nyls_layout(int m, int p, int n_newton) {
   return L;
 }
 
+// Exchange through LDS among the lanes of one wavefront (for kernels that run one
+// wavefront per workgroup).  The LDS operations of a wavefront execute in program
+// order, so only compiler reordering has to be prevented; a workgroup barrier would also
+// wait for the outstanding global loads of the next chunk.
+__device__ inline void nyls_wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Landmark time t_s and grid time t_i.
 __device__ inline double nyls_grid_t(const nyls_desc& d, int i) {
   return d.uniform ? __dadd_rn(d.t0, __dmul_rn((double)i, d.dt)) : d.t[i];

@@ -21,16 +21,6 @@
 
 constexpr int NYLS_WALK_PAD = 18;  // LDS row stride (doubles) of the reduction tile
 
-// Exchange through LDS among the lanes of one wavefront (every kernel using these helpers
-// runs one wavefront per workgroup).  The LDS operations of a wavefront execute in program
-// order, so only compiler reordering has to be prevented; a workgroup barrier would also
-// wait for the outstanding global loads of the next chunk.
-__device__ inline void nyls_wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Hermite factors h_q = (-1/sigma)^q H_q(z), q = 0..P, so that the q-th t-derivative of
 // K(t, t_s) is h_q e.  With g = -2 z / sigma: h_0 = 1, h_1 = g,
 // h_{q+1} = g h_q - (2 q / sigma^2) h_{q-1}.

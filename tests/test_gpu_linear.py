@@ -196,8 +196,19 @@ def test_mixed_without_refinement_is_worse(gpu_lib):
     assert e1 < e0
 
 
-def test_assemble_matches_oracle(gpu_lib):
-    insts = config1(4)
+ASSEMBLE_SETS = {
+    "first-order m=20": lambda: config1(4),
+    # second-order family, n = 2000: m + 2 spans one to four 16-column blocks, with the last
+    # block holding 1..4 columns (accumulated off the matrix cores) or more
+    **{"second-order m=%d" % m: (lambda m=m: [workloads.linear_second_order(i, n=2000, m=m)
+                                              for i in range(2)])
+       for m in (14, 15, 18, 31, 40, 46, 47, 48, 50, 62)},
+}
+
+
+@pytest.mark.parametrize("which", list(ASSEMBLE_SETS))
+def test_assemble_matches_oracle(gpu_lib, which):
+    insts = ASSEMBLE_SETS[which]()
     b = gpu_lib.Batch(insts, mode=gpu_lib.FP64)
     kkt, rhs = b.assemble()
     torch.cuda.synchronize()
@@ -216,8 +227,12 @@ def test_assemble_matches_oracle(gpu_lib):
             j = r + int(np.argmax(np.abs(ref["A"][k, r:])))
             sgn[k] = np.sign(sub[k, j]) * np.sign(ref["A"][k, j])
         sub = sub * sgn[:, None] * sgn[None, :]
-        np.testing.assert_allclose(sub, ref["A"], rtol=0, atol=1e-9 * np.max(np.abs(ref["A"])))
-        np.testing.assert_allclose(rhs[i, idx] * sgn, ref["rhs"], rtol=0, atol=1e-9 * np.max(np.abs(ref["rhs"])))
+        # the kernel-space Gram passes through W = U Lambda^{-1/2} twice: its rounding
+        # (eps |S|) reaches the system as eps lambda_1 / lambda_r of the largest entry
+        lam = np.sort(ref["lam"])[::-1]
+        bar = max(1e-9, 16 * np.finfo(float).eps * lam[0] / lam[r - 1])
+        np.testing.assert_allclose(sub, ref["A"], rtol=0, atol=bar * np.max(np.abs(ref["A"])))
+        np.testing.assert_allclose(rhs[i, idx] * sgn, ref["rhs"], rtol=0, atol=bar * np.max(np.abs(ref["rhs"])))
         # truncated directions are identity rows
         for k in range(r, m):
             assert a[k, k] == 1.0 and np.count_nonzero(a[k]) == 1
