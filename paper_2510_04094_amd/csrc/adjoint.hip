@@ -25,7 +25,7 @@
 // pair, p_i, d p_i / d sigma and k^(q)_i (q < p) from the Hermite factors, reduces their
 // dot products with alpha and beta over the landmarks, and keeps sum_i e_i p_i and
 // sum_i nu_i p_i in registers.  d/dsigma of the q-th kernel derivative h_q e is
-// -e (q h_q / sigma + z h_{q+1}) (h_q as in nyls_hfac, z = (t - t_s) / sigma).
+// -e (q h_q / sigma + z h_{q+1}) (h_q as in nyls_hfac, z = (t - t_s) / sigma = -sigma g / 2).
 #include "nyls_dense.h"
 #include "nyls_walk.h"
 
@@ -69,6 +69,8 @@ __global__ __launch_bounds__(64) void k_backward(
   wk.init(d, lane);
   const int sl = wk.sl, ph = wk.ph;
   const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
+  nyls_oppoly<P> op;
+  op.init(inv_s2);
   const __amdgpu_buffer_rsrc_t fr = nyls_rsrc(d.f, P * n * 8), rr = nyls_rsrc(d.r, n * 8);
 
   for (int s = lane; s < m; s += 64) tl[s] = nyls_grid_t(d, d.lidx[s]);
@@ -163,30 +165,33 @@ __global__ __launch_bounds__(64) void k_backward(
     double zacc[NB], sacc = 0.0;
 #pragma unroll
     for (int b = 0; b < NB; ++b) zacc[b] = 0.0;
-    double fj[P][4], cp = 0.0;
-    auto load = [&](int i0, double (&f)[P][4], double& c_) {
+    struct stage {
+      double f[P][4];
+      double c;
+    };
+    auto load = [&](int i0, stage& st) {
 #pragma unroll
       for (int k = 0; k < P; ++k)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) f[k][j] = nyls_bload(fr, (k * n + i0 + 4 * j + ph) * 8);
-      c_ = -nyls_bload(fr, ((P - 1) * n + i0 + (lane & 15)) * 8);
+        for (int j = 0; j < 4; ++j) st.f[k][j] = nyls_bload(fr, (k * n + i0 + 4 * j + ph) * 8);
+      st.c = -nyls_bload(fr, ((P - 1) * n + i0 + (lane & 15)) * 8);
     };
-    load(0, fj, cp);
-    for (int i0 = 0; i0 < n; i0 += 16) {
+    auto body = [&](int i0, const stage& st) {
       wk.advance(d, i0);
-      double fn[P][4], cpn;
-      load(i0 + 16, fn, cpn);
+      double cj[4][P];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double f[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) f[k] = st.f[k][j];
+        op.coef(f, cj[j]);
+      }
       double pe[NB][4];
       double acc = 0.0;
       wk.chunk(
           d, i0,
-          [&](int b, int j, double z, double e) {
-            double h[P + 2];
-            nyls_hfac<P>(-2.0 * inv_sigma * z, inv_s2, h);
-            double poly = h[P];
-#pragma unroll
-            for (int k = 1; k <= P; ++k) poly -= fj[k - 1][j] * h[P - k];
-            pe[b][j] = e * poly;
+          [&](int b, int j, double g, double e) {
+            pe[b][j] = e * nyls_horner<P>(g, cj[j]);
             acc += bev[b] * pe[b][j];
           },
           [&](int j) {
@@ -197,8 +202,8 @@ __global__ __launch_bounds__(64) void k_backward(
       nyls_walk_sum<1>(tile, lane, tot);
       const int ip = i0 + (lane & 15);
       const bool okp = ip < n && !nyls_is_condition_point(d, ip);
-      const double nu = okp ? tot[0] + cp * mub : 0.0;
-      if (lane < 16) sacc += cp * nu;
+      const double nu = okp ? tot[0] + st.c * mub : 0.0;
+      if (lane < 16) sacc += st.c * nu;
       const double w1[1] = {nu};
       double nj[1][4];
       nyls_walk_bcast<1>(w1, bc, lane, nj);
@@ -206,11 +211,15 @@ __global__ __launch_bounds__(64) void k_backward(
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int j = 0; j < 4; ++j) zacc[b] += nj[0][j] * pe[b][j];
-#pragma unroll
-      for (int k = 0; k < P; ++k)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) fj[k][j] = fn[k][j];
-      cp = cpn;
+    };
+    stage sa, sb;
+    load(0, sa);
+    for (int i0 = 0; i0 < n; i0 += 32) {
+      load(i0 + 16, sb);
+      body(i0, sa);
+      if (i0 + 16 >= n) break;
+      load(i0 + 32, sa);
+      body(i0 + 16, sb);
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -262,42 +271,43 @@ __global__ __launch_bounds__(64) void k_backward(
 #pragma unroll
   for (int b = 0; b < NB; ++b) aeacc[b] = anacc[b] = 0.0;
   {
-    double fj[P][4], rp = 0.0, cp = 0.0;
-    auto load = [&](int i0, double (&f)[P][4], double& r_, double& c_) {
+    struct stage {
+      double f[P][4];
+      double r, c;
+    };
+    auto load = [&](int i0, stage& st) {
 #pragma unroll
       for (int k = 0; k < P; ++k)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) f[k][j] = nyls_bload(fr, (k * n + i0 + 4 * j + ph) * 8);
+        for (int j = 0; j < 4; ++j) st.f[k][j] = nyls_bload(fr, (k * n + i0 + 4 * j + ph) * 8);
       const int ip = i0 + (lane & 15);
-      r_ = nyls_bload(rr, ip * 8);
-      c_ = -nyls_bload(fr, ((P - 1) * n + ip) * 8);
+      st.r = nyls_bload(rr, ip * 8);
+      st.c = -nyls_bload(fr, ((P - 1) * n + ip) * 8);
     };
-    load(0, fj, rp, cp);
-    for (int i0 = 0; i0 < n; i0 += 16) {
+    const double half_sigma = 0.5 * d.sigma;
+    auto body = [&](int i0, const stage& st) {
       wk.advance(d, i0);
-      double fn[P][4], rpn, cpn;
-      load(i0 + 16, fn, rpn, cpn);
       double pe[NB][4];
       double acc[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) acc[q] = 0.0;
       wk.chunk(
           d, i0,
-          [&](int b, int j, double z, double e) {
+          [&](int b, int j, double g, double e) {
             double h[P + 2];
-            nyls_hfac<P>(-2.0 * inv_sigma * z, inv_s2, h);
+            nyls_hfac<P>(g, inv_s2, h);
             // w_P = 1, w_q = -f_{P-q}:  poly = sum w_q h_q, sa = sum q w_q h_q,
-            // sb = sum w_q h_{q+1}
+            // sb = sum w_q h_{q+1};  z = (t - t_s) / sigma = -sigma g / 2
             double poly = h[P], sa = P * h[P], sb = h[P + 1];
 #pragma unroll
             for (int k = 1; k <= P; ++k) {
-              const double fk = fj[k - 1][j];
+              const double fk = st.f[k - 1][j];
               poly -= fk * h[P - k];
               sa -= (double)(P - k) * fk * h[P - k];
               sb -= fk * h[P - k + 1];
             }
             const double pv = e * poly;
-            const double dpv = -e * (inv_sigma * sa + z * sb);
+            const double dpv = -e * (inv_sigma * sa - half_sigma * g * sb);
             pe[b][j] = pv;
             acc[0] += alv[b] * pv;
             acc[1] += bev[b] * pv;
@@ -321,8 +331,8 @@ __global__ __launch_bounds__(64) void k_backward(
       nyls_walk_sum<Q>(tile, lane, tot);
       const int ip = i0 + (lane & 15);
       const bool okp = ip < n && !nyls_is_condition_point(d, ip);
-      const double ei = okp ? tot[0] + cp * bias - rp : 0.0;
-      const double nui = okp ? tot[1] + cp * mub : 0.0;
+      const double ei = okp ? tot[0] + st.c * bias - st.r : 0.0;
+      const double nui = okp ? tot[1] + st.c * mub : 0.0;
       if (lane < 16 && ip < n) {
         sne += nui * ei;
         t2 += ei * tot[3] + nui * tot[2];
@@ -347,12 +357,15 @@ __global__ __launch_bounds__(64) void k_backward(
           aeacc[b] += en[0][j] * pe[b][j];
           anacc[b] += en[1][j] * pe[b][j];
         }
-#pragma unroll
-      for (int k = 0; k < P; ++k)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) fj[k][j] = fn[k][j];
-      rp = rpn;
-      cp = cpn;
+    };
+    stage sa, sb;
+    load(0, sa);
+    for (int i0 = 0; i0 < n; i0 += 32) {
+      load(i0 + 16, sb);
+      body(i0, sa);
+      if (i0 + 16 >= n) break;
+      load(i0 + 32, sa);
+      body(i0 + 16, sb);
     }
   }
 #pragma unroll

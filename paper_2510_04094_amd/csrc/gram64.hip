@@ -245,32 +245,36 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
 #pragma unroll
     for (int c = 0; c < 4; ++c) tacc[b][c] = 0.0;
 
-  double fj[P][4], rj[4];
-  auto load = [&](int i0, double (&f)[P][4], double (&r_)[4]) {
+  nyls_oppoly<P> op;
+  op.init(inv_s2);
+  struct stage {
+    double f[P][4], r[4];
+  };
+  auto load = [&](int i0, stage& st) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int i = i0 + 4 * j + wk.ph;
 #pragma unroll
-      for (int k = 0; k < P; ++k) f[k][j] = nyls_bload(fr, (k * n + i) * 8);
-      r_[j] = nyls_bload(rr, i * 8);
+      for (int k = 0; k < P; ++k) st.f[k][j] = nyls_bload(fr, (k * n + i) * 8);
+      st.r[j] = nyls_bload(rr, i * 8);
     }
   };
-  load(0, fj, rj);
-  for (int i0 = 0; i0 < n; i0 += 16) {
+  auto body = [&](int i0, const stage& st) {
     wk.advance(d, i0);
-    double fn[P][4], rn[4];
-    load(i0 + 16, fn, rn);
+    double cj[4][P];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double f[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) f[k] = st.f[k][j];
+      op.coef(f, cj[j]);
+    }
     double q[NB];
     wk.chunk(
         d, i0,
-        [&](int b, int j, double z, double e) {
-          double h[P + 2];
-          nyls_hfac<P>(-2.0 * inv_sigma * z, inv_s2, h);
-          double poly = h[P];
-#pragma unroll
-          for (int k = 1; k <= P; ++k) poly -= fj[k - 1][j] * h[P - k];
-          const double v = kind[b] == 0 ? e * poly
-                                         : (kind[b] == 1 ? -fj[P - 1][j] : (kind[b] == 2 ? rj[j] : 0.0));
+        [&](int b, int j, double g, double e) {
+          const double v = kind[b] == 0 ? e * nyls_horner<P>(g, cj[j])
+                                         : (kind[b] == 1 ? -st.f[P - 1][j] : (kind[b] == 2 ? st.r[j] : 0.0));
           q[b] = v;
         },
         [&](int j) {
@@ -302,12 +306,15 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
             }
           }
         });
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-#pragma unroll
-      for (int k = 0; k < P; ++k) fj[k][j] = fn[k][j];
-      rj[j] = rn[j];
-    }
+  };
+  stage sa, sb;
+  load(0, sa);
+  for (int i0 = 0; i0 < n; i0 += 32) {
+    load(i0 + 16, sb);
+    body(i0, sa);
+    if (i0 + 16 >= n) break;
+    load(i0 + 32, sa);
+    body(i0 + 16, sb);
   }
   // tile (I, J): register v of lane l holds row 16 I + 4 v + l / 16, column 16 J + l % 16
   double* out = ws + L.gram;
@@ -406,9 +413,9 @@ __global__ __launch_bounds__(64) void k_gram64_rot_mfma(const nyls_desc* __restr
     double q[NB];
     wk.chunk(
         d, i0,
-        [&](int b, int j, double z, double e) {
+        [&](int b, int j, double g, double e) {
           double h[P + 2];
-          nyls_hfac<P>(-2.0 * inv_sigma * z, inv_s2, h);
+          nyls_hfac<P>(g, inv_s2, h);
           double poly = h[P];
 #pragma unroll
           for (int k = 1; k <= P; ++k) poly -= fj[k - 1][j] * h[P - k];

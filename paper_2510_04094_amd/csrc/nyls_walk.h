@@ -15,7 +15,9 @@
 // Kernel values: on a uniform grid t_i - t_s = k dt with k = i - i_s.  Along one lane's
 // points k advances by 4, so with a = dt / sigma
 //     e(k + 4) = e(k) R(k),  R(k) = exp(-a^2 (8 k + 16)),  R(k + 4) = R(k) exp(-32 a^2),
-// restarted with two exponentials every 64 points (runs of 16 values per lane).
+// restarted with two exponentials every 64 points (runs of 16 values per lane).  Next to e
+// the walk carries g = -2 (t_i - t_s) / sigma^2, the first Hermite factor, which also
+// advances by a constant.
 #pragma once
 #include "nyls_internal.h"
 
@@ -32,15 +34,59 @@ __device__ inline void nyls_hfac(double g, double inv_s2, double (&h)[P + 2]) {
   for (int q = 1; q <= P; ++q) h[q + 1] = g * h[q] - (2.0 * q * inv_s2) * h[q - 1];
 }
 
+// The same factors as polynomials in g, h_q = sum_k H[q][k] g^k (H[q][k] = 0 unless q - k is
+// even), and the operator polynomial of one point,
+//     h_P(g) - sum_{i=1..P} f_i h_{P-i}(g) = g^P + sum_{k<P} c_k g^k,
+// so that p_i = e * poly(g) costs P multiply-adds per (point, landmark) pair (Horner).
+template <int P>
+struct nyls_oppoly {
+  double H[P + 1][P + 1];
+
+  __device__ void init(double inv_s2) {
+#pragma unroll
+    for (int q = 0; q <= P; ++q)
+#pragma unroll
+      for (int k = 0; k <= P; ++k) H[q][k] = 0.0;
+    H[0][0] = 1.0;
+    if (P >= 1) H[1][1] = 1.0;
+#pragma unroll
+    for (int q = 1; q < P; ++q)
+#pragma unroll
+      for (int k = 0; k <= q + 1; ++k)
+        if (((q + 1 - k) & 1) == 0)
+          H[q + 1][k] = (k >= 1 ? H[q][k - 1] : 0.0) - (k <= q - 1 ? 2.0 * q * inv_s2 * H[q - 1][k] : 0.0);
+  }
+
+  // coefficients c_0 .. c_{P-1} for the operator weights f_1 .. f_P of one point
+  __device__ void coef(const double (&f)[P], double (&c)[P]) const {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      double v = (((P - k) & 1) == 0) ? H[P][k] : 0.0;
+#pragma unroll
+      for (int i = 1; i <= P; ++i)
+        if (k <= P - i && ((P - i - k) & 1) == 0) v -= f[i - 1] * H[P - i][k];
+      c[k] = v;
+    }
+  }
+};
+
+template <int P>
+__device__ inline double nyls_horner(double g, const double (&c)[P]) {
+  double v = g + c[P - 1];
+#pragma unroll
+  for (int k = P - 2; k >= 0; --k) v = fma(v, g, c[k]);
+  return v;
+}
+
 // EX = false: only for instances with nyls_desc::rec == 1 (no exact-exponential path).
 template <int NB, bool EX>
 struct nyls_walk {
   int sl, ph, n;
   bool lv[NB];
   int ls[NB];
-  double ev[NB], rv[NB], zc[NB];
+  double ev[NB], rv[NB], gc[NB];
   bool exact;  // wave-uniform: this run of 64 points uses one exponential per value
-  double a4, q4, inv_sigma, a;
+  double ga4, q4, inv_sigma, a, gk;  // gk: g per grid step k
   __amdgpu_buffer_rsrc_t tr;  // grid times (non-uniform grids)
 
   __device__ void init(const nyls_desc& d, int lane) {
@@ -49,7 +95,8 @@ struct nyls_walk {
     n = d.n;
     inv_sigma = 1.0 / d.sigma;
     a = d.dt * inv_sigma;
-    a4 = 4.0 * a;
+    gk = -2.0 * inv_sigma * a;
+    ga4 = 4.0 * gk;
     q4 = exp(-32.0 * a * a);
     exact = EX && !d.uniform;
     tr = nyls_rsrc(EX && !d.uniform ? d.t : nullptr, EX && !d.uniform ? n * 8 : 0);
@@ -58,7 +105,7 @@ struct nyls_walk {
       const int s = 16 * b + sl;
       lv[b] = s < d.m;
       ls[b] = lv[b] ? d.lidx[s] : 0;
-      ev[b] = rv[b] = zc[b] = 0.0;
+      ev[b] = rv[b] = gc[b] = 0.0;
     }
   }
 
@@ -83,16 +130,16 @@ struct nyls_walk {
           ev[b] = far ? 0.0 : e0;
           rv[b] = far ? 0.0 : r0;
         }
-        zc[b] = (double)k0 * a;
+        gc[b] = (double)k0 * gk;
       }
       if (EX) exact = __ballot(any) != 0;
     }
   }
 
-  // Calls emit(b, j, z, e) for every landmark slot b < NB and point j < 4 of the chunk at
-  // i0: z = (t_i - t_s) / sigma and e = exp(-z^2) for i = i0 + 4 j + ph, then done(j) once
-  // all slots of point j were emitted.  Past the end of the grid the values are
-  // meaningless (but finite); callers ignore them.
+  // Calls emit(b, j, g, e) for every landmark slot b < NB and point j < 4 of the chunk at
+  // i0: g = -2 (t_i - t_s) / sigma^2 and e = exp(-((t_i - t_s) / sigma)^2) for
+  // i = i0 + 4 j + ph, then done(j) once all slots of point j were emitted.  Past the end of
+  // the grid the values are meaningless (but finite); callers ignore them.
   template <class Emit, class Done>
   __device__ void chunk(const nyls_desc& d, int i0, Emit emit, Done done) {
     if (!EX || !exact) {
@@ -100,10 +147,10 @@ struct nyls_walk {
       for (int j = 0; j < 4; ++j) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          emit(b, j, zc[b], ev[b]);
+          emit(b, j, gc[b], ev[b]);
           ev[b] *= rv[b];
           rv[b] *= q4;
-          zc[b] += a4;
+          gc[b] += ga4;
         }
         done(j);
       }
@@ -116,7 +163,7 @@ struct nyls_walk {
         for (int b = 0; b < NB; ++b) {
           const double z = d.uniform ? (double)(i - ls[b]) * a
                                      : (ti - nyls_grid_t(d, ls[b])) * inv_sigma;
-          emit(b, j, z, exp(-z * z));
+          emit(b, j, -2.0 * inv_sigma * z, exp(-z * z));
         }
         done(j);
       }

@@ -76,42 +76,48 @@ __global__ __launch_bounds__(64) void k_points(
   // One pass over the grid.  Always writes y_hat for the current (alpha, b); when refining
   // also forms rho_i = r_i - p_i^T alpha - c_i b and accumulates sum_i rho_i p_i (zacc, per
   // landmark slot and phase) and sum_i c_i rho_i (sacc, lanes 0..15).
+  nyls_oppoly<P> op;
+  op.init(inv_s2);
+  // operator data of a lane's points (f), of the point it finishes (r, c) and the previous
+  // pass's y_hat of that point, loaded one chunk ahead into alternating stages
+  struct stage {
+    double f[P][4];
+    double r, c, y;
+  };
   auto pass = [&](auto REF, double b, double (&zacc)[NB], double& sacc, double& ymax,
                   bool track, double& dmax) {
     constexpr bool refining = decltype(REF)::value;
     constexpr int Q = refining ? 2 : 1;
-    // operator data of this lane's points (and of the point it finishes), and the previous
-    // pass's y_hat of that point, one chunk ahead
-    double fj[P][4], rp = 0.0, cp = 0.0, yp = 0.0;
-    auto load = [&](int i0, double (&f)[P][4], double& r_, double& c_, double& y_) {
+    auto load = [&](int i0, stage& st) {
       const int ip = i0 + (lane & 15);
       if (refining) {
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) f[k][j] = nyls_bload(fr, (k * n + i0 + 4 * j + wk.ph) * 8);
-        r_ = nyls_bload(rr, ip * 8);
-        c_ = -nyls_bload(fr, ((P - 1) * n + ip) * 8);
+          for (int j = 0; j < 4; ++j) st.f[k][j] = nyls_bload(fr, (k * n + i0 + 4 * j + wk.ph) * 8);
+        st.r = nyls_bload(rr, ip * 8);
+        st.c = -nyls_bload(fr, ((P - 1) * n + ip) * 8);
       }
-      y_ = track ? nyls_bload(yr, ip * 8) : 0.0;
+      st.y = track ? nyls_bload(yr, ip * 8) : 0.0;
     };
-    load(0, fj, rp, cp, yp);
-    for (int i0 = 0; i0 < n; i0 += 16) {
+    auto body = [&](int i0, const stage& st) {
       wk.advance(d, i0);
-      double fn[P][4], rpn = 0.0, cpn = 0.0, ypn = 0.0;
-      load(i0 + 16, fn, rpn, cpn, ypn);
+      double cj[4][P];
+      if (refining)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          double f[P];
+#pragma unroll
+          for (int k = 0; k < P; ++k) f[k] = st.f[k][j];
+          op.coef(f, cj[j]);
+        }
       double pe[refining ? NB : 1][4];
       double acc0 = 0.0, acc1 = 0.0;
       wk.chunk(
           d, i0,
-          [&](int bb, int j, double z, double e) {
+          [&](int bb, int j, double g, double e) {
             if (refining) {
-              double h[P + 2];
-              nyls_hfac<P>(-2.0 * inv_sigma * z, inv_s2, h);
-              double poly = h[P];
-#pragma unroll
-              for (int k = 1; k <= P; ++k) poly -= fj[k - 1][j] * h[P - k];
-              const double pv = e * poly;
+              const double pv = e * nyls_horner<P>(g, cj[j]);
               pe[refining ? bb : 0][j] = pv;
               acc1 += alv[bb] * pv;
             }
@@ -128,15 +134,15 @@ __global__ __launch_bounds__(64) void k_points(
       const double yv = tot[0] + b;
       if (ip < n) {
         if (lane < 16) {
-          if (track) dmax = fmax(dmax, fabs(yv - yp));
+          if (track) dmax = fmax(dmax, fabs(yv - st.y));
           yo[ip] = yv;
         }
         ymax = fmax(ymax, fabs(yv));
       }
       if (refining) {
         const bool okp = ip < n && !nyls_is_condition_point(d, ip);
-        const double rho = okp ? rp - tot[Q - 1] - cp * b : 0.0;
-        if (lane < 16) sacc += cp * rho;
+        const double rho = okp ? st.r - tot[Q - 1] - st.c * b : 0.0;
+        if (lane < 16) sacc += st.c * rho;
         const double w1[1] = {rho};
         double rj[1][4];
         nyls_walk_bcast<1>(w1, bc, lane, rj);
@@ -145,13 +151,15 @@ __global__ __launch_bounds__(64) void k_points(
 #pragma unroll
           for (int j = 0; j < 4; ++j) zacc[bb] += rj[0][j] * pe[refining ? bb : 0][j];
       }
-#pragma unroll
-      for (int k = 0; k < P; ++k)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) fj[k][j] = fn[k][j];
-      rp = rpn;
-      cp = cpn;
-      yp = ypn;
+    };
+    stage sa, sb;
+    load(0, sa);
+    for (int i0 = 0; i0 < n; i0 += 32) {
+      load(i0 + 16, sb);
+      body(i0, sa);
+      if (i0 + 16 >= n) break;
+      load(i0 + 32, sa);
+      body(i0 + 16, sb);
     }
   };
 
