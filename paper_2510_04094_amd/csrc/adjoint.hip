@@ -287,6 +287,16 @@ __global__ __launch_bounds__(64) void k_backward(
     const double half_sigma = 0.5 * d.sigma;
     auto body = [&](int i0, const stage& st) {
       wk.advance(d, i0);
+      // per point: p_i = e poly(g), d p_i / d sigma = e (sigma / 2) D(g)
+      double cj[4][P], dj[4][P + 2];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double f[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) f[k] = st.f[k][j];
+        op.coef(f, cj[j]);
+        op.dcoef(f, dj[j]);
+      }
       double pe[NB][4];
       double acc[Q];
 #pragma unroll
@@ -295,19 +305,9 @@ __global__ __launch_bounds__(64) void k_backward(
           d, i0,
           [&](int b, int j, double g, double e) {
             double h[P + 2];
-            nyls_hfac<P>(g, inv_s2, h);
-            // w_P = 1, w_q = -f_{P-q}:  poly = sum w_q h_q, sa = sum q w_q h_q,
-            // sb = sum w_q h_{q+1};  z = (t - t_s) / sigma = -sigma g / 2
-            double poly = h[P], sa = P * h[P], sb = h[P + 1];
-#pragma unroll
-            for (int k = 1; k <= P; ++k) {
-              const double fk = st.f[k - 1][j];
-              poly -= fk * h[P - k];
-              sa -= (double)(P - k) * fk * h[P - k];
-              sb -= fk * h[P - k + 1];
-            }
-            const double pv = e * poly;
-            const double dpv = -e * (inv_sigma * sa - half_sigma * g * sb);
+            nyls_hfac<P>(g, inv_s2, h);  // only h_q, q < P, are used
+            const double pv = e * nyls_horner<P>(g, cj[j]);
+            const double dpv = e * nyls_horner<P + 2>(g, dj[j]);  // without the sigma / 2
             pe[b][j] = pv;
             acc[0] += alv[b] * pv;
             acc[1] += bev[b] * pv;
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(64) void k_backward(
       const double nui = okp ? tot[1] + st.c * mub : 0.0;
       if (lane < 16 && ip < n) {
         sne += nui * ei;
-        t2 += ei * tot[3] + nui * tot[2];
+        t2 += half_sigma * (ei * tot[3] + nui * tot[2]);
         if (dl_dr) dl_dr[d.goff + ip] = gam * nui;
         if (dl_df) {
 #pragma unroll

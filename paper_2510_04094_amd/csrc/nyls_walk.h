@@ -40,21 +40,42 @@ __device__ inline void nyls_hfac(double g, double inv_s2, double (&h)[P + 2]) {
 // so that p_i = e * poly(g) costs P multiply-adds per (point, landmark) pair (Horner).
 template <int P>
 struct nyls_oppoly {
-  double H[P + 1][P + 1];
+  double H[P + 2][P + 2];
+  double s2;
 
   __device__ void init(double inv_s2) {
+    s2 = inv_s2;
 #pragma unroll
-    for (int q = 0; q <= P; ++q)
+    for (int q = 0; q <= P + 1; ++q)
 #pragma unroll
-      for (int k = 0; k <= P; ++k) H[q][k] = 0.0;
+      for (int k = 0; k <= P + 1; ++k) H[q][k] = 0.0;
     H[0][0] = 1.0;
-    if (P >= 1) H[1][1] = 1.0;
+    H[1][1] = 1.0;
 #pragma unroll
-    for (int q = 1; q < P; ++q)
+    for (int q = 1; q <= P; ++q)
 #pragma unroll
       for (int k = 0; k <= q + 1; ++k)
         if (((q + 1 - k) & 1) == 0)
           H[q + 1][k] = (k >= 1 ? H[q][k - 1] : 0.0) - (k <= q - 1 ? 2.0 * q * inv_s2 * H[q - 1][k] : 0.0);
+  }
+
+  // Monic D(g) of degree P + 2 with d/dsigma of p_i = e * (sigma / 2) * D(g):
+  // with z = -sigma g / 2, -(sa / sigma + z sb) = (sigma / 2) (g sb(g) - 2 s2 sa(g)),
+  // sa = sum_q q w_q h_q and sb = sum_q w_q h_{q+1} (w_P = 1, w_q = -f_{P-q}).  Returns the
+  // coefficients d_0 .. d_{P+1} for the operator weights f_1 .. f_P of one point.
+  __device__ void dcoef(const double (&f)[P], double (&c)[P + 2]) const {
+#pragma unroll
+    for (int k = 0; k <= P + 1; ++k) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q <= P; ++q) {
+        if (((q - k) & 1) != 0) continue;  // both terms vanish unless q - k is even
+        const double e_qk = (k >= 1 && k - 1 <= q + 1 ? H[q + 1][k - 1] : 0.0) -
+                            (q > 0 && k <= q ? 2.0 * q * s2 * H[q][k] : 0.0);
+        v += (q == P ? 1.0 : -f[P - q - 1]) * e_qk;
+      }
+      c[k] = v;
+    }
   }
 
   // coefficients c_0 .. c_{P-1} for the operator weights f_1 .. f_P of one point
@@ -70,11 +91,12 @@ struct nyls_oppoly {
   }
 };
 
-template <int P>
-__device__ inline double nyls_horner(double g, const double (&c)[P]) {
-  double v = g + c[P - 1];
+// Monic polynomial g^D + sum_{k<D} c_k g^k by Horner's rule (D multiply-adds).
+template <int D>
+__device__ inline double nyls_horner(double g, const double (&c)[D]) {
+  double v = g + c[D - 1];
 #pragma unroll
-  for (int k = P - 2; k >= 0; --k) v = fma(v, g, c[k]);
+  for (int k = D - 2; k >= 0; --k) v = fma(v, g, c[k]);
   return v;
 }
 
