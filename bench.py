@@ -33,8 +33,8 @@ TRAFFIC = {
     "backward": {
         "sources": ["paper_2510_04094_amd/csrc/adjoint.hip", "paper_2510_04094_amd/csrc/nyls_walk.h",
                     "paper_2510_04094_amd/csrc/nyls_dense.h", "paper_2510_04094_amd/csrc/nyls_internal.h"],
-        "sha1": "74c4000bd0ea8fde624cf7269cd31cd921e75263",
-        "kib": {"mixed": (2075531.7, 1119736.4), "fp64": (1908495.0, 1118782.2)},
+        "sha1": "6c50049794f42f1e6ba0d1617b1d764baea81b0c",
+        "kib": {"mixed": (1976115.3, 1119602.0), "fp64": (1618526.9, 1119589.6)},
         "scale": (2.0, 1.0),
     },
 }
@@ -213,7 +213,7 @@ def main():
     ap.add_argument("--modes", default="fp64,mixed")
     ap.add_argument("--check", type=int, default=64, help="instances verified against the oracle")
     ap.add_argument("--plain", type=int, default=32, help="instances for the plain FP64 comparator")
-    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle instances timed (0: 4 per core)")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle instances timed (0: 12 per core)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (HBM counter calibration)")
@@ -310,7 +310,7 @@ def main():
                                            "instances": args.plain, "note": "forward only"}
     if not args.no_cpu:
         cores = host_cores()
-        count = args.cpu_sample or 4 * cores
+        count = args.cpu_sample or 12 * cores
         t0 = time.perf_counter()
         times = pool_map(_oracle_job, [(i, args.n, args.m, seed_config) for i in range(count)], cores)
         wall = time.perf_counter() - t0
