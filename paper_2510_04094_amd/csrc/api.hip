@@ -22,6 +22,8 @@ struct nyls_plan {
   unsigned rec_mask = 0;
   unsigned nb_mask = 0;
   unsigned gnb_mask = 0;
+  unsigned tl_mask = 0;
+  unsigned ntl_mask = 0;
   nyls_desc* d_desc = nullptr;
   int32_t* d_lidx = nullptr;
   int32_t* d_order = nullptr;
@@ -80,6 +82,8 @@ nyls_plan_view view(const nyls_plan* pl) {
   v.rec_mask = pl->rec_mask;
   v.nb_mask = pl->nb_mask;
   v.gnb_mask = pl->gnb_mask;
+  v.tl_mask = pl->tl_mask;
+  v.ntl_mask = pl->ntl_mask;
   v.only = 0;
   return v;
 }
@@ -179,6 +183,8 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
     pl->rec_mask |= 1u << d.rec;
     pl->nb_mask |= 1u << nyls_slot_blocks(q.m);
     pl->gnb_mask |= 1u << nyls_slot_blocks(q.m + 2);
+    if (d.rec == 1 && nyls_walk_tail(q.m) != 0) pl->tl_mask |= 1u << nyls_slot_blocks(q.m);
+    else pl->ntl_mask |= 1u << nyls_slot_blocks(q.m);
     pl->maxm = std::max(pl->maxm, q.m);
     pl->maxp = std::max(pl->maxp, q.p);
     pl->maxn = std::max(pl->maxn, q.n);

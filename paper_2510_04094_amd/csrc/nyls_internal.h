@@ -236,6 +236,15 @@ enum { NYLS_K_EIG = 0, NYLS_K_GRAM64, NYLS_K_GRAM32, NYLS_K_KKT, NYLS_K_POINTS, 
 // 16-landmark slot blocks per lane of the one-wave passes for an instance with m landmarks.
 __host__ __device__ inline int nyls_slot_blocks(int m) { return m <= 32 ? 2 : (m <= 64 ? 4 : 8); }
 
+// Landmarks in the last 16-slot block when there are at most four of them (m = 16 (NB - 1)
+// + 1 .. 4, NB = nyls_slot_blocks(m) > 1), else 0.  On instances with rec == 1 the one-wave
+// passes walk such a block in a tail layout (one (point, landmark) pair per lane and chunk)
+// instead of pair by pair, where it would cost a quarter of the work for a few landmarks.
+__host__ __device__ inline int nyls_walk_tail(int m) {
+  const int nb = nyls_slot_blocks(m), t = m - 16 * (nb - 1);
+  return (nb > 1 && t >= 1 && t <= 4) ? t : 0;
+}
+
 // Host launchers (defined in the .hip files; all enqueue on `stream`).
 struct nyls_plan_view {
   int32_t batch, mode, maxm, maxp, maxn;
@@ -250,6 +259,8 @@ struct nyls_plan_view {
   const int32_t* d_order;   // instance order, most expensive first
   int64_t total;
   unsigned nt_mask;         // bit t set when some instance has ceil((m+2)/16) == t
+  unsigned tl_mask;         // bit b: some rec == 1 instance of slot class b walks a tail layout
+  unsigned ntl_mask;        // bit b: some instance of slot class b does not
 };
 
 // `single` >= 0 restricts a launch to that one instance (one workgroup).

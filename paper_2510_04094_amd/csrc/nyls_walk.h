@@ -101,8 +101,16 @@ __device__ inline double nyls_horner(double g, const double (&c)[D]) {
 }
 
 // EX = false: only for instances with nyls_desc::rec == 1 (no exact-exponential path).
-template <int NB, bool EX>
+// TL: the last block holds nyls_walk_tail(m) landmarks and is walked in the tail layout:
+// lane = 4 pt + ts takes tail slot ts (landmark 16 (NB - 1) + ts, used when below m) for the
+// single chunk point i0 + pt, 16 points further each chunk:
+//     e(k + 16) = e(k) R16(k),  R16(k) = exp(-a^2 (32 k + 256)),  R16(k + 16) = R16(k) exp(-512 a^2),
+// restarted with the other runs every 64 points.  The per-lane arrays keep all NB blocks (the
+// landmark data of the last block stays usable in the block layout).
+template <int NB, bool EX, bool TL = false>
 struct nyls_walk {
+  static_assert(!(TL && EX), "the tail layout is for instances with rec == 1");
+  static constexpr int NM = TL ? NB - 1 : NB;  // blocks walked pair by pair
   int sl, ph, n;
   bool lv[NB];
   int ls[NB];
@@ -110,6 +118,9 @@ struct nyls_walk {
   bool exact;  // wave-uniform: this run of 64 points uses one exponential per value
   double ga4, q4, inv_sigma, a, gk;  // gk: g per grid step k
   __amdgpu_buffer_rsrc_t tr;  // grid times (non-uniform grids)
+  int tpt, tts, tls;          // tail layout: chunk point, tail slot, landmark grid index
+  bool tlv;
+  double te, tr16, tg, q16, g16;
 
   __device__ void init(const nyls_desc& d, int lane) {
     sl = lane & 15;
@@ -129,6 +140,13 @@ struct nyls_walk {
       ls[b] = lv[b] ? d.lidx[s] : 0;
       ev[b] = rv[b] = gc[b] = 0.0;
     }
+    tpt = lane >> 2;
+    tts = lane & 3;
+    tlv = TL && 16 * (NB - 1) + tts < d.m;
+    tls = tlv ? d.lidx[16 * (NB - 1) + tts] : 0;
+    q16 = TL ? exp(-512.0 * a * a) : 0.0;
+    g16 = 16.0 * gk;
+    te = tr16 = tg = 0.0;
   }
 
   // Must be called before chunk(i0) for every chunk, in increasing order from i0 = 0:
@@ -137,8 +155,19 @@ struct nyls_walk {
   __device__ void advance(const nyls_desc& d, int i0) {
     if ((!EX || d.uniform) && (i0 & 63) == 0) {
       bool any = false;
+      if (TL) {
+        // a tail run holds four values: z falls by at most 48 a <= 12 along it, so a run
+        // starting below exp(-700) while approaching stays below exp(-200) and is set to zero
+        const int k0 = i0 + tpt - tls;
+        const double z0 = (double)k0 * a;
+        const bool far = k0 < 0 && z0 * z0 > 700.0;
+        const double e0 = exp(-z0 * z0), r0 = exp(-a * a * (32.0 * k0 + 256.0));
+        te = far ? 0.0 : e0;
+        tr16 = far ? 0.0 : r0;
+        tg = (double)k0 * gk;
+      }
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
+      for (int b = 0; b < NM; ++b) {
         const int k0 = i0 + ph - ls[b];
         if (EX) {
           any |= nyls_gauss_start(k0, 16, 4, a, ev[b], rv[b]);
@@ -162,19 +191,27 @@ struct nyls_walk {
   // i0: g = -2 (t_i - t_s) / sigma^2 and e = exp(-((t_i - t_s) / sigma)^2) for
   // i = i0 + 4 j + ph, then done(j) once all slots of point j were emitted.  Past the end of
   // the grid the values are meaningless (but finite); callers ignore them.
-  template <class Emit, class Done>
-  __device__ void chunk(const nyls_desc& d, int i0, Emit emit, Done done) {
+  // With TL, blocks b < NB - 1 are emitted this way and tail(g, e) is called once for the
+  // lane's tail pair (point i0 + tpt, landmark 16 (NB - 1) + tts).
+  template <class Emit, class Done, class Tail>
+  __device__ void chunk(const nyls_desc& d, int i0, Emit emit, Done done, Tail tail) {
     if (!EX || !exact) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
+        for (int b = 0; b < NM; ++b) {
           emit(b, j, gc[b], ev[b]);
           ev[b] *= rv[b];
           rv[b] *= q4;
           gc[b] += ga4;
         }
         done(j);
+      }
+      if (TL) {
+        tail(tg, te);
+        te *= tr16;
+        tr16 *= q16;
+        tg += g16;
       }
     } else {
 #pragma unroll
@@ -190,6 +227,12 @@ struct nyls_walk {
         done(j);
       }
     }
+  }
+
+  template <class Emit, class Done>
+  __device__ void chunk(const nyls_desc& d, int i0, Emit emit, Done done) {
+    static_assert(!TL, "the tail layout needs a tail callback");
+    chunk(d, i0, emit, done, [](double, double) {});
   }
 };
 
@@ -235,6 +278,26 @@ __device__ inline void nyls_walk_sum(const double* tile, int lane, double (&out)
   nyls_wave_lds_sync();
 }
 
+// Tail layout: lane 4 pt + ts stores its tail pair's term of quantity q (ttile: LDS,
+// Q * 64 doubles); nyls_walk_sum_tail adds the four tail slots of each point to the sums.
+__device__ inline void nyls_walk_put_tail(double* ttile, int lane, int q, double v) {
+  ttile[q * 64 + lane] = v;
+}
+
+template <int Q>
+__device__ inline void nyls_walk_sum_tail(const double* tile, const double* ttile, int lane,
+                                          double (&out)[Q]) {
+  nyls_wave_lds_sync();
+  const int pt = lane & 15, qq = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const double* row = tile + (q * 16 + pt) * NYLS_WALK_PAD + 4 * qq;
+    const double s = ((row[0] + row[1]) + (row[2] + row[3])) + ttile[q * 64 + 4 * pt + qq];
+    out[q] = nyls_add_xor32(nyls_add_xor16(s));
+  }
+  nyls_wave_lds_sync();
+}
+
 // Per-point values w[q] held by lanes 0..15 (for chunk point lane) are returned in every lane
 // for its own points: out[q][j] = w[q] of point 4 j + ph.  buf: LDS, Q * 16 doubles.
 template <int Q>
@@ -250,6 +313,31 @@ __device__ inline void nyls_walk_bcast(const double (&w)[Q], double* buf, int la
 #pragma unroll
     for (int j = 0; j < 4; ++j) out[q][j] = buf[q * 16 + ph * 4 + j];
   nyls_wave_lds_sync();
+}
+
+// The same, also returning in tout[q] the value of the lane's tail point (chunk point lane / 4).
+template <int Q>
+__device__ inline void nyls_walk_bcast_tail(const double (&w)[Q], double* buf, int lane,
+                                            double (&out)[Q][4], double (&tout)[Q]) {
+  if (lane < 16)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) buf[q * 16 + (lane & 3) * 4 + (lane >> 2)] = w[q];
+  nyls_wave_lds_sync();
+  const int ph = lane >> 4, tp = lane >> 2;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[q][j] = buf[q * 16 + ph * 4 + j];
+    tout[q] = buf[q * 16 + (tp & 3) * 4 + (tp >> 2)];
+  }
+  nyls_wave_lds_sync();
+}
+
+// Sum of v over the 16 lanes with the same tail slot (lane & 3); every lane gets its slot's sum.
+__device__ inline double nyls_tail_fold(double v) {
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 8);
+  return nyls_add_xor32(nyls_add_xor16(v));
 }
 
 // Sum of v over the four phases (lanes sl, sl + 16, sl + 32, sl + 48).

@@ -31,7 +31,7 @@ __device__ inline int instance_of(const int32_t* order, int single) {
   return single >= 0 ? single : (order ? order[blockIdx.x] : (int)blockIdx.x);
 }
 
-template <int NB, int P, bool EX>
+template <int NB, int P, bool EX, bool TL>
 __global__ __launch_bounds__(64) void k_points(
     const nyls_desc* __restrict__ desc, const int32_t* __restrict__ order,
     double* __restrict__ wsbase, int refine, double* __restrict__ yhat,
@@ -39,13 +39,15 @@ __global__ __launch_bounds__(64) void k_points(
     int32_t* __restrict__ status, int maxm, int single, double tol_stop, double tol_flag,
     int only) {
   __shared__ __align__(16) double tile[2 * 16 * NYLS_WALK_PAD];
+  __shared__ double ttile[TL ? 2 * 64 : 1];
   __shared__ double bc[16];
   __shared__ double Rv[NK], xv[NK], zs[NYLS_MAX_M];
   __shared__ int piv[NK];
 
   const int inst = instance_of(order, single);
   const nyls_desc& d = desc[inst];
-  if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB)
+  if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB ||
+      (!EX && nyls_walk_tail(d.m) != 0) != TL)
     return;  // another launch handles this instance
   if (only && !((int)wsbase[d.ws + nyls_layout(d.m, P, 0).info + 1] & only)) return;
   const int m = d.m, n = d.n;
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(64) void k_points(
   const double gam = d.gamma;
   double* yo = yhat + d.goff;
 
-  nyls_walk<NB, EX> wk;
+  nyls_walk<NB, EX, TL> wk;
   wk.init(d, lane);
   const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
   const __amdgpu_buffer_rsrc_t fr = nyls_rsrc(d.f, P * n * 8), rr = nyls_rsrc(d.r, n * 8);
@@ -67,6 +69,8 @@ __global__ __launch_bounds__(64) void k_points(
   double alv[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) alv[b] = wk.lv[b] ? ws[L.alpha + 16 * b + wk.sl] : 0.0;
+  const int st_ = 16 * (NB - 1) + wk.tts;  // tail layout: this lane's tail landmark
+  double alt = wk.tlv ? ws[L.alpha + st_] : 0.0;
   for (int e = lane; e < N; e += 64) {
     xv[e] = ws[L.x + e];
     piv[e] = (int)ws[L.piv + e];
@@ -75,17 +79,18 @@ __global__ __launch_bounds__(64) void k_points(
 
   // One pass over the grid.  Always writes y_hat for the current (alpha, b); when refining
   // also forms rho_i = r_i - p_i^T alpha - c_i b and accumulates sum_i rho_i p_i (zacc, per
-  // landmark slot and phase) and sum_i c_i rho_i (sacc, lanes 0..15).
+  // landmark slot and phase; zt for the lane's tail slot) and sum_i c_i rho_i (sacc, lanes
+  // 0..15).
   nyls_oppoly<P> op;
   op.init(inv_s2);
   // operator data of a lane's points (f), of the point it finishes (r, c) and the previous
   // pass's y_hat of that point, loaded one chunk ahead into alternating stages
   struct stage {
-    double f[P][4];
+    double f[P][4], ft[P];  // ft: operator data of the tail point (tail layout)
     double r, c, y;
   };
-  auto pass = [&](auto REF, double b, double (&zacc)[NB], double& sacc, double& ymax,
-                  bool track, double& dmax) {
+  auto pass = [&](auto REF, double b, double (&zacc)[NB], double& zt, double& sacc,
+                  double& ymax, bool track, double& dmax) {
     constexpr bool refining = decltype(REF)::value;
     constexpr int Q = refining ? 2 : 1;
     auto load = [&](int i0, stage& st) {
@@ -97,6 +102,9 @@ __global__ __launch_bounds__(64) void k_points(
           for (int j = 0; j < 4; ++j) st.f[k][j] = nyls_bload(fr, (k * n + i0 + 4 * j + wk.ph) * 8);
         st.r = nyls_bload(rr, ip * 8);
         st.c = -nyls_bload(fr, ((P - 1) * n + ip) * 8);
+        if (TL)
+#pragma unroll
+          for (int k = 0; k < P; ++k) st.ft[k] = nyls_bload(fr, (k * n + i0 + wk.tpt) * 8);
       }
       st.y = track ? nyls_bload(yr, ip * 8) : 0.0;
     };
@@ -112,7 +120,7 @@ __global__ __launch_bounds__(64) void k_points(
           op.coef(f, cj[j]);
         }
       double pe[refining ? NB : 1][4];
-      double acc0 = 0.0, acc1 = 0.0;
+      double acc0 = 0.0, acc1 = 0.0, pvt = 0.0;
       wk.chunk(
           d, i0,
           [&](int bb, int j, double g, double e) {
@@ -127,9 +135,19 @@ __global__ __launch_bounds__(64) void k_points(
             nyls_walk_put(tile, lane, 0, j, acc0);
             if (refining) nyls_walk_put(tile, lane, 1, j, acc1);
             acc0 = acc1 = 0.0;
+          },
+          [&](double g, double e) {
+            if (refining) {
+              double ct[P];
+              op.coef(st.ft, ct);
+              pvt = e * nyls_horner<P>(g, ct);
+              nyls_walk_put_tail(ttile, lane, 1, alt * pvt);
+            }
+            nyls_walk_put_tail(ttile, lane, 0, alt * e);
           });
       double tot[Q];
-      nyls_walk_sum<Q>(tile, lane, tot);
+      if (TL) nyls_walk_sum_tail<Q>(tile, ttile, lane, tot);
+      else nyls_walk_sum<Q>(tile, lane, tot);
       const int ip = i0 + (lane & 15);
       const double yv = tot[0] + b;
       if (ip < n) {
@@ -144,10 +162,15 @@ __global__ __launch_bounds__(64) void k_points(
         const double rho = okp ? st.r - tot[Q - 1] - st.c * b : 0.0;
         if (lane < 16) sacc += st.c * rho;
         const double w1[1] = {rho};
-        double rj[1][4];
-        nyls_walk_bcast<1>(w1, bc, lane, rj);
+        double rj[1][4], rt[1];
+        if (TL) {
+          nyls_walk_bcast_tail<1>(w1, bc, lane, rj, rt);
+          zt += rt[0] * pvt;
+        } else {
+          nyls_walk_bcast<1>(w1, bc, lane, rj);
+        }
 #pragma unroll
-        for (int bb = 0; bb < NB; ++bb)
+        for (int bb = 0; bb < wk.NM; ++bb)
 #pragma unroll
           for (int j = 0; j < 4; ++j) zacc[bb] += rj[0][j] * pe[refining ? bb : 0][j];
       }
@@ -176,11 +199,11 @@ __global__ __launch_bounds__(64) void k_points(
   bool need_output = true;
   int passes = 0;
   for (int step = 0; step < refine; ++step) {
-    double zacc[NB], sacc = 0.0, dmax = 0.0;
+    double zacc[NB], zt = 0.0, sacc = 0.0, dmax = 0.0;
     ymax = 0.0;
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb) zacc[bb] = 0.0;
-    pass(std::true_type{}, xv[m], zacc, sacc, ymax, step > 0, dmax);
+    pass(std::true_type{}, xv[m], zacc, zt, sacc, ymax, step > 0, dmax);
     ++passes;
     ymax = nyls_wave_max(ymax);
     if (step > 0) {
@@ -193,9 +216,13 @@ __global__ __launch_bounds__(64) void k_points(
       }
     }
 #pragma unroll
-    for (int bb = 0; bb < NB; ++bb) {
-      const double zt = nyls_walk_fold(zacc[bb]);
-      if (wk.ph == 0 && wk.lv[bb]) zs[16 * bb + wk.sl] = zt;
+    for (int bb = 0; bb < wk.NM; ++bb) {
+      const double zb = nyls_walk_fold(zacc[bb]);
+      if (wk.ph == 0 && wk.lv[bb]) zs[16 * bb + wk.sl] = zb;
+    }
+    if (TL) {
+      const double ztot = nyls_tail_fold(zt);
+      if (lane < 4 && wk.tlv) zs[st_] = ztot;
     }
     const double ssum = nyls_wave_sum(sacc);
     __syncthreads();
@@ -231,6 +258,11 @@ __global__ __launch_bounds__(64) void k_points(
         alv[bb] = acc;
       }
     }
+    if (TL && wk.tlv) {
+      double acc = 0.0;
+      for (int k = 0; k < r; ++k) acc += W[st_ * m + k] * xv[k];
+      alt = acc;
+    }
     double dsq = 0.0;
     for (int k = lane; k < r; k += 64) dsq += Rv[k] * Rv[k];
     const double bound = sqrt(nyls_wave_sum(dsq)) + fabs(Rv[m]);
@@ -241,9 +273,9 @@ __global__ __launch_bounds__(64) void k_points(
     }
   }
   if (need_output) {
-    double zacc[NB], sacc = 0.0, dmax = 0.0;
+    double zacc[NB], zt = 0.0, sacc = 0.0, dmax = 0.0;
     ymax = 0.0;
-    pass(std::false_type{}, xv[m], zacc, sacc, ymax, refine > 0, dmax);
+    pass(std::false_type{}, xv[m], zacc, zt, sacc, ymax, refine > 0, dmax);
     ymax = nyls_wave_max(ymax);
     corr = nyls_wave_max(dmax);
   }
@@ -269,22 +301,22 @@ __global__ __launch_bounds__(64) void k_points(
   }
 }
 
-template <int NB, bool EX>
+template <int NB, bool EX, bool TL>
 void launch_nbx(const nyls_plan_view& pv, double* ws, int refine, double* yhat, double* omega,
                 double* bias, double* lambda, int32_t* status, int single, double ts, double tf,
                 hipStream_t st) {
   const dim3 grid(single >= 0 ? 1 : pv.batch);
   if (pv.p_mask & 2)
-    hipLaunchKernelGGL((k_points<NB, 1, EX>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
+    hipLaunchKernelGGL((k_points<NB, 1, EX, TL>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
                        refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf, pv.only);
   if (pv.p_mask & 4)
-    hipLaunchKernelGGL((k_points<NB, 2, EX>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
+    hipLaunchKernelGGL((k_points<NB, 2, EX, TL>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
                        refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf, pv.only);
   if (pv.p_mask & 8)
-    hipLaunchKernelGGL((k_points<NB, 3, EX>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
+    hipLaunchKernelGGL((k_points<NB, 3, EX, TL>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
                        refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf, pv.only);
   if (pv.p_mask & 16)
-    hipLaunchKernelGGL((k_points<NB, 4, EX>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
+    hipLaunchKernelGGL((k_points<NB, 4, EX, TL>), grid, dim3(64), 0, st, pv.d_desc, pv.d_order, ws,
                        refine, yhat, omega, bias, lambda, status, pv.maxm, single, ts, tf, pv.only);
 }
 
@@ -296,10 +328,12 @@ hipError_t launch_nb(const nyls_plan_view& pv, double* ws, int refine, double* y
   // level: the adjoint's residual terms (dl/dgamma) need the forward solution to FP64
   // accuracy, whatever precision the factorisation had.
   const double ts = 1e-11, tf = 1e-8;
-  if (pv.rec_mask & 2)
-    launch_nbx<NB, false>(pv, ws, refine, yhat, omega, bias, lambda, status, single, ts, tf, st);
+  if ((pv.rec_mask & 2) && (pv.ntl_mask & (1u << NB)))
+    launch_nbx<NB, false, false>(pv, ws, refine, yhat, omega, bias, lambda, status, single, ts, tf, st);
+  if (pv.tl_mask & (1u << NB))
+    launch_nbx<NB, false, true>(pv, ws, refine, yhat, omega, bias, lambda, status, single, ts, tf, st);
   if (pv.rec_mask & 1)
-    launch_nbx<NB, true>(pv, ws, refine, yhat, omega, bias, lambda, status, single, ts, tf, st);
+    launch_nbx<NB, true, false>(pv, ws, refine, yhat, omega, bias, lambda, status, single, ts, tf, st);
   return hipGetLastError();
 }
 
