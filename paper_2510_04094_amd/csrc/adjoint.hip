@@ -41,12 +41,29 @@ __global__ __launch_bounds__(64) void k_backward(
   constexpr int ML = 16 * NB;   // landmark slots
   constexpr int Q = 4 + 2 * P;  // dot products per point in the gradient pass
   constexpr int NKL = ML + 1 + P;
-  __shared__ __align__(16) double tile[Q * 16 * NYLS_WALK_PAD];
+  // LDS: the gradient pass's reduction tile (Q quantities x 16 points) shares its space with
+  // the small per-instance vectors, which the mu refinement uses next to tile rows 0..15
+  // (one quantity) and which are parked in the workspace while the gradient pass runs.  This
+  // keeps the workgroup under a quarter of the 160 KiB of LDS per compute unit, so LDS does
+  // not limit the number of resident wavefronts below what the registers allow.
+  constexpr int TILE = Q * 16 * NYLS_WALK_PAD;
+  constexpr int VOFF = 16 * NYLS_WALK_PAD;
+  constexpr int VLEN = 6 * ML + P * ML + 4 * NKL;
+  __shared__ __align__(16) double lds[TILE > VOFF + VLEN ? TILE : VOFF + VLEN];
   __shared__ double bc[2 * 16];
-  __shared__ double tl[ML], kb[ML], ae[ML], an[ML], ug1[ML], ug2[ML];
-  __shared__ double hk[P][ML];
-  __shared__ double xv[NKL], mu[NKL], R[NKL], xb[NKL];
   __shared__ int piv[NKL];
+  double* const tile = lds;
+  double* const tl = lds + VOFF;
+  double* const kb = tl + ML;
+  double* const ae = kb + ML;
+  double* const an = ae + ML;
+  double* const ug1 = an + ML;
+  double* const ug2 = ug1 + ML;
+  double* const hkv = ug2 + ML;  // hkv[j * ML + s] = hkv[j * ML + s]
+  double* const xv = hkv + P * ML;
+  double* const mu = xv + NKL;
+  double* const R = mu + NKL;
+  double* const xb = R + NKL;
 
   const int inst = order ? order[blockIdx.x] : (int)blockIdx.x;
   const nyls_desc& d = desc[inst];
@@ -122,7 +139,7 @@ __global__ __launch_bounds__(64) void k_backward(
 #pragma unroll
     for (int q = 0; q < P; ++q)
       if (q == d.cond_d[j]) hv = h[q];
-    hk[j][s] = hv * exp(-z * z);
+    hkv[j * ML + s] = hv * exp(-z * z);
   }
   __syncthreads();
 
@@ -266,6 +283,14 @@ __global__ __launch_bounds__(64) void k_backward(
   }
   const double mub = mu[m];
 
+  // park kb, hk and mu in the workspace (x stays there) while the tile covers them
+  for (int s = lane; s < m; s += 64) {
+    ws[L.beta + s] = kb[s];
+    for (int j = 0; j < P; ++j) ws[L.acc + j * m + s] = hkv[j * ML + s];
+  }
+  for (int a = lane; a < N; a += 64) ws[L.mu + a] = mu[a];
+  __syncthreads();
+
   // 3. gradient pass
   double aeacc[NB], anacc[NB], sne = 0.0, t2 = 0.0;
 #pragma unroll
@@ -287,16 +312,9 @@ __global__ __launch_bounds__(64) void k_backward(
     const double half_sigma = 0.5 * d.sigma;
     auto body = [&](int i0, const stage& st) {
       wk.advance(d, i0);
-      // per point: p_i = e poly(g), d p_i / d sigma = e (sigma / 2) D(g)
-      double cj[4][P], dj[4][P + 2];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        double f[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) f[k] = st.f[k][j];
-        op.coef(f, cj[j]);
-        op.dcoef(f, dj[j]);
-      }
+      // per point: p_i = e poly(g), d p_i / d sigma = e (sigma / 2) D(g); the coefficients
+      // of point j are formed when its first slot is emitted (one point's set is live)
+      double cj[P], dj[P + 2];
       double pe[NB][4];
       double acc[Q];
 #pragma unroll
@@ -304,10 +322,17 @@ __global__ __launch_bounds__(64) void k_backward(
       wk.chunk(
           d, i0,
           [&](int b, int j, double g, double e) {
+            if (b == 0) {
+              double f[P];
+#pragma unroll
+              for (int k = 0; k < P; ++k) f[k] = st.f[k][j];
+              op.coef(f, cj);
+              op.dcoef(f, dj);
+            }
             double h[P + 2];
             nyls_hfac<P>(g, inv_s2, h);  // only h_q, q < P, are used
-            const double pv = e * nyls_horner<P>(g, cj[j]);
-            const double dpv = e * nyls_horner<P + 2>(g, dj[j]);  // without the sigma / 2
+            const double pv = e * nyls_horner<P>(g, cj);
+            const double dpv = e * nyls_horner<P + 2>(g, dj);  // without the sigma / 2
             pe[b][j] = pv;
             acc[0] += alv[b] * pv;
             acc[1] += bev[b] * pv;
@@ -379,6 +404,16 @@ __global__ __launch_bounds__(64) void k_backward(
   const double sum_nu_e = nyls_wave_sum(sne);
   t2 = nyls_wave_sum(t2);
   __syncthreads();
+  for (int s = lane; s < m; s += 64) {
+    tl[s] = nyls_grid_t(d, d.lidx[s]);
+    kb[s] = ws[L.beta + s];
+    for (int j = 0; j < P; ++j) hkv[j * ML + s] = ws[L.acc + j * m + s];
+  }
+  for (int a = lane; a < N; a += 64) {
+    xv[a] = ws[L.x + a];
+    mu[a] = ws[L.mu + a];
+  }
+  __syncthreads();
 
   // 4. sigma: condition-row term (phase-0 lanes own the landmarks), then the K_mm term
   double t3 = 0.0;
@@ -405,8 +440,8 @@ __global__ __launch_bounds__(64) void k_backward(
   for (int s = lane; s < m; s += 64) {
     double g1 = kb[s] - gam * an[s], g2 = gam * ae[s];
     for (int j = 0; j < P; ++j) {
-      g1 -= hk[j][s] * mu[m + 1 + j];
-      g2 += hk[j][s] * xv[m + 1 + j];
+      g1 -= hkv[j * ML + s] * mu[m + 1 + j];
+      g2 += hkv[j * ML + s] * xv[m + 1 + j];
     }
     kb[s] = g1;
     ae[s] = g2;
