@@ -84,6 +84,8 @@ __global__ __launch_bounds__(64) void k_backward(
 
   nyls_walk<NB, EX> wk;
   wk.init(d, lane);
+  nyls_cpts cpt;
+  cpt.init(d);
   const int sl = wk.sl, ph = wk.ph;
   const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
   nyls_oppoly<P> op;
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(64) void k_backward(
       double tot[1];
       nyls_walk_sum<1>(tile, lane, tot);
       const int ip = i0 + (lane & 15);
-      const bool okp = ip < n && !nyls_is_condition_point(d, ip);
+      const bool okp = ip < n && !cpt.has(ip);
       const double nu = okp ? tot[0] + st.c * mub : 0.0;
       if (lane < 16) sacc += st.c * nu;
       const double w1[1] = {nu};
@@ -355,7 +357,7 @@ __global__ __launch_bounds__(64) void k_backward(
       double tot[Q];
       nyls_walk_sum<Q>(tile, lane, tot);
       const int ip = i0 + (lane & 15);
-      const bool okp = ip < n && !nyls_is_condition_point(d, ip);
+      const bool okp = ip < n && !cpt.has(ip);
       const double ei = okp ? tot[0] + st.c * bias - st.r : 0.0;
       const double nui = okp ? tot[1] + st.c * mub : 0.0;
       if (lane < 16 && ip < n) {

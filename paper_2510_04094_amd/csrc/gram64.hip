@@ -227,6 +227,8 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
 
   nyls_walk<NB, EX> wk;
   wk.init(d, lane);
+  nyls_cpts cpt;
+  cpt.init(d);
   const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
   const __amdgpu_buffer_rsrc_t fr = nyls_rsrc(d.f, P * n * 8), rr = nyls_rsrc(d.r, n * 8);
   // what this lane's slot b carries: 0 landmark, 1 c_i, 2 r_i, 3 nothing
@@ -273,13 +275,16 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
     wk.chunk(
         d, i0,
         [&](int b, int j, double g, double e) {
-          const double v = kind[b] == 0 ? e * nyls_horner<P>(g, cj[j])
-                                         : (kind[b] == 1 ? -st.f[P - 1][j] : (kind[b] == 2 ? st.r[j] : 0.0));
-          q[b] = v;
+          const double pv = e * nyls_horner<P>(g, cj[j]);
+          // blocks entirely below m hold landmarks only (wave-uniform test)
+          q[b] = 16 * b + 16 <= m ? pv
+                                  : (kind[b] == 0 ? pv
+                                                  : (kind[b] == 1 ? -st.f[P - 1][j]
+                                                                  : (kind[b] == 2 ? st.r[j] : 0.0)));
         },
         [&](int j) {
           const int i = i0 + 4 * j + wk.ph;
-          const bool ok = i < n && !nyls_is_condition_point(d, i);
+          const bool ok = i < n && !cpt.has(i);
 #pragma unroll
           for (int b = 0; b < NB; ++b) q[b] = ok ? q[b] : 0.0;
           int t = 0;
@@ -379,6 +384,8 @@ __global__ __launch_bounds__(64) void k_gram64_rot_mfma(const nyls_desc* __restr
 
   nyls_walk<NB, EX> wk;
   wk.init(d, lane);
+  nyls_cpts cpt;
+  cpt.init(d);
   const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
   const __amdgpu_buffer_rsrc_t fr = nyls_rsrc(d.f, P * n * 8), rr = nyls_rsrc(d.r, n * 8);
   const double* U = ws + L.U;
@@ -423,7 +430,7 @@ __global__ __launch_bounds__(64) void k_gram64_rot_mfma(const nyls_desc* __restr
         },
         [&](int j) {
           const int i = i0 + 4 * j + wk.ph;
-          okj[j] = i < n && !nyls_is_condition_point(d, i);
+          okj[j] = i < n && !cpt.has(i);
 #pragma unroll
           for (int b = 0; b < NB; ++b) X[(4 * j + wk.ph) * LDX + 16 * b + wk.sl] = okj[j] ? q[b] : 0.0;
         });

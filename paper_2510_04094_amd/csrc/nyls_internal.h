@@ -72,6 +72,23 @@ __device__ inline double nyls_grid_t(const nyls_desc& d, int i) {
   return d.uniform ? __dadd_rn(d.t0, __dmul_rn((double)i, d.dt)) : d.t[i];
 }
 
+// The condition points of an instance held in (scalar) registers for the per-point passes,
+// which skip them in the residual set: read once instead of at every point.
+struct nyls_cpts {
+  int c[NYLS_MAX_P];
+  __device__ void init(const nyls_desc& d) {
+#pragma unroll
+    for (int j = 0; j < NYLS_MAX_P; ++j)
+      c[j] = __builtin_amdgcn_readfirstlane(j < d.p ? d.cond_i[j] : -1);
+  }
+  __device__ bool has(int i) const {
+    bool r = false;
+#pragma unroll
+    for (int j = 0; j < NYLS_MAX_P; ++j) r |= (c[j] == i);
+    return r;
+  }
+};
+
 __device__ inline bool nyls_is_condition_point(const nyls_desc& d, int i) {
   bool c = false;
   for (int j = 0; j < d.p; ++j) c |= (d.cond_i[j] == i);

@@ -63,6 +63,8 @@ __global__ __launch_bounds__(64) void k_points(
 
   nyls_walk<NB, EX, TL> wk;
   wk.init(d, lane);
+  nyls_cpts cpt;
+  cpt.init(d);
   const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
   const __amdgpu_buffer_rsrc_t fr = nyls_rsrc(d.f, P * n * 8), rr = nyls_rsrc(d.r, n * 8);
   const __amdgpu_buffer_rsrc_t yr = nyls_rsrc(yhat + d.goff, n * 8);
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(64) void k_points(
         ymax = fmax(ymax, fabs(yv));
       }
       if (refining) {
-        const bool okp = ip < n && !nyls_is_condition_point(d, ip);
+        const bool okp = ip < n && !cpt.has(ip);
         const double rho = okp ? st.r - tot[Q - 1] - st.c * b : 0.0;
         if (lane < 16) sacc += st.c * rho;
         const double w1[1] = {rho};
