@@ -22,6 +22,7 @@ struct nyls_plan {
   unsigned rec_mask = 0;
   unsigned nb_mask = 0;
   unsigned gnb_mask = 0;
+  unsigned gcls_mask = 0;
   unsigned tl_mask = 0;
   unsigned ntl_mask = 0;
   nyls_desc* d_desc = nullptr;
@@ -82,6 +83,7 @@ nyls_plan_view view(const nyls_plan* pl) {
   v.rec_mask = pl->rec_mask;
   v.nb_mask = pl->nb_mask;
   v.gnb_mask = pl->gnb_mask;
+  v.gcls_mask = pl->gcls_mask;
   v.tl_mask = pl->tl_mask;
   v.ntl_mask = pl->ntl_mask;
   v.only = 0;
@@ -183,6 +185,7 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
     pl->rec_mask |= 1u << d.rec;
     pl->nb_mask |= 1u << nyls_slot_blocks(q.m);
     pl->gnb_mask |= 1u << nyls_slot_blocks(q.m + 2);
+    if (q.m + 2 <= 64) pl->gcls_mask |= 1u << nyls_gram_class(q.m);
     if (d.rec == 1 && nyls_walk_tail(q.m) != 0) pl->tl_mask |= 1u << nyls_slot_blocks(q.m);
     else pl->ntl_mask |= 1u << nyls_slot_blocks(q.m);
     pl->maxm = std::max(pl->maxm, q.m);

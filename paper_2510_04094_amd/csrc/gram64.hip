@@ -27,6 +27,8 @@
 // group partials summed in a fixed order.
 #include "nyls_walk.h"
 
+#include <type_traits>
+
 namespace {
 
 constexpr int TP = 64;      // points per tile
@@ -208,22 +210,23 @@ __device__ inline double row_bcast(double v) {
   return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + T, 0xf, 0xf, false);
 }
 
-template <int NB, int P, bool EX>
-__global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict__ desc,
+// NB = ceil((m + 2) / 16) column blocks with data; TLG: the last holds at most four columns
+// and is accumulated on the VALU (nyls_gram_class).
+template <int NB, int P, bool EX, bool TLG>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_gram64_mfma(const nyls_desc* __restrict__ desc,
                                                     const int32_t* __restrict__ order,
                                                     double* __restrict__ wsbase, int only) {
-  constexpr int T = NB * (NB + 1) / 2;
+  constexpr int NF = TLG ? NB - 1 : NB;  // blocks on the matrix cores
+  constexpr int T = NF * (NF + 1) / 2;
   const nyls_desc& d = desc[instance_of(order)];
-  if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m + 2) != NB) return;
+  if (d.p != P || d.rec != (EX ? 0 : 1) || d.m + 2 > 64 ||
+      nyls_gram_class(d.m) != 2 * NB + (TLG ? 1 : 0))
+    return;
   const int m = d.m, n = d.n, g = m + 2;
   const nyls_wsl L = nyls_layout(m, P, 0);
   double* ws = wsbase + d.ws;
   if (use_eigenbasis(ws, L, only)) return;  // k_gram64_rot_mfma
   const int lane = threadIdx.x;
-  // blocks with data; the last one goes to the VALU when it has at most four columns
-  const int nbu = (g + 15) >> 4;
-  const bool tl = nbu > 1 && g - 16 * (nbu - 1) <= 4;
-  const int nf = tl ? nbu - 1 : nbu;  // blocks on the matrix cores
 
   nyls_walk<NB, EX> wk;
   wk.init(d, lane);
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
   nyls_d4 acc[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) acc[t] = nyls_d4{0.0, 0.0, 0.0, 0.0};
-  double tacc[NB][4];  // tail: sum_i q_i[16 b + sl] q_i[16 (nbu - 1) + c]
+  double tacc[NB][4];  // tail: sum_i q_i[16 b + sl] q_i[16 (NB - 1) + c]
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -275,12 +278,9 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
     wk.chunk(
         d, i0,
         [&](int b, int j, double g, double e) {
-          const double pv = e * nyls_horner<P>(g, cj[j]);
-          // blocks entirely below m hold landmarks only (wave-uniform test)
-          q[b] = 16 * b + 16 <= m ? pv
-                                  : (kind[b] == 0 ? pv
-                                                  : (kind[b] == 1 ? -st.f[P - 1][j]
-                                                                  : (kind[b] == 2 ? st.r[j] : 0.0)));
+          const double v = kind[b] == 0 ? e * nyls_horner<P>(g, cj[j])
+                                         : (kind[b] == 1 ? -st.f[P - 1][j] : (kind[b] == 2 ? st.r[j] : 0.0));
+          q[b] = v;
         },
         [&](int j) {
           const int i = i0 + 4 * j + wk.ph;
@@ -289,17 +289,14 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
           for (int b = 0; b < NB; ++b) q[b] = ok ? q[b] : 0.0;
           int t = 0;
 #pragma unroll
-          for (int I = 0; I < NB; ++I)
+          for (int I = 0; I < NF; ++I)
 #pragma unroll
-            for (int J = I; J < NB; ++J) {
-              if (J < nf) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(q[I], q[J], acc[t], 0, 0, 0);
+            for (int J = I; J < NF; ++J) {
+              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(q[I], q[J], acc[t], 0, 0, 0);
               ++t;
             }
-          if (tl) {
-            double qt = 0.0;
-#pragma unroll
-            for (int b = 1; b < NB; ++b)
-              if (b == nbu - 1) qt = q[b];
+          if (TLG) {
+            const double qt = q[NB - 1];
             const double c0 = row_bcast<0>(qt), c1 = row_bcast<1>(qt), c2 = row_bcast<2>(qt),
                          c3 = row_bcast<3>(qt);
 #pragma unroll
@@ -325,22 +322,20 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
   double* out = ws + L.gram;
   int t = 0;
 #pragma unroll
-  for (int I = 0; I < NB; ++I)
+  for (int I = 0; I < NF; ++I)
 #pragma unroll
-    for (int J = I; J < NB; ++J) {
-      if (J < nf) {
+    for (int J = I; J < NF; ++J) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int a = 16 * I + 4 * v + (lane >> 4), b = 16 * J + (lane & 15);
-          if (a < g && b < g) {
-            out[a * g + b] = acc[t][v];
-            if (I != J) out[b * g + a] = acc[t][v];
-          }
+      for (int v = 0; v < 4; ++v) {
+        const int a = 16 * I + 4 * v + (lane >> 4), b = 16 * J + (lane & 15);
+        if (a < g && b < g) {
+          out[a * g + b] = acc[t][v];
+          if (I != J) out[b * g + a] = acc[t][v];
         }
       }
       ++t;
     }
-  if (tl) {
+  if (TLG) {
     // fold the four phases (points); phase-0 lanes own row 16 b + sl.  Entries inside the
     // tail block are written once per (row, column) by the lane of that row.
 #pragma unroll
@@ -348,10 +343,10 @@ __global__ __launch_bounds__(64) void k_gram64_mfma(const nyls_desc* __restrict_
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const double v = nyls_walk_fold(tacc[b][c]);
-        const int a = 16 * b + wk.sl, x = 16 * (nbu - 1) + c;
-        if (wk.ph == 0 && b < nbu && a < g && x < g) {
+        const int a = 16 * b + wk.sl, x = 16 * (NB - 1) + c;
+        if (wk.ph == 0 && a < g && x < g) {
           out[a * g + x] = v;
-          if (b < nbu - 1) out[x * g + a] = v;
+          if (b < NB - 1) out[x * g + a] = v;
         }
       }
   }
@@ -502,17 +497,29 @@ void launch_mfma_nbx(const nyls_plan_view& pv, double* ws, hipStream_t st) {
   if (pv.p_mask & 4) hipLaunchKernelGGL((k_gram64_rot_mfma<NB, 2, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
   if (pv.p_mask & 8) hipLaunchKernelGGL((k_gram64_rot_mfma<NB, 3, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
   if (pv.p_mask & 16) hipLaunchKernelGGL((k_gram64_rot_mfma<NB, 4, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
-  if (pv.only) return;
-  if (pv.p_mask & 2) hipLaunchKernelGGL((k_gram64_mfma<NB, 1, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
-  if (pv.p_mask & 4) hipLaunchKernelGGL((k_gram64_mfma<NB, 2, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
-  if (pv.p_mask & 8) hipLaunchKernelGGL((k_gram64_mfma<NB, 3, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
-  if (pv.p_mask & 16) hipLaunchKernelGGL((k_gram64_mfma<NB, 4, EX>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
 }
 
 template <int NB>
 void launch_mfma_nb(const nyls_plan_view& pv, double* ws, hipStream_t st) {
   if (pv.rec_mask & 2) launch_mfma_nbx<NB, false>(pv, ws, st);
   if (pv.rec_mask & 1) launch_mfma_nbx<NB, true>(pv, ws, st);
+}
+
+template <int NB, bool EX, bool TLG>
+void launch_ks_x(const nyls_plan_view& pv, double* ws, hipStream_t st) {
+  const dim3 grid(pv.batch), block(64);
+  if (pv.p_mask & 2) hipLaunchKernelGGL((k_gram64_mfma<NB, 1, EX, TLG>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
+  if (pv.p_mask & 4) hipLaunchKernelGGL((k_gram64_mfma<NB, 2, EX, TLG>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
+  if (pv.p_mask & 8) hipLaunchKernelGGL((k_gram64_mfma<NB, 3, EX, TLG>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
+  if (pv.p_mask & 16) hipLaunchKernelGGL((k_gram64_mfma<NB, 4, EX, TLG>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
+}
+
+// kernel-space Grams, one launch set per column-block class present in the batch
+template <int NB, bool TLG>
+void launch_ks(const nyls_plan_view& pv, double* ws, hipStream_t st) {
+  if (!(pv.gcls_mask & (1u << (2 * NB + (TLG ? 1 : 0))))) return;
+  if (pv.rec_mask & 2) launch_ks_x<NB, false, TLG>(pv, ws, st);
+  if (pv.rec_mask & 1) launch_ks_x<NB, true, TLG>(pv, ws, st);
 }
 
 }  // namespace
@@ -533,6 +540,15 @@ size_t nyls_gram64_lds_bytes(int maxm) {
 hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t st) {
   if (pv.gnb_mask & 4) launch_mfma_nb<2>(pv, ws, st);
   if (pv.gnb_mask & 16) launch_mfma_nb<4>(pv, ws, st);
+  if (!pv.only) {
+    launch_ks<1, false>(pv, ws, st);
+    launch_ks<2, false>(pv, ws, st);
+    launch_ks<2, true>(pv, ws, st);
+    launch_ks<3, false>(pv, ws, st);
+    launch_ks<3, true>(pv, ws, st);
+    launch_ks<4, false>(pv, ws, st);
+    launch_ks<4, true>(pv, ws, st);
+  }
   const size_t lds = nyls_gram64_lds_bytes(pv.maxm);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -87,6 +87,13 @@ struct nyls_cpts {
     for (int j = 0; j < NYLS_MAX_P; ++j) r |= (c[j] == i);
     return r;
   }
+  // some condition point lies in [lo, hi) (wave-uniform for uniform lo, hi)
+  __device__ bool any_in(int lo, int hi) const {
+    bool r = false;
+#pragma unroll
+    for (int j = 0; j < NYLS_MAX_P; ++j) r |= (c[j] >= lo && c[j] < hi);
+    return r;
+  }
 };
 
 __device__ inline bool nyls_is_condition_point(const nyls_desc& d, int i) {
@@ -253,6 +260,14 @@ enum { NYLS_K_EIG = 0, NYLS_K_GRAM64, NYLS_K_GRAM32, NYLS_K_KKT, NYLS_K_POINTS, 
 // 16-landmark slot blocks per lane of the one-wave passes for an instance with m landmarks.
 __host__ __device__ inline int nyls_slot_blocks(int m) { return m <= 32 ? 2 : (m <= 64 ? 4 : 8); }
 
+// Column blocks of the kernel-space MFMA Gram (m + 2 <= 64): nbu = ceil((m + 2) / 16) blocks
+// carry data, and the last of them goes to the VALU when it holds at most four columns;
+// encoded as 2 nbu + (1 if so).
+__host__ __device__ inline int nyls_gram_class(int m) {
+  const int g = m + 2, nbu = (g + 15) >> 4;
+  return 2 * nbu + ((nbu > 1 && g - 16 * (nbu - 1) <= 4) ? 1 : 0);
+}
+
 // Landmarks in the last 16-slot block when there are at most four of them (m = 16 (NB - 1)
 // + 1 .. 4, NB = nyls_slot_blocks(m) > 1), else 0.  On instances with rec == 1 the one-wave
 // passes walk such a block in a tail layout (one (point, landmark) pair per lane and chunk)
@@ -276,6 +291,7 @@ struct nyls_plan_view {
   const int32_t* d_order;   // instance order, most expensive first
   int64_t total;
   unsigned nt_mask;         // bit t set when some instance has ceil((m+2)/16) == t
+  unsigned gcls_mask;       // bit nyls_gram_class(m) for the instances with m + 2 <= 64
   unsigned tl_mask;         // bit b: some rec == 1 instance of slot class b walks a tail layout
   unsigned ntl_mask;        // bit b: some instance of slot class b does not
 };
