@@ -341,11 +341,13 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
       g = nyls_rdlane(dl, mm) - dL + eL / (g + (g >= 0.0 ? r : -r));
       double sn = 1.0, cs = 1.0, pp = 0.0;
       double carry = own ? Ar[mm] : 0.0;
-      bool split = false;
-      // rotation i reads d_i, d_{i+1} and e_i, which no earlier rotation of this sweep has
+      // Rotation i reads d_i, d_{i+1} and e_i, which no earlier rotation of this sweep has
       // rewritten (rotation i rewrites d_{i+1} and e_{i+1}): read them from copies taken
-      // before the sweep, off the dependency chain of g, sn, cs
+      // before the sweep, off the dependency chain of g, sn, cs.  The lane's Z entry of
+      // column i is loaded one rotation ahead, so the LDS latency overlaps the chain.
       const double d0 = dl, e0 = el;
+      double z0 = own ? Ar[mm - 1] : 0.0;
+      bool split = false;
       for (int i = mm - 1; i >= l; --i) {
         const double ei = nyls_rdlane(e0, i);
         const double di = nyls_rdlane(d0, i), di1 = nyls_rdlane(d0, i + 1);
@@ -368,11 +370,9 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
         pp = sn * r;
         dl = sel_lane(dl, lane, i + 1, g + pp);
         g = cs * r - b;
-        if (own) {
-          const double z0 = Ar[i];
-          Ar[i + 1] = sn * z0 + cs * carry;
-          carry = cs * z0 - sn * carry;
-        }
+        if (own) Ar[i + 1] = sn * z0 + cs * carry;
+        carry = cs * z0 - sn * carry;
+        z0 = (own && i > l) ? Ar[i - 1] : 0.0;
       }
       if (split) continue;
       if (own) Ar[l] = carry;
