@@ -215,9 +215,15 @@ __device__ inline double nyls_rsqrt(double x) {
   return y;
 }
 
+// stage: QL_FULL all steps in one wave; QL_REDUCE steps 1-2, writing d, e and Q to the
+// workspace for k_ql_lanes; QL_REPLAY applies the rotations k_ql_lanes logged to Q, then
+// step 4; QL_REDO = QL_FULL for the instances whose rotation log overflowed.
+enum { QL_FULL = 0, QL_REDUCE = 1, QL_REPLAY = 3, QL_REDO = 4 };
+
 __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ desc,
                                                const int32_t* __restrict__ order,
-                                               double* __restrict__ wsbase, int single, int lda) {
+                                               double* __restrict__ wsbase, int single, int lda,
+                                               int stage) {
   extern __shared__ double sm[];
   const int inst = instance_of(order, single);
   const nyls_desc& d = desc[inst];
@@ -225,6 +231,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
   if (m > kQlMaxM) return;  // k_eig handles larger bases
   const nyls_wsl L = nyls_layout(m, d.p, 0);
   double* ws = wsbase + d.ws;
+  if (stage == QL_REDO && ws[L.info + 7] != 2.0) return;
   const int lane = threadIdx.x;
   double* A = sm;                   // [lda][lda] (lda >= m): K_mm, then Q, then Z
   double* vv = A + lda * lda;       // [64] reflector, broadcast copy
@@ -234,6 +241,78 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
   const bool own = lane < m;
   double* Ar = A + lane * lda;
 
+  double dl = 0.0, el = 0.0, bl = 0.0;  // d_lane, e_lane, beta_lane
+  const double eps = 2.220446049250313e-16;
+  int iters = 0;
+  bool converged = true;
+  if (stage == QL_REPLAY) {
+    if (ws[L.info + 7] == 2.0) return;  // log overflow: QL_REDO recomputes this instance
+    // Q and the eigenvalues from the workspace, then the logged sweeps: each is a header
+    // (mm, number of rotations k) and k pairs (c, s) for columns i = mm - 1, mm - 2, ...
+    if (own)
+      for (int j = 0; j < m; ++j) Ar[j] = ws[L.U + lane * m + j];
+    dl = own ? ws[L.lam + lane] : 0.0;
+    // lanes past m read (and never write) row m - 1, so every read stays inside A
+    const double* Ac = A + (own ? lane : m - 1) * lda;
+    iters = (int)ws[L.info + 2];
+    converged = ws[L.info + 7] == 0.0;
+    // The log is streamed in blocks of 64 entries, one entry per lane (the next block is
+    // loaded while the current one is used); entry p is read with lane broadcasts.
+    const double* lg = ws + L.gram;
+    const int nsw = (int)ws[L.info + 6];
+    const int cap = (int)((L.U - L.gram) / 2);
+    double ca = 0.0, cb = 0.0, na = 0.0, nb = 0.0;  // current and next block
+    auto fetch = [&](int blk, double& a, double& b) {
+      const int e = 64 * blk + lane;
+      a = e < cap ? lg[2 * e] : 0.0;
+      b = e < cap ? lg[2 * e + 1] : 0.0;
+    };
+    int pos = 0, cur = 0;
+    fetch(0, ca, cb);
+    fetch(1, na, nb);
+    auto entry = [&](double& a, double& b) {
+      if ((pos >> 6) != cur) {  // wave-uniform
+        ++cur;
+        ca = na;
+        cb = nb;
+        fetch(cur + 1, na, nb);
+      }
+      a = nyls_rdlane(ca, pos & 63);
+      b = nyls_rdlane(cb, pos & 63);
+      ++pos;
+    };
+    for (int sw = 0; sw < nsw; ++sw) {
+      double hm, hn;
+      entry(hm, hn);
+      const int mm = (int)hm, nrot = (int)hn;
+      double carry = Ac[mm];
+      int k = 0;
+      // groups of four rotations: the four Z entries they read are loaded together
+      for (; k + 4 <= nrot; k += 4) {
+        const int i = mm - 1 - k;  // i - 3 >= mm - nrot >= 0
+        double z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) z[u] = Ac[i - u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          double cs, sn;
+          entry(cs, sn);
+          if (own) Ar[i - u + 1] = sn * z[u] + cs * carry;
+          carry = cs * z[u] - sn * carry;
+        }
+      }
+      for (; k < nrot; ++k) {
+        const int i = mm - 1 - k;
+        double cs, sn;
+        entry(cs, sn);
+        const double z0 = Ac[i];
+        if (own) Ar[i + 1] = sn * z0 + cs * carry;
+        carry = cs * z0 - sn * carry;
+      }
+      if (own) Ar[mm - nrot] = carry;
+    }
+    nyls_wave_lds_sync();
+  } else {
   const double inv_sigma = 1.0 / d.sigma;
   if (own) tl[lane] = nyls_grid_t(d, d.lidx[lane]);
   nyls_wave_lds_sync();
@@ -246,7 +325,6 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
   }
   nyls_wave_lds_sync();
 
-  double dl = 0.0, el = 0.0, bl = 0.0;  // d_lane, e_lane, beta_lane
   // 1. tridiagonalisation
   for (int k = 0; k + 2 < m; ++k) {
     const bool act = own && lane > k;
@@ -320,10 +398,17 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
     nyls_wave_lds_sync();
   }
 
+  if (stage == QL_REDUCE) {
+    // d, e and Q for k_ql_lanes and the replay (W and U are written at the end)
+    if (own) {
+      ws[L.lam + lane] = dl;
+      ws[L.W + lane] = el;
+      for (int j = 0; j < m; ++j) ws[L.U + lane * m + j] = Ar[j];
+    }
+    return;
+  }
+
   // 3. implicit QL on (d, e), rotations accumulated into Z (rows in A)
-  const double eps = 2.220446049250313e-16;
-  int iters = 0;
-  bool converged = true;
   for (int l = 0; l < m; ++l) {
     int it = 0;
     for (;;) {
@@ -382,6 +467,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
     }
   }
   nyls_wave_lds_sync();
+  }  // stage != QL_REPLAY
 
   // 4. sort descending (ties by index), sign each eigenvector (largest |entry| positive,
   //    first on ties), cut-off, W = U_r Lambda_r^{-1/2}
@@ -424,7 +510,99 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
     ws[L.info + 0] = (double)rank;
     ws[L.info + 1] = (double)bits;
     ws[L.info + 2] = (double)iters;
+    ws[L.info + 6] = 0.0;  // k_ql_lanes' sweep count; the adjoint's pass count later
+    ws[L.info + 7] = 0.0;
   }
+}
+
+// Implicit QL on the tridiagonal (d, e) of QL_REDUCE with one lane per instance (64
+// instances per wavefront): the scalar recurrences of a sweep are a serial chain, so a
+// wavefront that runs 64 of them side by side keeps its lanes busy where the one-wave
+// kernel runs one chain on all 64 lanes.  The arithmetic and the order of operations are
+// those of step 3 of k_eig_ql; the plane rotations are logged to the instance's workspace
+// (from L.gram up to L.U, unused at this point) for the replay on Q.  An instance whose log
+// would overflow is marked (info[7] = 2) and redone by k_eig_ql(QL_REDO).
+__global__ __launch_bounds__(64) void k_ql_lanes(const nyls_desc* __restrict__ desc,
+                                                 double* __restrict__ wsbase, int batch) {
+  __shared__ double dv[kQlMaxM][64], ev[kQlMaxM][64];  // [index][lane]: conflict-free
+  const int lane = threadIdx.x;
+  const int inst = blockIdx.x * 64 + lane;
+  const bool act = inst < batch && desc[inst < batch ? inst : 0].m <= kQlMaxM;
+  const nyls_desc& d = desc[act ? inst : 0];
+  const int m = act ? d.m : 0;
+  const nyls_wsl L = nyls_layout(d.m, d.p, 0);
+  double* ws = wsbase + d.ws;
+  for (int k = 0; k < m; ++k) {
+    dv[k][lane] = ws[L.lam + k];
+    ev[k][lane] = ws[L.W + k];
+  }
+  double* lg = ws + L.gram;
+  const int cap = (int)((L.U - L.gram) / 2);  // log entries (pairs of doubles)
+  const double eps = 2.220446049250313e-16;
+  int iters = 0, pos = 0, nsw = 0;
+  bool converged = true, overflow = false;
+  for (int l = 0; l < m && !overflow; ++l) {
+    int it = 0;
+    for (;;) {
+      int mm = l;
+      while (mm < m - 1 && !(fabs(ev[mm][lane]) <= eps * (fabs(dv[mm][lane]) + fabs(dv[mm + 1][lane]))))
+        ++mm;
+      if (mm == l) break;
+      if (++it > kQlMaxIter) { converged = false; break; }
+      if (pos + 1 + (mm - l) > cap) { overflow = true; break; }
+      ++iters;
+      const double dL = dv[l][lane], eL = ev[l][lane];
+      double g = (dv[l + 1][lane] - dL) / (2.0 * eL);
+      double r = sqrt(g * g + 1.0);
+      g = dv[mm][lane] - dL + eL / (g + (g >= 0.0 ? r : -r));
+      double sn = 1.0, cs = 1.0, pp = 0.0;
+      const int hdr = pos++;
+      int nrot = 0;
+      bool split = false;
+      double ei = ev[mm - 1][lane], di = dv[mm - 1][lane], di1 = dv[mm][lane];
+      for (int i = mm - 1; i >= l; --i) {
+        const int ip = i > 0 ? i - 1 : 0;  // next rotation's entries (unused after the last)
+        const double ein = ev[ip][lane], din = dv[ip][lane];
+        const double f = sn * ei, b = cs * ei;
+        const double x = f * f + g * g;
+        if (x == 0.0) {  // exact deflation: the chase stops here
+          ev[i + 1][lane] = 0.0;
+          dv[i + 1][lane] = di1 - pp;
+          ev[mm][lane] = 0.0;
+          split = true;
+          break;
+        }
+        const double y = nyls_rsqrt(x);
+        ev[i + 1][lane] = x * y;
+        sn = f * y;
+        cs = g * y;
+        g = di1 - pp;
+        r = (di - g) * sn + 2.0 * cs * b;
+        pp = sn * r;
+        dv[i + 1][lane] = g + pp;
+        g = cs * r - b;
+        lg[2 * pos] = cs;
+        lg[2 * pos + 1] = sn;
+        ++pos;
+        ++nrot;
+        di1 = di;
+        di = din;
+        ei = ein;
+      }
+      lg[2 * hdr] = (double)mm;
+      lg[2 * hdr + 1] = (double)nrot;
+      ++nsw;
+      if (split) continue;
+      dv[l][lane] -= pp;
+      ev[l][lane] = g;
+      ev[mm][lane] = 0.0;
+    }
+  }
+  if (!act) return;
+  for (int k = 0; k < m; ++k) ws[L.lam + k] = dv[k][lane];
+  ws[L.info + 2] = (double)iters;
+  ws[L.info + 6] = (double)nsw;
+  ws[L.info + 7] = overflow ? 2.0 : (converged ? 0.0 : 1.0);
 }
 
 size_t eig_lds_bytes(int maxm, bool vlds) {
@@ -444,8 +622,20 @@ hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hip
                        64 * sizeof(int);
     hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_ql),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_eig_ql, dim3(single >= 0 ? 1 : pv.batch), dim3(64), lds, st, pv.d_desc,
-                       pv.d_order, ws, single, lda);
+    const dim3 grid(single >= 0 ? 1 : pv.batch);
+    if (single >= 0) {
+      hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
+                         (int)QL_FULL);
+    } else {
+      hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
+                         (int)QL_REDUCE);
+      hipLaunchKernelGGL(k_ql_lanes, dim3((pv.batch + 63) / 64), dim3(64), 0, st, pv.d_desc, ws,
+                         pv.batch);
+      hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
+                         (int)QL_REPLAY);
+      hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
+                         (int)QL_REDO);
+    }
   }
   if (!(pv.nb_mask & 256)) return hipGetLastError();
   const bool vlds = pv.maxm <= kVldsMaxM;
