@@ -198,6 +198,10 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig(const nyls_desc* __restrict_
 //     |d_{i+1}|) is evaluated by all lanes at once; the scalar recurrences read d and e with
 //     lane broadcasts and are evaluated by every lane (they are uniform).
 constexpr int kQlMaxIter = 60;  // QL sweeps per eigenvalue
+// Instances per wavefront of k_ql_lanes (at most 64).  Fewer would spread a batch over more
+// CUs and shorten the lockstep of a wavefront's lanes, but 32, 16 and 8 all measured slower
+// than 64 on batches of thousands of m = 50 instances.
+constexpr int kQlLaneInst = 64;
 
 __device__ inline double sel_lane(double x, int lane, int i, double v) { return lane == i ? v : x; }
 
@@ -523,11 +527,11 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
 // (from L.gram up to L.U, unused at this point) for the replay on Q.  An instance whose log
 // would overflow is marked (info[7] = 2) and redone by k_eig_ql(QL_REDO).
 __global__ __launch_bounds__(64) void k_ql_lanes(const nyls_desc* __restrict__ desc,
-                                                 double* __restrict__ wsbase, int batch) {
+                                                 double* __restrict__ wsbase, int batch, int ipw) {
   __shared__ double dv[kQlMaxM][64], ev[kQlMaxM][64];  // [index][lane]: conflict-free
   const int lane = threadIdx.x;
-  const int inst = blockIdx.x * 64 + lane;
-  const bool act = inst < batch && desc[inst < batch ? inst : 0].m <= kQlMaxM;
+  const int inst = blockIdx.x * ipw + lane;  // ipw <= 64 instances per wavefront
+  const bool act = lane < ipw && inst < batch && desc[inst < batch ? inst : 0].m <= kQlMaxM;
   const nyls_desc& d = desc[act ? inst : 0];
   const int m = act ? d.m : 0;
   const nyls_wsl L = nyls_layout(d.m, d.p, 0);
@@ -541,12 +545,26 @@ __global__ __launch_bounds__(64) void k_ql_lanes(const nyls_desc* __restrict__ d
   const double eps = 2.220446049250313e-16;
   int iters = 0, pos = 0, nsw = 0;
   bool converged = true, overflow = false;
+  // nx > l: the first index above l whose off-diagonal passes the split test (m - 1 counts
+  // as passing), known from the last sweep or scan; otherwise unknown.  The sweep below
+  // evaluates the test for every index it finalises, so a full scan is needed only at the
+  // start and after an exact deflation; the chosen mm is the first passing index from l,
+  // as in the plain scan.
+  int nx = -1;
   for (int l = 0; l < m && !overflow; ++l) {
     int it = 0;
     for (;;) {
       int mm = l;
-      while (mm < m - 1 && !(fabs(ev[mm][lane]) <= eps * (fabs(dv[mm][lane]) + fabs(dv[mm + 1][lane]))))
-        ++mm;
+      if (l < m - 1 && !(fabs(ev[l][lane]) <= eps * (fabs(dv[l][lane]) + fabs(dv[l + 1][lane])))) {
+        if (nx > l) {
+          mm = nx;
+        } else {
+          mm = l + 1;
+          while (mm < m - 1 && !(fabs(ev[mm][lane]) <= eps * (fabs(dv[mm][lane]) + fabs(dv[mm + 1][lane]))))
+            ++mm;
+          nx = mm;
+        }
+      }
       if (mm == l) break;
       if (++it > kQlMaxIter) { converged = false; break; }
       if (pos + 1 + (mm - l) > cap) { overflow = true; break; }
@@ -557,9 +575,9 @@ __global__ __launch_bounds__(64) void k_ql_lanes(const nyls_desc* __restrict__ d
       g = dv[mm][lane] - dL + eL / (g + (g >= 0.0 ? r : -r));
       double sn = 1.0, cs = 1.0, pp = 0.0;
       const int hdr = pos++;
-      int nrot = 0;
+      int nrot = 0, sm = mm;
       bool split = false;
-      double ei = ev[mm - 1][lane], di = dv[mm - 1][lane], di1 = dv[mm][lane];
+      double ei = ev[mm - 1][lane], di = dv[mm - 1][lane], di1 = dv[mm][lane], dup = 0.0;
       for (int i = mm - 1; i >= l; --i) {
         const int ip = i > 0 ? i - 1 : 0;  // next rotation's entries (unused after the last)
         const double ein = ev[ip][lane], din = dv[ip][lane];
@@ -573,13 +591,18 @@ __global__ __launch_bounds__(64) void k_ql_lanes(const nyls_desc* __restrict__ d
           break;
         }
         const double y = nyls_rsqrt(x);
-        ev[i + 1][lane] = x * y;
+        const double en = x * y;
+        ev[i + 1][lane] = en;
         sn = f * y;
         cs = g * y;
         g = di1 - pp;
         r = (di - g) * sn + 2.0 * cs * b;
         pp = sn * r;
-        dv[i + 1][lane] = g + pp;
+        const double dn = g + pp;
+        dv[i + 1][lane] = dn;
+        // index i + 1 is final for this sweep (its d above was written one step earlier)
+        if (i + 1 < mm && fabs(en) <= eps * (fabs(dn) + fabs(dup))) sm = i + 1;
+        dup = dn;
         g = cs * r - b;
         lg[2 * pos] = cs;
         lg[2 * pos + 1] = sn;
@@ -592,10 +615,14 @@ __global__ __launch_bounds__(64) void k_ql_lanes(const nyls_desc* __restrict__ d
       lg[2 * hdr] = (double)mm;
       lg[2 * hdr + 1] = (double)nrot;
       ++nsw;
-      if (split) continue;
+      if (split) {
+        nx = -1;
+        continue;
+      }
       dv[l][lane] -= pp;
       ev[l][lane] = g;
       ev[mm][lane] = 0.0;
+      nx = sm;
     }
   }
   if (!act) return;
@@ -629,8 +656,8 @@ hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hip
     } else {
       hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
                          (int)QL_REDUCE);
-      hipLaunchKernelGGL(k_ql_lanes, dim3((pv.batch + 63) / 64), dim3(64), 0, st, pv.d_desc, ws,
-                         pv.batch);
+      hipLaunchKernelGGL(k_ql_lanes, dim3((pv.batch + kQlLaneInst - 1) / kQlLaneInst), dim3(64), 0,
+                         st, pv.d_desc, ws, pv.batch, kQlLaneInst);
       hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
                          (int)QL_REPLAY);
       hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
