@@ -33,8 +33,8 @@ TRAFFIC = {
     "backward": {
         "sources": ["paper_2510_04094_amd/csrc/adjoint.hip", "paper_2510_04094_amd/csrc/nyls_walk.h",
                     "paper_2510_04094_amd/csrc/nyls_dense.h", "paper_2510_04094_amd/csrc/nyls_internal.h"],
-        "sha1": "6c50049794f42f1e6ba0d1617b1d764baea81b0c",
-        "kib": {"mixed": (1976115.3, 1119602.0), "fp64": (1618526.9, 1119589.6)},
+        "sha1": "814fd763a2b7f604c888ae918dd0f2824233894a",
+        "kib": {"mixed": (2580179.3, 1128721.1), "fp64": (2228775.8, 1128731.8)},
         "scale": (2.0, 1.0),
     },
 }
