@@ -9,6 +9,7 @@
 // signed so its largest-magnitude entry (first on ties) is positive, and eigenpairs with
 // lambda_k <= tau * lambda_1 are dropped (the retained rank r goes to info[0]).
 #include "nyls_dense.h"
+#include "nyls_walk.h"
 
 namespace {
 
@@ -205,6 +206,95 @@ constexpr int kQlLaneInst = 64;
 
 __device__ inline double sel_lane(double x, int lane, int i, double v) { return lane == i ? v : x; }
 
+// Sum over the wavefront, bitwise equal in every lane: rotations by 8, 4, 2 and 1 within each
+// row of 16 lanes (DPP row_ror; the two lanes of every exchange add the same two values),
+// then the lane-swap exchanges across rows.  No LDS round trip.
+__device__ inline double eig_wave_sum(double v) {
+  v += __builtin_amdgcn_update_dpp(0.0, v, 0x128, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0.0, v, 0x124, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0.0, v, 0x122, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0.0, v, 0x121, 0xf, 0xf, false);
+  return nyls_add_xor32(nyls_add_xor16(v));
+}
+
+// Row-per-lane updates in LDS over columns j0 <= j < m, in unguarded chunks of 8, then 4,
+// then single columns: a chunk's loads (the lane's own row and the broadcast vectors) are
+// all issued before its stores, so each chunk waits for LDS once instead of once per column.
+// sum_j r[j] a[j] (two partial sums)
+template <int C>
+__device__ inline void eig_dot_chunk(const double* r, const double* a, int j, double& s0,
+                                     double& s1) {
+  double x[C], y[C];
+#pragma unroll
+  for (int u = 0; u < C; ++u) { x[u] = r[j + u]; y[u] = a[j + u]; }
+#pragma unroll
+  for (int u = 0; u < C; ++u) {
+    if (u & 1) s1 = fma(x[u], y[u], s1);
+    else s0 = fma(x[u], y[u], s0);
+  }
+}
+__device__ inline double eig_row_dot(const double* r, const double* a, int j0, int m) {
+  double s0 = 0.0, s1 = 0.0;
+  int j = j0;
+  for (; j + 8 <= m; j += 8) eig_dot_chunk<8>(r, a, j, s0, s1);
+  if (j + 4 <= m) { eig_dot_chunk<4>(r, a, j, s0, s1); j += 4; }
+  for (; j < m; ++j) s0 = fma(r[j], a[j], s0);
+  return s0 + s1;
+}
+// r[j] -= v a[j] + w b[j]
+template <int C>
+__device__ inline void eig_rank2_chunk(double* r, double v, const double* a, double w,
+                                       const double* b, int j) {
+  double x[C], y[C], z[C];
+#pragma unroll
+  for (int u = 0; u < C; ++u) { x[u] = r[j + u]; y[u] = a[j + u]; z[u] = b[j + u]; }
+#pragma unroll
+  for (int u = 0; u < C; ++u) r[j + u] = x[u] - (v * y[u] + w * z[u]);
+}
+__device__ inline void eig_row_rank2(double* r, double v, const double* a, double w,
+                                     const double* b, int j0, int m) {
+  int j = j0;
+  for (; j + 8 <= m; j += 8) eig_rank2_chunk<8>(r, v, a, w, b, j);
+  if (j + 4 <= m) { eig_rank2_chunk<4>(r, v, a, w, b, j); j += 4; }
+  for (; j < m; ++j) r[j] -= v * a[j] + w * b[j];
+}
+// r[j] -= v a[j]
+template <int C>
+__device__ inline void eig_rank1_chunk(double* r, double v, const double* a, int j) {
+  double x[C], y[C];
+#pragma unroll
+  for (int u = 0; u < C; ++u) { x[u] = r[j + u]; y[u] = a[j + u]; }
+#pragma unroll
+  for (int u = 0; u < C; ++u) r[j + u] = x[u] - v * y[u];
+}
+__device__ inline void eig_row_rank1(double* r, double v, const double* a, int j0, int m) {
+  int j = j0;
+  for (; j + 8 <= m; j += 8) eig_rank1_chunk<8>(r, v, a, j);
+  if (j + 4 <= m) { eig_rank1_chunk<4>(r, v, a, j); j += 4; }
+  for (; j < m; ++j) r[j] -= v * a[j];
+}
+// sum_i a[i] Q[i][col] over rows j0 <= i < m (column access, stride lda)
+template <int C>
+__device__ inline void eig_col_chunk(const double* a, const double* q, int lda, int i, double& s0,
+                                     double& s1) {
+  double x[C], y[C];
+#pragma unroll
+  for (int u = 0; u < C; ++u) { x[u] = a[i + u]; y[u] = q[(i + u) * lda]; }
+#pragma unroll
+  for (int u = 0; u < C; ++u) {
+    if (u & 1) s1 = fma(x[u], y[u], s1);
+    else s0 = fma(x[u], y[u], s0);
+  }
+}
+__device__ inline double eig_col_dot(const double* a, const double* q, int lda, int j0, int m) {
+  double s0 = 0.0, s1 = 0.0;
+  int i = j0;
+  for (; i + 8 <= m; i += 8) eig_col_chunk<8>(a, q, lda, i, s0, s1);
+  if (i + 4 <= m) { eig_col_chunk<4>(a, q, lda, i, s0, s1); i += 4; }
+  for (; i < m; ++i) s0 = fma(a[i], q[i * lda], s0);
+  return s0 + s1;
+}
+
 // 1/sqrt(x) for normal or subnormal x > 0: the hardware estimate followed by two Newton
 // steps y <- y (3 - x y^2) / 2 (each one roughly squares the relative error), so that the
 // rotation c = g y, s = f y (x = f^2 + g^2) has c^2 + s^2 = 1 to a few ulp.  The dependency
@@ -241,6 +331,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
   double* vv = A + lda * lda;       // [64] reflector, broadcast copy
   double* tt = vv + 64;             // [64] column sums / sign / sorted eigenvalues
   double* tl = tt + 64;             // [64] landmark times
+  double* ww = tl;                  // [64] Householder w, broadcast copy (after tl's last use)
   int* pos = reinterpret_cast<int*>(tl + 64);  // [64] sorted position
   const bool own = lane < m;
   double* Ar = A + lane * lda;
@@ -256,39 +347,33 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
     if (own)
       for (int j = 0; j < m; ++j) Ar[j] = ws[L.U + lane * m + j];
     dl = own ? ws[L.lam + lane] : 0.0;
-    // lanes past m read (and never write) row m - 1, so every read stays inside A
+    // lanes past m read row m - 1, so every read stays inside A
     const double* Ac = A + (own ? lane : m - 1) * lda;
     iters = (int)ws[L.info + 2];
     converged = ws[L.info + 7] == 0.0;
-    // The log is streamed in blocks of 64 entries, one entry per lane (the next block is
-    // loaded while the current one is used); entry p is read with lane broadcasts.
+    // Lanes past m write their (unused) results to the vv/tt/tl area, one column apart so the
+    // stores do not collide; step 4 rewrites that area before reading it.  No lane mask is
+    // needed in the rotation loop.
+    double* Aw = own ? Ar : vv + (lane - m);
+    // Each sweep's log window (its header and at most m - 1 <= 63 rotations) is one entry
+    // per lane; rotation k is read from lane k + 1 with lane broadcasts.  The next sweep's
+    // window is loaded while this one is applied.
     const double* lg = ws + L.gram;
     const int nsw = (int)ws[L.info + 6];
     const int cap = (int)((L.U - L.gram) / 2);
-    double ca = 0.0, cb = 0.0, na = 0.0, nb = 0.0;  // current and next block
-    auto fetch = [&](int blk, double& a, double& b) {
-      const int e = 64 * blk + lane;
+    auto fetch = [&](int e0, double& a, double& b) {
+      const int e = e0 + lane;
       a = e < cap ? lg[2 * e] : 0.0;
       b = e < cap ? lg[2 * e + 1] : 0.0;
     };
-    int pos = 0, cur = 0;
+    double ca, cb;
     fetch(0, ca, cb);
-    fetch(1, na, nb);
-    auto entry = [&](double& a, double& b) {
-      if ((pos >> 6) != cur) {  // wave-uniform
-        ++cur;
-        ca = na;
-        cb = nb;
-        fetch(cur + 1, na, nb);
-      }
-      a = nyls_rdlane(ca, pos & 63);
-      b = nyls_rdlane(cb, pos & 63);
-      ++pos;
-    };
+    int hdr = 0;
     for (int sw = 0; sw < nsw; ++sw) {
-      double hm, hn;
-      entry(hm, hn);
-      const int mm = (int)hm, nrot = (int)hn;
+      const int mm = (int)nyls_rdlane(ca, 0), nrot = (int)nyls_rdlane(cb, 0);
+      const int nxt = hdr + 1 + nrot;
+      double na, nb;
+      fetch(nxt, na, nb);
       double carry = Ac[mm];
       int k = 0;
       // groups of four rotations: the four Z entries they read are loaded together
@@ -299,21 +384,22 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
         for (int u = 0; u < 4; ++u) z[u] = Ac[i - u];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          double cs, sn;
-          entry(cs, sn);
-          if (own) Ar[i - u + 1] = sn * z[u] + cs * carry;
+          const double cs = nyls_rdlane(ca, k + u + 1), sn = nyls_rdlane(cb, k + u + 1);
+          Aw[i - u + 1] = sn * z[u] + cs * carry;
           carry = cs * z[u] - sn * carry;
         }
       }
       for (; k < nrot; ++k) {
         const int i = mm - 1 - k;
-        double cs, sn;
-        entry(cs, sn);
+        const double cs = nyls_rdlane(ca, k + 1), sn = nyls_rdlane(cb, k + 1);
         const double z0 = Ac[i];
-        if (own) Ar[i + 1] = sn * z0 + cs * carry;
+        Aw[i + 1] = sn * z0 + cs * carry;
         carry = cs * z0 - sn * carry;
       }
-      if (own) Ar[mm - nrot] = carry;
+      Aw[mm - nrot] = carry;
+      ca = na;
+      cb = nb;
+      hdr = nxt;
     }
     nyls_wave_lds_sync();
   } else {
@@ -333,7 +419,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
   for (int k = 0; k + 2 < m; ++k) {
     const bool act = own && lane > k;
     const double x = act ? Ar[k] : 0.0;
-    const double sig2 = nyls_wave_sum(x * x);
+    const double sig2 = eig_wave_sum(x * x);
     const double x1 = nyls_rdlane(x, k + 1);
     dl = sel_lane(dl, lane, k, A[k * lda + k]);
     if (!(sig2 - x1 * x1 > 0.0)) {  // already tridiagonal in this column: H_k = I
@@ -351,16 +437,13 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
     if (act) Ar[k] = v;
     nyls_wave_lds_sync();
     double pl = 0.0;
-    if (act)
-      for (int j = k + 1; j < m; ++j) pl += Ar[j] * vv[j];
+    if (act) pl = eig_row_dot(Ar, vv, k + 1, m);
     pl *= beta;
-    const double K = 0.5 * beta * nyls_wave_sum(v * pl);
+    const double K = 0.5 * beta * eig_wave_sum(v * pl);
     const double w = pl - K * v;
-    // w goes to row k right of the diagonal (never read again as matrix data)
-    if (act) A[k * lda + lane] = w;
+    ww[lane] = w;
     nyls_wave_lds_sync();
-    if (act)
-      for (int j = k + 1; j < m; ++j) Ar[j] -= v * A[k * lda + j] + w * vv[j];
+    if (act) eig_row_rank2(Ar, v, ww, w, vv, k + 1, m);
     nyls_wave_lds_sync();
   }
   {
@@ -387,13 +470,10 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
       vv[lane] = v;
       nyls_wave_lds_sync();
       // t_j = sum_i v_i Q[i][j] (lane j owns column j)
-      double t = 0.0;
-      if (act)
-        for (int i = k + 1; i < m; ++i) t += vv[i] * A[i * lda + lane];
+      const double t = act ? eig_col_dot(vv, A + lane, lda, k + 1, m) : 0.0;
       tt[lane] = beta * t;
       nyls_wave_lds_sync();
-      if (act)
-        for (int j = k + 1; j < m; ++j) Ar[j] -= v * tt[j];
+      if (act) eig_row_rank1(Ar, v, tt, k + 1, m);
     }
     // row and column k of Q: e_k
     if (lane == k)
