@@ -9,7 +9,6 @@
 // signed so its largest-magnitude entry (first on ties) is positive, and eigenpairs with
 // lambda_k <= tau * lambda_1 are dropped (the retained rank r goes to info[0]).
 #include "nyls_dense.h"
-#include "nyls_walk.h"
 
 namespace {
 
@@ -206,95 +205,6 @@ constexpr int kQlLaneInst = 64;
 
 __device__ inline double sel_lane(double x, int lane, int i, double v) { return lane == i ? v : x; }
 
-// Sum over the wavefront, bitwise equal in every lane: rotations by 8, 4, 2 and 1 within each
-// row of 16 lanes (DPP row_ror; the two lanes of every exchange add the same two values),
-// then the lane-swap exchanges across rows.  No LDS round trip.
-__device__ inline double eig_wave_sum(double v) {
-  v += __builtin_amdgcn_update_dpp(0.0, v, 0x128, 0xf, 0xf, false);
-  v += __builtin_amdgcn_update_dpp(0.0, v, 0x124, 0xf, 0xf, false);
-  v += __builtin_amdgcn_update_dpp(0.0, v, 0x122, 0xf, 0xf, false);
-  v += __builtin_amdgcn_update_dpp(0.0, v, 0x121, 0xf, 0xf, false);
-  return nyls_add_xor32(nyls_add_xor16(v));
-}
-
-// Row-per-lane updates in LDS over columns j0 <= j < m, in unguarded chunks of 8, then 4,
-// then single columns: a chunk's loads (the lane's own row and the broadcast vectors) are
-// all issued before its stores, so each chunk waits for LDS once instead of once per column.
-// sum_j r[j] a[j] (two partial sums)
-template <int C>
-__device__ inline void eig_dot_chunk(const double* r, const double* a, int j, double& s0,
-                                     double& s1) {
-  double x[C], y[C];
-#pragma unroll
-  for (int u = 0; u < C; ++u) { x[u] = r[j + u]; y[u] = a[j + u]; }
-#pragma unroll
-  for (int u = 0; u < C; ++u) {
-    if (u & 1) s1 = fma(x[u], y[u], s1);
-    else s0 = fma(x[u], y[u], s0);
-  }
-}
-__device__ inline double eig_row_dot(const double* r, const double* a, int j0, int m) {
-  double s0 = 0.0, s1 = 0.0;
-  int j = j0;
-  for (; j + 8 <= m; j += 8) eig_dot_chunk<8>(r, a, j, s0, s1);
-  if (j + 4 <= m) { eig_dot_chunk<4>(r, a, j, s0, s1); j += 4; }
-  for (; j < m; ++j) s0 = fma(r[j], a[j], s0);
-  return s0 + s1;
-}
-// r[j] -= v a[j] + w b[j]
-template <int C>
-__device__ inline void eig_rank2_chunk(double* r, double v, const double* a, double w,
-                                       const double* b, int j) {
-  double x[C], y[C], z[C];
-#pragma unroll
-  for (int u = 0; u < C; ++u) { x[u] = r[j + u]; y[u] = a[j + u]; z[u] = b[j + u]; }
-#pragma unroll
-  for (int u = 0; u < C; ++u) r[j + u] = x[u] - (v * y[u] + w * z[u]);
-}
-__device__ inline void eig_row_rank2(double* r, double v, const double* a, double w,
-                                     const double* b, int j0, int m) {
-  int j = j0;
-  for (; j + 8 <= m; j += 8) eig_rank2_chunk<8>(r, v, a, w, b, j);
-  if (j + 4 <= m) { eig_rank2_chunk<4>(r, v, a, w, b, j); j += 4; }
-  for (; j < m; ++j) r[j] -= v * a[j] + w * b[j];
-}
-// r[j] -= v a[j]
-template <int C>
-__device__ inline void eig_rank1_chunk(double* r, double v, const double* a, int j) {
-  double x[C], y[C];
-#pragma unroll
-  for (int u = 0; u < C; ++u) { x[u] = r[j + u]; y[u] = a[j + u]; }
-#pragma unroll
-  for (int u = 0; u < C; ++u) r[j + u] = x[u] - v * y[u];
-}
-__device__ inline void eig_row_rank1(double* r, double v, const double* a, int j0, int m) {
-  int j = j0;
-  for (; j + 8 <= m; j += 8) eig_rank1_chunk<8>(r, v, a, j);
-  if (j + 4 <= m) { eig_rank1_chunk<4>(r, v, a, j); j += 4; }
-  for (; j < m; ++j) r[j] -= v * a[j];
-}
-// sum_i a[i] Q[i][col] over rows j0 <= i < m (column access, stride lda)
-template <int C>
-__device__ inline void eig_col_chunk(const double* a, const double* q, int lda, int i, double& s0,
-                                     double& s1) {
-  double x[C], y[C];
-#pragma unroll
-  for (int u = 0; u < C; ++u) { x[u] = a[i + u]; y[u] = q[(i + u) * lda]; }
-#pragma unroll
-  for (int u = 0; u < C; ++u) {
-    if (u & 1) s1 = fma(x[u], y[u], s1);
-    else s0 = fma(x[u], y[u], s0);
-  }
-}
-__device__ inline double eig_col_dot(const double* a, const double* q, int lda, int j0, int m) {
-  double s0 = 0.0, s1 = 0.0;
-  int i = j0;
-  for (; i + 8 <= m; i += 8) eig_col_chunk<8>(a, q, lda, i, s0, s1);
-  if (i + 4 <= m) { eig_col_chunk<4>(a, q, lda, i, s0, s1); i += 4; }
-  for (; i < m; ++i) s0 = fma(a[i], q[i * lda], s0);
-  return s0 + s1;
-}
-
 // 1/sqrt(x) for normal or subnormal x > 0: the hardware estimate followed by two Newton
 // steps y <- y (3 - x y^2) / 2 (each one roughly squares the relative error), so that the
 // rotation c = g y, s = f y (x = f^2 + g^2) has c^2 + s^2 = 1 to a few ulp.  The dependency
@@ -419,7 +329,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
   for (int k = 0; k + 2 < m; ++k) {
     const bool act = own && lane > k;
     const double x = act ? Ar[k] : 0.0;
-    const double sig2 = eig_wave_sum(x * x);
+    const double sig2 = nyls_wave_sum_dpp(x * x);
     const double x1 = nyls_rdlane(x, k + 1);
     dl = sel_lane(dl, lane, k, A[k * lda + k]);
     if (!(sig2 - x1 * x1 > 0.0)) {  // already tridiagonal in this column: H_k = I
@@ -437,13 +347,13 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
     if (act) Ar[k] = v;
     nyls_wave_lds_sync();
     double pl = 0.0;
-    if (act) pl = eig_row_dot(Ar, vv, k + 1, m);
+    if (act) pl = nyls_row_dot(Ar, vv, k + 1, m);
     pl *= beta;
-    const double K = 0.5 * beta * eig_wave_sum(v * pl);
+    const double K = 0.5 * beta * nyls_wave_sum_dpp(v * pl);
     const double w = pl - K * v;
     ww[lane] = w;
     nyls_wave_lds_sync();
-    if (act) eig_row_rank2(Ar, v, ww, w, vv, k + 1, m);
+    if (act) nyls_row_rank2(Ar, v, ww, w, vv, k + 1, m);
     nyls_wave_lds_sync();
   }
   {
@@ -470,10 +380,10 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
       vv[lane] = v;
       nyls_wave_lds_sync();
       // t_j = sum_i v_i Q[i][j] (lane j owns column j)
-      const double t = act ? eig_col_dot(vv, A + lane, lda, k + 1, m) : 0.0;
+      const double t = act ? nyls_col_dot(vv, A + lane, lda, k + 1, m) : 0.0;
       tt[lane] = beta * t;
       nyls_wave_lds_sync();
-      if (act) eig_row_rank1(Ar, v, tt, k + 1, m);
+      if (act) nyls_row_rank1(Ar, v, tt, k + 1, m);
     }
     // row and column k of Q: e_k
     if (lane == k)

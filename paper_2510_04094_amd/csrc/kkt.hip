@@ -90,7 +90,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
   const nyls_desc& d = desc[inst];
   if (only && !((int)wsbase[d.ws + nyls_layout(d.m, d.p, 0).info + 1] & only)) return;
   const int m = d.m, p = d.p;
-  const int g = m + 2, N = m + 1 + p, lda = N + 1;
+  const int g = m + 2, N = m + 1 + p, lda = N | 1;  // odd row stride: row-per-lane access is conflict-free
   const nyls_wsl L = nyls_layout(m, p, 0);
   double* ws = wsbase + d.ws;
   const double* W = ws + L.W;
@@ -104,7 +104,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
   double* rhs = K + N * lda;            // [N]
   double* kc = rhs + (N + 1);           // [p][m] kernel-derivative vectors of the conditions
   double* red = kc + NYLS_MAX_P * NYLS_MAX_M;
-  int* piv = reinterpret_cast<int*>(red + 16);
+  int* piv = reinterpret_cast<int*>(red + 16);  // [N + 1]
+  int* perm = piv + (N + 1);                     // [N + 1]
 
   // T = S W over the landmark block (kernel-space Gram only); with the eigenbasis Gram
   // (rows rotated by U^T) the transform is the diagonal Lambda^{-1/2}.
@@ -202,9 +203,22 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
     for (int a = tid; a < N; a += NYLS_BLOCK) rhs_out[(size_t)inst * kn + a] = rhs[a];
   }
   if (!factor) return;
-  const int sing = nyls_lu(K, lda, N, piv, red);
-  nyls_lu_solve(K, lda, N, piv, rhs);
-  for (int e = tid; e < N * N; e += NYLS_BLOCK) ws[L.lu + e] = K[(e / N) * lda + e % N];
+  int sing;
+  if (N <= 64) {
+    // one wavefront factors and solves (rows stay in place, perm gives their order); the
+    // other wavefronts wait at the barrier
+    if (tid < 64) {
+      const int s1 = nyls_lu_wave(K, lda, N, rhs, piv, perm);
+      if (tid == 0) red[0] = (double)s1;
+    }
+    __syncthreads();
+    sing = (int)red[0];
+    for (int e = tid; e < N * N; e += NYLS_BLOCK) ws[L.lu + e] = K[perm[e / N] * lda + e % N];
+  } else {
+    sing = nyls_lu(K, lda, N, piv, red);
+    nyls_lu_solve(K, lda, N, piv, rhs);
+    for (int e = tid; e < N * N; e += NYLS_BLOCK) ws[L.lu + e] = K[(e / N) * lda + e % N];
+  }
   for (int a = tid; a < N; a += NYLS_BLOCK) {
     ws[L.piv + a] = (double)piv[a];
     ws[L.x + a] = rhs[a];
@@ -228,7 +242,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
 size_t nyls_kkt_lds_bytes(int maxm, int maxp) {
   const int N = maxm + 1 + maxp;
   return ((size_t)N * (N + 1) + (N + 1) + NYLS_MAX_P * NYLS_MAX_M + 16) * sizeof(double) +
-         (size_t)(N + 1) * sizeof(int);
+         (size_t)2 * (N + 1) * sizeof(int);
 }
 
 hipError_t nyls_launch_kkt(const nyls_plan_view& pv, double* ws, double* kkt_out, double* rhs_out,

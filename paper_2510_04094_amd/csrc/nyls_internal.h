@@ -57,6 +57,25 @@ __host__ __device__ inline nyls_wsl nyls_layout(int m, int p, int n_newton) {
   return L;
 }
 
+// The value of this lane and that of lane l ^ 32 (l ^ 16), as (a, b) = the lower lane's
+// value and the upper lane's: the gfx950 lane-swap instructions exchange halves of the
+// wavefront in the VALU (no LDS round trip), and both lanes of a pair see the same (a, b).
+__device__ inline void nyls_pair_xor32(double v, double& a, double& b) {
+  const long long u = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+  a = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+  b = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+
+__device__ inline void nyls_pair_xor16(double v, double& a, double& b) {
+  const long long u = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+  a = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+  b = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+
 // Exchange through LDS among the lanes of one wavefront (for kernels that run one
 // wavefront per workgroup).  The LDS operations of a wavefront execute in program
 // order, so only compiler reordering has to be prevented; a workgroup barrier would also

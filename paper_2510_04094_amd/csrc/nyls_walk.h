@@ -236,24 +236,17 @@ struct nyls_walk {
   }
 };
 
-// v + (v of lane l ^ 32), and v + (v of lane l ^ 16): the gfx950 lane-swap instructions
-// exchange halves of the wavefront in the VALU (no LDS round trip).  Both lanes of a pair
-// add the lower lane's value first, so they hold bitwise equal sums.
+// v + (v of lane l ^ 32), and v + (v of lane l ^ 16).  Both lanes of a pair add the lower
+// lane's value first, so they hold bitwise equal sums.
 __device__ inline double nyls_add_xor32(double v) {
-  const long long u = __double_as_longlong(v);
-  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
-  const double a = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
-  const double b = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+  double a, b;
+  nyls_pair_xor32(v, a, b);
   return a + b;
 }
 
 __device__ inline double nyls_add_xor16(double v) {
-  const long long u = __double_as_longlong(v);
-  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
-  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
-  const double a = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
-  const double b = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+  double a, b;
+  nyls_pair_xor16(v, a, b);
   return a + b;
 }
 
