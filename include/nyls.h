@@ -15,14 +15,17 @@
  *     otherwise, row-major, owned by the caller.  The library never frees them.
  *   - Work functions only enqueue kernels on `stream` (no host synchronisation, no
  *     allocation) and return 0, or a negative NYLS_E* code when an argument is invalid;
- *     nothing is enqueued then.  Numerical outcomes are reported per instance in the
+ *     nothing is enqueued then.  nyls_solve in NYLS_FP64 mode forks part of its work onto
+ *     a stream the plan owns and joins it back on `stream` (events), so later work on
+ *     `stream` is ordered after all of it; graph capture of `stream` captures both.  Numerical outcomes are reported per instance in the
  *     `status` bitmask (NYLS_S*), readable after the stream is synchronised.
  *   - `ws` is a caller-allocated device workspace of nyls_workspace_size(plan) bytes.  It
  *     carries state between calls: nyls_solve leaves the basis, factors and solution there
  *     for nyls_predict / nyls_backward; nyls_newton_step keeps its basis there.  One plan
  *     with one workspace must not be used from two streams at once; distinct plans can.
  *   - Per-instance padded layouts use MAXM = max m over the batch and KN = MAXM + 1 + 4.
- *   - Only the plan functions allocate (the device descriptor table).
+ *   - Only the plan functions allocate (the device descriptor table; an NYLS_FP64 plan
+ *     also creates one non-blocking stream at default priority and two events).
  */
 #ifndef NYLS_H
 #define NYLS_H

@@ -30,6 +30,10 @@ struct nyls_plan {
   int32_t* d_order = nullptr;
   std::vector<nyls_desc> h_desc;
   rocblas_handle blas = nullptr;
+  // FP64 solves run the kernel-space Gram on `side` while the eigensolver runs on the
+  // caller's stream (fork and join through the two events)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -232,6 +236,10 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
              hipSuccess;
   }
   if (ok && mode == NYLS_FP64_EXPLICIT) ok = rocblas_create_handle(&pl->blas) == rocblas_status_success;
+  if (ok && mode == NYLS_FP64)
+    ok = hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     nyls_plan_destroy(pl);
     return NYLS_E_HIP;
@@ -243,6 +251,9 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
 void nyls_plan_destroy(nyls_plan* pl) {
   if (!pl) return;
   if (pl->blas) rocblas_destroy_handle(pl->blas);
+  if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+  if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
+  if (pl->side) (void)hipStreamDestroy(pl->side);
   if (pl->d_desc) (void)hipFree(pl->d_desc);
   if (pl->d_lidx) (void)hipFree(pl->d_lidx);
   if (pl->d_order) (void)hipFree(pl->d_order);
@@ -340,14 +351,32 @@ int nyls_solve(const nyls_plan* pl, int32_t refine_steps, double* omega, double*
     }
     return hip_rc(e);
   }
-  const int gk = pl->mode == NYLS_MIXED ? NYLS_K_GRAM32 : NYLS_K_GRAM64;
-  nyls_prof_begin(NYLS_K_EIG, stream);
-  e = nyls_launch_eig(pv, w, -1, stream);
-  nyls_prof_end(NYLS_K_EIG, stream);
-  nyls_prof_begin(gk, stream);
-  if (e == hipSuccess)
-    e = (pl->mode == NYLS_MIXED) ? nyls_launch_gram32(pv, w, stream) : nyls_launch_gram64(pv, w, stream);
-  nyls_prof_end(gk, stream);
+  if (pl->mode == NYLS_FP64) {
+    // The kernel-space Grams need nothing from the eigensolver, and the eigensolver is
+    // latency-bound (part of it runs one lane per instance on a few CUs): the Grams run on
+    // the side stream meanwhile, and the eigenbasis Grams that replace them where K_mm is
+    // ill-conditioned follow the join.
+    e = hipEventRecord(pl->ev_fork, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(pl->side, pl->ev_fork, 0);
+    nyls_prof_begin(NYLS_K_GRAM64, pl->side);
+    if (e == hipSuccess) e = nyls_launch_gram64_kspace(pv, w, pl->side);
+    nyls_prof_end(NYLS_K_GRAM64, pl->side);
+    hipError_t ej = hipEventRecord(pl->ev_join, pl->side);
+    nyls_prof_begin(NYLS_K_EIG, stream);
+    if (e == hipSuccess) e = nyls_launch_eig(pv, w, -1, stream);
+    nyls_prof_end(NYLS_K_EIG, stream);
+    // joined whatever happened above, so no work is left running on the side stream
+    if (ej == hipSuccess) ej = hipStreamWaitEvent(stream, pl->ev_join, 0);
+    if (e == hipSuccess) e = ej;
+    if (e == hipSuccess) e = nyls_launch_gram64_rest(pv, w, stream);
+  } else {
+    nyls_prof_begin(NYLS_K_EIG, stream);
+    e = nyls_launch_eig(pv, w, -1, stream);
+    nyls_prof_end(NYLS_K_EIG, stream);
+    nyls_prof_begin(NYLS_K_GRAM32, stream);
+    if (e == hipSuccess) e = nyls_launch_gram32(pv, w, stream);
+    nyls_prof_end(NYLS_K_GRAM32, stream);
+  }
   nyls_prof_begin(NYLS_K_KKT, stream);
   if (e == hipSuccess) e = nyls_launch_kkt(pv, w, nullptr, nullptr, 1, stream);
   nyls_prof_end(NYLS_K_KKT, stream);

@@ -268,9 +268,9 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
     // Each sweep's log window (its header and at most m - 1 <= 63 rotations) is one entry
     // per lane; rotation k is read from lane k + 1 with lane broadcasts.  The next sweep's
     // window is loaded while this one is applied.
-    const double* lg = ws + L.gram;
+    const double* lg = ws + L.log;
     const int nsw = (int)ws[L.info + 6];
-    const int cap = (int)((L.U - L.gram) / 2);
+    const int cap = (int)((L.aux - L.log) / 2);
     auto fetch = [&](int e0, double& a, double& b) {
       const int e = e0 + lane;
       a = e < cap ? lg[2 * e] : 0.0;
@@ -514,7 +514,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
 // wavefront that runs 64 of them side by side keeps its lanes busy where the one-wave
 // kernel runs one chain on all 64 lanes.  The arithmetic and the order of operations are
 // those of step 3 of k_eig_ql; the plane rotations are logged to the instance's workspace
-// (from L.gram up to L.U, unused at this point) for the replay on Q.  An instance whose log
+// (its rotation-log region) for the replay on Q.  An instance whose log
 // would overflow is marked (info[7] = 2) and redone by k_eig_ql(QL_REDO).
 __global__ __launch_bounds__(64) void k_ql_lanes(const nyls_desc* __restrict__ desc,
                                                  double* __restrict__ wsbase, int batch, int ipw) {
@@ -530,8 +530,8 @@ __global__ __launch_bounds__(64) void k_ql_lanes(const nyls_desc* __restrict__ d
     dv[k][lane] = ws[L.lam + k];
     ev[k][lane] = ws[L.W + k];
   }
-  double* lg = ws + L.gram;
-  const int cap = (int)((L.U - L.gram) / 2);  // log entries (pairs of doubles)
+  double* lg = ws + L.log;
+  const int cap = (int)((L.aux - L.log) / 2);  // log entries (pairs of doubles)
   const double eps = 2.220446049250313e-16;
   int iters = 0, pos = 0, nsw = 0;
   bool converged = true, overflow = false;

@@ -225,7 +225,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int m = d.m, n = d.n, g = m + 2;
   const nyls_wsl L = nyls_layout(m, P, 0);
   double* ws = wsbase + d.ws;
-  if (use_eigenbasis(ws, L, only)) return;  // k_gram64_rot_mfma
+  // only < 0: every instance, before the eigensolver has chosen the basis (instances that
+  // turn out to need the eigenbasis are redone by k_gram64_rot_mfma afterwards)
+  if (only >= 0 && use_eigenbasis(ws, L, only)) return;  // k_gram64_rot_mfma
   const int lane = threadIdx.x;
 
   nyls_walk<NB, EX> wk;
@@ -506,20 +508,30 @@ void launch_mfma_nb(const nyls_plan_view& pv, double* ws, hipStream_t st) {
 }
 
 template <int NB, bool EX, bool TLG>
-void launch_ks_x(const nyls_plan_view& pv, double* ws, hipStream_t st) {
+void launch_ks_x(const nyls_plan_view& pv, double* ws, hipStream_t st, int only) {
   const dim3 grid(pv.batch), block(64);
-  if (pv.p_mask & 2) hipLaunchKernelGGL((k_gram64_mfma<NB, 1, EX, TLG>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
-  if (pv.p_mask & 4) hipLaunchKernelGGL((k_gram64_mfma<NB, 2, EX, TLG>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
-  if (pv.p_mask & 8) hipLaunchKernelGGL((k_gram64_mfma<NB, 3, EX, TLG>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
-  if (pv.p_mask & 16) hipLaunchKernelGGL((k_gram64_mfma<NB, 4, EX, TLG>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, pv.only);
+  if (pv.p_mask & 2) hipLaunchKernelGGL((k_gram64_mfma<NB, 1, EX, TLG>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, only);
+  if (pv.p_mask & 4) hipLaunchKernelGGL((k_gram64_mfma<NB, 2, EX, TLG>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, only);
+  if (pv.p_mask & 8) hipLaunchKernelGGL((k_gram64_mfma<NB, 3, EX, TLG>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, only);
+  if (pv.p_mask & 16) hipLaunchKernelGGL((k_gram64_mfma<NB, 4, EX, TLG>), grid, block, 0, st, pv.d_desc, pv.d_order, ws, only);
 }
 
 // kernel-space Grams, one launch set per column-block class present in the batch
 template <int NB, bool TLG>
-void launch_ks(const nyls_plan_view& pv, double* ws, hipStream_t st) {
+void launch_ks(const nyls_plan_view& pv, double* ws, hipStream_t st, int only) {
   if (!(pv.gcls_mask & (1u << (2 * NB + (TLG ? 1 : 0))))) return;
-  if (pv.rec_mask & 2) launch_ks_x<NB, false, TLG>(pv, ws, st);
-  if (pv.rec_mask & 1) launch_ks_x<NB, true, TLG>(pv, ws, st);
+  if (pv.rec_mask & 2) launch_ks_x<NB, false, TLG>(pv, ws, st, only);
+  if (pv.rec_mask & 1) launch_ks_x<NB, true, TLG>(pv, ws, st, only);
+}
+
+void launch_ks_all(const nyls_plan_view& pv, double* ws, hipStream_t st, int only) {
+  launch_ks<1, false>(pv, ws, st, only);
+  launch_ks<2, false>(pv, ws, st, only);
+  launch_ks<2, true>(pv, ws, st, only);
+  launch_ks<3, false>(pv, ws, st, only);
+  launch_ks<3, true>(pv, ws, st, only);
+  launch_ks<4, false>(pv, ws, st, only);
+  launch_ks<4, true>(pv, ws, st, only);
 }
 
 }  // namespace
@@ -537,18 +549,19 @@ size_t nyls_gram64_lds_bytes(int maxm) {
   return total;
 }
 
+hipError_t nyls_launch_gram64_kspace(const nyls_plan_view& pv, double* ws, hipStream_t st) {
+  launch_ks_all(pv, ws, st, -1);
+  return hipGetLastError();
+}
+
 hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t st) {
+  if (!pv.only) launch_ks_all(pv, ws, st, 0);
+  return nyls_launch_gram64_rest(pv, ws, st);
+}
+
+hipError_t nyls_launch_gram64_rest(const nyls_plan_view& pv, double* ws, hipStream_t st) {
   if (pv.gnb_mask & 4) launch_mfma_nb<2>(pv, ws, st);
   if (pv.gnb_mask & 16) launch_mfma_nb<4>(pv, ws, st);
-  if (!pv.only) {
-    launch_ks<1, false>(pv, ws, st);
-    launch_ks<2, false>(pv, ws, st);
-    launch_ks<2, true>(pv, ws, st);
-    launch_ks<3, false>(pv, ws, st);
-    launch_ks<3, true>(pv, ws, st);
-    launch_ks<4, false>(pv, ws, st);
-    launch_ks<4, true>(pv, ws, st);
-  }
   const size_t lds = nyls_gram64_lds_bytes(pv.maxm);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -28,7 +28,7 @@ struct nyls_desc {
 
 // Per-instance workspace block (offsets in doubles from nyls_desc::ws).
 struct nyls_wsl {
-  int64_t W, lam, info, gram, lu, piv, x, alpha, acc, H, mu, beta, tmp, U, aux, end;
+  int64_t W, lam, info, gram, lu, piv, x, alpha, acc, H, mu, beta, tmp, U, aux, log, end;
 };
 
 __host__ __device__ inline nyls_wsl nyls_layout(int m, int p, int n_newton) {
@@ -51,7 +51,10 @@ __host__ __device__ inline nyls_wsl nyls_layout(int m, int p, int n_newton) {
   L.beta = L.mu + nk;            // m     W mu_omega
   L.tmp = L.beta + m;            // g*g   scratch (S W products, eigenvectors when m is large)
   L.U = L.tmp + g * g;           // m*m   all eigenvectors (sorted, signed), U[s*m + k]
-  L.aux = L.U + (int64_t)m * m;  // Newton: constant block (m+2)^2 + weighted Gram (m+2)^2
+  L.log = L.U + (int64_t)m * m;  // plane-rotation log of the lane-parallel QL: 2 m^2 (c, s)
+                                 // entries when m <= 64, else empty
+  L.aux = L.log + (m <= 64 ? 4 * (int64_t)m * m : 0);  // Newton: constant block (m+2)^2 +
+                                                        // weighted Gram (m+2)^2
   L.end = L.aux + (n_newton > 0 ? 2 * g * g : 0);
   L.end = (L.end + 7) & ~int64_t(7);
   return L;
@@ -318,6 +321,12 @@ struct nyls_plan_view {
 // `single` >= 0 restricts a launch to that one instance (one workgroup).
 hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hipStream_t st);
 hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t st);
+// The two halves of nyls_launch_gram64 for a solve that overlaps the Gram with the
+// eigensolver: the kernel-space Grams of every instance (they read nothing the eigensolver
+// writes), then, once the eigensolver is done, the eigenbasis Grams that replace them where
+// K_mm is ill-conditioned and the Grams of bases too wide for the one-wave kernels.
+hipError_t nyls_launch_gram64_kspace(const nyls_plan_view& pv, double* ws, hipStream_t st);
+hipError_t nyls_launch_gram64_rest(const nyls_plan_view& pv, double* ws, hipStream_t st);
 hipError_t nyls_launch_gram32(const nyls_plan_view& pv, double* ws, hipStream_t st);
 hipError_t nyls_launch_kkt(const nyls_plan_view& pv, double* ws, double* kkt_out, double* rhs_out,
                            int factor, hipStream_t st);
