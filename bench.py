@@ -33,8 +33,8 @@ TRAFFIC = {
     "backward": {
         "sources": ["paper_2510_04094_amd/csrc/adjoint.hip", "paper_2510_04094_amd/csrc/nyls_walk.h",
                     "paper_2510_04094_amd/csrc/nyls_dense.h", "paper_2510_04094_amd/csrc/nyls_internal.h"],
-        "sha1": "814fd763a2b7f604c888ae918dd0f2824233894a",
-        "kib": {"mixed": (2580179.3, 1128721.1), "fp64": (2228775.8, 1128731.8)},
+        "sha1": "9d49d95515e797dc57dc55a646f7fc0ade765c4e",
+        "kib": {"mixed": (2712945.1, 1128749.3), "fp64": (2319766.4, 1128784.3)},
         "scale": (2.0, 1.0),
     },
 }

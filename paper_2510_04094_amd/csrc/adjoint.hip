@@ -157,7 +157,8 @@ __global__ __launch_bounds__(64) void k_backward(
     mu[a] = val;
   }
   __syncthreads();
-  nyls_lu_solve_w(LU, N, N, piv, mu);
+  if (N <= 64) nyls_lu_solve_wave(LU, N, piv, mu);
+  else nyls_lu_solve_w(LU, N, N, piv, mu);
   auto beta_from_mu = [&]() {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -268,7 +269,8 @@ __global__ __launch_bounds__(64) void k_backward(
       R[a] = xb[a] - amu;
     }
     __syncthreads();
-    nyls_lu_solve_w(LU, N, N, piv, R);
+    if (N <= 64) nyls_lu_solve_wave(LU, N, piv, R);
+    else nyls_lu_solve_w(LU, N, N, piv, R);
     double dsq = 0.0, xsq = 0.0;
     for (int k = lane; k < r; k += 64) {
       dsq += R[k] * R[k];

@@ -281,6 +281,62 @@ __device__ inline int nyls_lu_wave(double* A, int lda, int N, double* b, int* pi
   return singular;
 }
 
+// Solve A x = b with the factors nyls_lu / nyls_lu_wave leave (rows in pivot order, row
+// stride N, any address space; piv: the row interchanges, any address space), N <= 64, by
+// one wavefront: lane k holds entry k.  The interchanges are composed into a permutation in
+// registers and b (LDS, overwritten by x) is gathered once; each substitution step
+// broadcasts the solved entry with a lane read, and every lane walks its own factor row in
+// chunks of eight entries loaded together (prefetching the next chunk as well measured no
+// faster and costs 16 VGPRs).  Same operations in the same order as nyls_lu_solve_w.
+__device__ inline void nyls_lu_solve_wave(const double* A, int N, const int* piv, double* b) {
+  const int lane = threadIdx.x & 63;
+  const bool row = lane < N;
+  const double* Ar = A + (size_t)(row ? lane : 0) * N;  // lanes past N read row 0 only
+  const int pv = row ? piv[lane] : lane;
+  int cur = lane;  // the entry of b that ends up at position `lane`
+  for (int k = 0; k < N; ++k) {
+    const int q = __builtin_amdgcn_readlane(pv, k);
+    const int ck = __builtin_amdgcn_readlane(cur, k), cq = __builtin_amdgcn_readlane(cur, q);
+    if (lane == k) cur = cq;
+    if (lane == q) cur = ck;
+  }
+  double c = row ? b[cur] : 0.0;
+  double a8[8];
+  auto load8 = [&](int t0, double (&v)[8]) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = Ar[t0 + u < N ? t0 + u : N - 1];
+  };
+  // forward: unit lower factor
+  for (int t0 = 0; t0 < N; t0 += 8) {
+    load8(t0, a8);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + u;
+      if (t < N) {
+        const double yt = nyls_rdlane(c, t);
+        if (row && lane > t) c -= a8[u] * yt;
+      }
+    }
+  }
+  // back substitution: x_t = y_t / u_tt, then the entries above subtract it
+  const double dg = row ? Ar[lane] : 1.0;
+  const int tl = (N - 1) & ~7;  // first column of the last chunk
+  for (int t0 = tl; t0 >= 0; t0 -= 8) {
+    load8(t0, a8);
+#pragma unroll
+    for (int u = 7; u >= 0; --u) {
+      const int t = t0 + u;
+      if (t < N) {
+        const double xt = nyls_rdlane(c, t) / nyls_rdlane(dg, t);
+        if (row && lane < t) c -= a8[u] * xt;
+        if (lane == t) c = xt;
+      }
+    }
+  }
+  if (row) b[lane] = c;
+  nyls_wave_lds_sync();
+}
+
 // Solve A x = b with LU factors (row stride lda, any address space); b in LDS.
 __device__ inline void nyls_lu_solve_w(const double* A, int lda, int N, const int* piv, double* b) {
   const int lane = threadIdx.x;
