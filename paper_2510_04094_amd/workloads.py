@@ -57,6 +57,19 @@ def ystar_at(prob, s):
     return np.exp(-sp["damp"] * s) * (np.sin(arg) @ sp["c"])
 
 
+def random_landmarks(instance, n, m, ends=True, config=6):
+    """m strictly ascending grid indices drawn uniformly without replacement (the random
+    landmark variant of the Nystrom basis, Sec. 3); with `ends` the first and last grid
+    points are always landmarks."""
+    rng = _rng(config, instance)
+    if ends:
+        inner = rng.choice(np.arange(1, n - 1), size=m - 2, replace=False)
+        idx = np.concatenate([[0], np.sort(inner), [n - 1]])
+    else:
+        idx = np.sort(rng.choice(n, size=m, replace=False))
+    return idx.astype(np.int64)
+
+
 def linear_first_order(instance, n=200, m=20, t_end=1.0, sigma=0.1, gamma=1e8,
                        tau=1e-12, config=1):
     """y' + a(t) y = g(t), y(0) = y*(0); a = a0 + a1 cos t, a ~ U(.5, 2); y* = 3 sinusoids."""

@@ -53,6 +53,26 @@ def test_backward_matches_oracle(gpu_lib, mode_name):
         assert rel(out["dl_dgamma"][i], ref["dl_dgamma"]) <= 1e-3, ("dgamma", i)
 
 
+def test_backward_with_random_landmarks(gpu_lib):
+    """Adjoint gradients for caller-given (random) landmark sets, FP64 mode, same bars as
+    the equidistant case."""
+    insts = instances(3)
+    for i, q in enumerate(insts):
+        q["lidx"] = workloads.random_landmarks(40 + i, q["n"], q["m"], ends=i != 1)
+    b, out, g = gpu_gradients(gpu_lib, insts, gpu_lib.FP64)
+    for i, q in enumerate(insts):
+        ref = oracle.adjoint.grad(q, q["t_obs"], g[i])
+        o = slice(b.goff[i], b.goff[i + 1])
+        for k in range(q["p"]):
+            gf, rf = out["dl_df"][k, o], ref["dl_df"][k]
+            assert np.max(np.abs(gf - rf)) <= 1e-5 * np.max(np.abs(rf)), ("df", i, k)
+        assert np.max(np.abs(out["dl_dr"][o] - ref["dl_dr"])) <= 1e-5 * np.max(np.abs(ref["dl_dr"]))
+        for j in range(q["p"]):
+            assert rel(out["dl_dv"][i, j], ref["dl_dv"][j]) <= 1e-5, ("dv", i, j)
+        scale = 1e-5 * abs(ref["dl_dsigma"]) + 1e-8 * np.max(np.abs(ref["sigma_terms"]))
+        assert abs(out["dl_dsigma"][i] - ref["dl_dsigma"]) <= scale, ("dsigma", i)
+
+
 def gpu_loss(gpu_lib, insts):
     b = gpu_lib.Batch(insts, mode=gpu_lib.FP64)
     b.solve()

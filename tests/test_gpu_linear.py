@@ -143,6 +143,30 @@ def test_explicit_time_arrays(gpu_lib, mode_name):
         assert rel_inf(ys[i], sol["yhat"]) <= tol, (i, rel_inf(ys[i], sol["yhat"]))
 
 
+@pytest.mark.parametrize("mode_name", ["FP64", "MIXED"])
+def test_random_landmarks_match_oracle(gpu_lib, mode_name):
+    """Landmark sets handed over by the caller instead of the equidistant rule: uniformly
+    random grid indices with and without the end points, and every point of a short grid
+    as a landmark (m = n = 100, the Jacobi eigensolver and the LDS Gram).  Each slot's
+    kernel recurrence runs along the points for its own landmark time, so any landmark set
+    works.  Cut-off 1e-8 for both families (the second-order family's own)."""
+    specs = [(1, 200, 20, True), (1, 237, 40, False), (1, 100, 100, True),
+             (2, 1237, 50, True), (2, 1500, 31, False), (2, 2000, 62, True)]
+    insts = []
+    for i, (p, n, m, ends) in enumerate(specs):
+        q = (workloads.linear_first_order(i, n=n, m=m, tau=1e-8) if p == 1
+             else workloads.linear_second_order(i, n=n, m=m))
+        q["lidx"] = workloads.random_landmarks(20 + i, n, m, ends=ends)
+        insts.append(q)
+    b = gpu_lib.Batch(insts, mode=getattr(gpu_lib, mode_name))
+    out = b.solve()
+    torch.cuda.synchronize()
+    ys = gpu_yhat(b, out)
+    bar = 1e-9 if mode_name == "FP64" else 1e-6
+    for i, sol in enumerate(oracle_solutions(insts)):
+        assert rel_inf(ys[i], sol["yhat"]) <= bar, (i, rel_inf(ys[i], sol["yhat"]))
+
+
 def test_fp64_coarse_grids(gpu_lib):
     """dt > sigma / 4: the one-wave passes take their guarded path, where a run of the
     recurrence that starts far from its landmark and approaches it is evaluated with exact

@@ -93,6 +93,10 @@ def nullspace_solution(sol, prob):
 @pytest.mark.parametrize("maker", [
     lambda: workloads.linear_first_order(5, n=120, m=15),
     lambda: workloads.linear_second_order(4, n=300, m=20, gamma=1e4, tau=1e-10),
+    lambda: dict(workloads.linear_first_order(5, n=150, m=18, gamma=1e5),
+                 lidx=workloads.random_landmarks(5, 150, 18)),
+    lambda: dict(workloads.linear_second_order(6, n=300, m=20, gamma=1e4, tau=1e-10),
+                 lidx=workloads.random_landmarks(6, 300, 20, ends=False)),
 ])
 def test_kkt_solution_equals_nullspace_least_squares(maker):
     prob = maker()
@@ -106,6 +110,8 @@ def test_kkt_solution_equals_nullspace_least_squares(maker):
 @pytest.mark.parametrize("maker", [
     lambda: workloads.linear_first_order(7, n=100, m=12, gamma=1e4),
     lambda: workloads.linear_second_order(8, n=160, m=16, gamma=1e5, tau=1e-10),
+    lambda: dict(workloads.linear_first_order(9, n=100, m=12, gamma=1e4),
+                 lidx=workloads.random_landmarks(9, 100, 12, ends=False)),
 ])
 def test_primal_equals_dual_with_nystrom_kernel(maker):
     """Strong duality: Lemma 1's primal and the dual LS-SVM with kernel k_m^T W W^T k_m agree.
@@ -137,6 +143,21 @@ def test_manufactured_first_order_accuracy():
         sol = oracle.linear.solve(prob)
         errs.append(np.max(np.abs(sol["yhat"] - prob["ystar"])) / np.max(np.abs(prob["ystar"])))
     assert np.median(errs) < 1e-2 and max(errs) < 5e-2
+
+
+def test_random_landmarks_manufactured_accuracy():
+    """Random landmark sets (m = 40 of n = 200 grid points, end points kept) reproduce the
+    manufactured solution about as well as 40 equidistant landmarks (1e-6 .. 1.5e-5 with
+    these seeds), and the given indices are the ones used.  (With m = 20 the random gaps
+    reach 50 grid points = 2.6 sigma and the error grows to several percent.)"""
+    errs = []
+    for i in range(8):
+        prob = workloads.linear_first_order(i, m=40)
+        prob["lidx"] = workloads.random_landmarks(i, prob["n"], prob["m"])
+        sol = oracle.linear.solve(prob)
+        np.testing.assert_array_equal(sol["t_land"], prob["t"][prob["lidx"]])
+        errs.append(np.max(np.abs(sol["yhat"] - prob["ystar"])) / np.max(np.abs(prob["ystar"])))
+    assert np.median(errs) < 1e-5 and max(errs) < 1e-4
 
 
 def test_kkt_matrix_is_symmetric():
