@@ -162,9 +162,11 @@ int nyls_assemble(const nyls_plan* plan, double* kkt, double* rhs, void* ws, hip
  *   refine_steps  most FP64 iterative-refinement steps after the solve, 0..8.  Each step
  *                 forms the exact residual matrix-free from one pass over the points (and
  *                 writes y_hat of the current solution).  The iteration stops once the
- *                 change of y_hat (measured, or bounded by |d omega|_2 + |d b|) falls
- *                 below 1e-11 max|y_hat|, or once a change is more than half the previous
- *                 one (rounding floor reached).  The fused modes
+ *                 change of y_hat (measured, bounded by |d omega|_2 + |d b|, or predicted
+ *                 for the correction just solved as the last measured change times the
+ *                 ratio of the two latest corrections' bounds) falls below 1e-11
+ *                 max|y_hat|, or once a change is more than half the previous one
+ *                 (rounding floor reached).  The fused modes
  *                 factor an approximation of the system (a kernel-space FP64 Gram, or an
  *                 FP32 Gram), so >= 2 steps are recommended when K_mm is ill-conditioned;
  *                 NYLS_FP64_EXPLICIT assembles the exact system (0 steps suffice).
@@ -218,8 +220,10 @@ int nyls_riccati_eval(const nyls_plan* plan, const double* q, const double* x,
  *   dl_dv [batch][4]; dl_dsigma [batch]; dl_dgamma [batch]  (outputs may be NULL)
  * Gradients w.r.t. the data f, r, v are exact derivatives of the Lemma 1 solution;
  * sigma enters through the kernel values and through K_mm (spectral derivative).  The
- * adjoint solve is refined in FP64 (matrix-free, up to three steps, stopping at rounding
- * level) because the stored factors are of an approximate system.  Not available for
+ * adjoint solve is refined in FP64 (matrix-free, up to three steps) because the stored
+ * factors are of an approximate system; it stops once the correction, or the next one
+ * predicted from the contraction seen so far, is below 1e-8 of the solution, or at the
+ * rounding floor.  Not available for
  * NYLS_FP64_EXPLICIT plans. */
 int nyls_backward(const nyls_plan* plan, const double* t_obs, const int64_t* obs_off,
                   const double* dl_dyobs, double* dl_df, double* dl_dr, double* dl_dv,

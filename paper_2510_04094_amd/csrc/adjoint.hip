@@ -281,9 +281,13 @@ __global__ __launch_bounds__(64) void k_backward(
     for (int a = lane; a < N; a += 64) mu[a] += R[a];
     __syncthreads();
     beta_from_mu();
+    // Stop once this correction, or the next one predicted from the contraction seen so
+    // far (this correction over the previous one, or over mu itself for the first), is
+    // below 1e-8 |mu|, or once the corrections stop halving.
     const bool stalled = step > 0 && dn > 0.5 * dprev;
+    const double pred = dn * (dn / (step > 0 ? dprev : xn));
     dprev = dn;
-    if (dn <= 1e-8 * xn || stalled) break;
+    if (dn <= 1e-8 * xn || pred <= 1e-8 * xn || stalled) break;
   }
   const double mub = mu[m];
 

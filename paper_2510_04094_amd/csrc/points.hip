@@ -196,8 +196,11 @@ __global__ __launch_bounds__(64) void k_points(
   //  * before a solve, when the measured change is below tol_stop, or above half the
   //    previous one (the FP64 residual has reached its rounding floor): y_hat and the
   //    solution of this pass are kept.
+  //  * after a solve, when the change this correction will make is predicted below
+  //    tol_stop: the change just measured (of the previous correction) times the ratio of
+  //    the two corrections' bounds, i.e. the contraction of the iteration seen so far.
   // Otherwise the last correction is followed by an output pass (which also measures it).
-  double corr = 0.0, dprev = 0.0, ymax = 0.0;
+  double corr = 0.0, dprev = 0.0, ymax = 0.0, bprev = 0.0;
   bool need_output = true;
   int passes = 0;
   for (int step = 0; step < refine; ++step) {
@@ -268,11 +271,13 @@ __global__ __launch_bounds__(64) void k_points(
     double dsq = 0.0;
     for (int k = lane; k < r; k += 64) dsq += Rv[k] * Rv[k];
     const double bound = sqrt(nyls_wave_sum(dsq)) + fabs(Rv[m]);
-    if (bound <= tol_stop * ymax) {
-      corr = bound;
+    const double pred = step > 0 && bprev > 0.0 ? corr * (bound / bprev) : bound;
+    if (bound <= tol_stop * ymax || pred <= tol_stop * ymax) {
+      corr = fmin(bound, pred);
       need_output = false;
       break;
     }
+    bprev = bound;
   }
   if (need_output) {
     double zacc[NB], zt = 0.0, sacc = 0.0, dmax = 0.0;
