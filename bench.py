@@ -33,8 +33,8 @@ TRAFFIC = {
     "backward": {
         "sources": ["paper_2510_04094_amd/csrc/adjoint.hip", "paper_2510_04094_amd/csrc/nyls_walk.h",
                     "paper_2510_04094_amd/csrc/nyls_dense.h", "paper_2510_04094_amd/csrc/nyls_internal.h"],
-        "sha1": "9d49d95515e797dc57dc55a646f7fc0ade765c4e",
-        "kib": {"mixed": (2712945.1, 1128749.3), "fp64": (2319766.4, 1128784.3)},
+        "sha1": "fbb06b0af5a55ee561369574fc3f691923534ebf",
+        "kib": {"mixed": (2206279.1, 1128782.0), "fp64": (2303883.8, 1129578.8)},
         "scale": (2.0, 1.0),
     },
 }
