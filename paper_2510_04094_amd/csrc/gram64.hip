@@ -204,7 +204,9 @@ __device__ inline bool use_eigenbasis(const double* ws, const nyls_wsl& L, int o
   return only || (rank > 0 && ws[L.lam + rank - 1] < kRotate * ws[L.lam]);
 }
 
-// Value of lane 16 (lane / 16) + T (the same column of this lane's point).
+// Value of lane 16 (lane / 16) + T (the same column of this lane's point).  The builtin's
+// result is returned as the double itself (one v_mov_b64_dpp with row_newbcast); inside an
+// overloaded call it could be read as an integer, which nyls_dpp_f64 avoids elsewhere.
 template <int T>
 __device__ inline double row_bcast(double v) {
   return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + T, 0xf, 0xf, false);
