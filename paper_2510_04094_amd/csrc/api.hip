@@ -448,7 +448,7 @@ const char* nyls_error_string(int32_t code) {
     case NYLS_E_BATCH: return "batch must be >= 1";
     case NYLS_E_MODE: return "unknown or unsupported mode";
     case NYLS_E_ORDER: return "ODE order p outside 1..4";
-    case NYLS_E_SIZE: return "need 2 <= m <= n and m <= 128";
+    case NYLS_E_SIZE: return "need 2 <= m <= n and m <= 128 (m <= 126 in NYLS_MIXED)";
     case NYLS_E_PARAM: return "need sigma > 0, gamma > 0, 0 <= tau < 1 (finite)";
     case NYLS_E_GRID: return "grid: dt <= 0 or explicit times missing / not ascending";
     case NYLS_E_LANDMARK: return "landmark indices not strictly ascending inside [0, n)";

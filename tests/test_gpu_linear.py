@@ -167,6 +167,29 @@ def test_random_landmarks_match_oracle(gpu_lib, mode_name):
         assert rel_inf(ys[i], sol["yhat"]) <= bar, (i, rel_inf(ys[i], sol["yhat"]))
 
 
+@pytest.mark.parametrize("mode_name", ["FP64", "MIXED"])
+def test_long_single_instances(gpu_lib, mode_name):
+    """Long-time single instances, each its own batch of one: n = 5e4 points over t in
+    [0, 20] and [0, 25] with m = 100 and the largest basis (m = 128, 126 in the mixed mode:
+    Jacobi eigensolver, LDS Gram, 256-thread LU); first-order family, sigma = 0.3, cut-off 1e-10 (K_mm keeps
+    lambda_r / lambda_1 ~ 7e-3, so the first-order FP64 bar applies)."""
+    import time
+    mmax = 128 if mode_name == "FP64" else 126  # the FP32 Gram holds m + 2 <= 128 columns
+    for i, (m, t_end) in enumerate([(100, 20.0), (mmax, 25.0)]):
+        q = workloads.linear_first_order(i, n=50000, m=m, t_end=t_end, sigma=0.3, tau=1e-10)
+        b = gpu_lib.Batch([q], mode=getattr(gpu_lib, mode_name))
+        b.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = b.solve()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        y = gpu_yhat(b, out)[0]
+        err = rel_inf(y, oracle.linear.solve(q)["yhat"])
+        print("n=5e4 m=%d %s: %.2f ms per solve, rel err %.1e" % (m, mode_name, ms, err))
+        assert err <= (1e-10 if mode_name == "FP64" else 1e-6), (m, err)
+
+
 def test_fp64_coarse_grids(gpu_lib):
     """dt > sigma / 4: the one-wave passes take their guarded path, where a run of the
     recurrence that starts far from its landmark and approaches it is evaluated with exact
