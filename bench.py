@@ -34,7 +34,7 @@ TRAFFIC = {
         "sources": ["paper_2510_04094_amd/csrc/adjoint.hip", "paper_2510_04094_amd/csrc/nyls_walk.h",
                     "paper_2510_04094_amd/csrc/nyls_dense.h", "paper_2510_04094_amd/csrc/nyls_internal.h"],
         "sha1": "fbb06b0af5a55ee561369574fc3f691923534ebf",
-        "kib": {"mixed": (2206279.1, 1128782.0), "fp64": (2303883.8, 1129578.8)},
+        "kib": {"mixed": (2247586.8, 1128848.5), "fp64": (2353872.3, 1129594.8)},
         "scale": (2.0, 1.0),
     },
 }
@@ -202,6 +202,22 @@ def plain_fp64_rate(nyls, insts):
     return len(insts) / (time.perf_counter() - t0)
 
 
+def long_single_ms(nyls, steps=3):
+    """One long-time instance (first-order family, n = 5e4 over [0, 20], m = 100, sigma = 0.3,
+    FP64 mode): ms per nyls_solve.  Its parity with the oracle is a GPU test."""
+    import torch
+    from paper_2510_04094_amd import workloads
+    q = workloads.linear_first_order(0, n=50000, m=100, t_end=20.0, sigma=0.3, tau=1e-10)
+    b = nyls.Batch([q], mode=nyls.FP64)
+    b.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.solve()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +231,7 @@ def main():
     ap.add_argument("--plain", type=int, default=32, help="instances for the plain FP64 comparator")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle instances timed (0: 12 per core)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--long", type=int, default=1, help="time one long single instance (n = 5e4, m = 100)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -308,6 +325,10 @@ def main():
     if args.plain > 0:
         line["plain_fp64_per_instance"] = {"solves_per_s": plain_fp64_rate(nyls, insts[:args.plain]),
                                            "instances": args.plain, "note": "forward only"}
+    if args.long:
+        line["long_single_instance"] = {"ms_per_solve": long_single_ms(nyls), "n": 50000, "m": 100,
+                                        "note": "first-order family on [0, 20], FP64, forward only; "
+                                                "one workgroup per kernel (one CU)"}
     if not args.no_cpu:
         cores = host_cores()
         count = args.cpu_sample or 12 * cores
