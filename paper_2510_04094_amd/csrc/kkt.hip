@@ -131,6 +131,28 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
     kc[j * NYLS_MAX_M + s] = nyls_pick(kd, d.cond_d[j]);
   }
   __syncthreads();
+  // feature-space condition rows h_j = W^T k^(d_j)(t_{i_j}), each entry formed once (p m <=
+  // 2 per thread), then kept in kc in place of the kernel vectors and in the workspace for
+  // the later passes
+  double hv[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + u * NYLS_BLOCK;
+    hv[u] = 0.0;
+    if (e < p * m) {
+      const int j = e / m, k = e - j * m;
+      if (k < r)
+        for (int s = 0; s < m; ++s) hv[u] += W[s * m + k] * kc[j * NYLS_MAX_M + s];
+      ws[L.H + e] = hv[u];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + u * NYLS_BLOCK;
+    if (e < p * m) kc[(e / m) * NYLS_MAX_M + e % m] = hv[u];
+  }
+  __syncthreads();
   for (int e = tid; e < N * N; e += NYLS_BLOCK) {
     const int a = e / N, b = e - a * N;
     if (mx && a <= m && b <= m) continue;
@@ -157,10 +179,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
             for (int s = 0; s < m; ++s) acc += W[s * m + k] * S[s * g + m];
           val = gam * acc;
         } else {
-          const int j = o - m - 1;
-          double acc = 0.0;
-          for (int s = 0; s < m; ++s) acc += W[s * m + k] * kc[j * NYLS_MAX_M + s];
-          val = acc;
+          val = kc[(o - m - 1) * NYLS_MAX_M + k];  // h_j[k]
         }
       }
     } else if (a == m && b == m) {
@@ -187,14 +206,6 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
       val = d.v[a - m - 1];
     }
     rhs[a] = val;
-  }
-  // feature-space condition rows for later passes
-  for (int e = tid; e < p * m; e += NYLS_BLOCK) {
-    const int j = e / m, k = e - j * m;
-    double acc = 0.0;
-    if (k < r)
-      for (int s = 0; s < m; ++s) acc += W[s * m + k] * kc[j * NYLS_MAX_M + s];
-    ws[L.H + e] = acc;
   }
   __syncthreads();
   if (kkt_out) {
