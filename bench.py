@@ -34,7 +34,7 @@ TRAFFIC = {
         "sources": ["paper_2510_04094_amd/csrc/adjoint.hip", "paper_2510_04094_amd/csrc/nyls_walk.h",
                     "paper_2510_04094_amd/csrc/nyls_dense.h", "paper_2510_04094_amd/csrc/nyls_internal.h"],
         "sha1": "fbb06b0af5a55ee561369574fc3f691923534ebf",
-        "kib": {"mixed": (2247586.8, 1128848.5), "fp64": (2353872.3, 1129594.8)},
+        "kib": {"mixed": (2191364.8, 1128808.3), "fp64": (2351165.4, 1129577.0)},
         "scale": (2.0, 1.0),
     },
 }
