@@ -257,8 +257,10 @@ def main():
     for name in args.modes.split(","):
         mode = {"fp64": nyls.FP64, "mixed": nyls.MIXED}[name]
         b, out, sec, prof, info = run_mode(nyls, insts, mode, args.steps, args.warmup)
-        # verification on a deterministic sample (--check 0 skips it: profiling runs only;
-        # such a line counts every instance and says so with frac_ok = null)
+        # verification on a deterministic sample, after the timed steps (--check 0 skips it:
+        # profiling runs only; such a line counts every instance and says so with frac_ok =
+        # null).  The oracle only checks the GPU's y_hat here; nothing it computes reaches
+        # the GPU path.
         if args.check > 0:
             idx = np.unique(np.linspace(0, args.batch - 1, min(args.check, args.batch)).astype(int))
             y = out["yhat"].cpu().numpy()
