@@ -87,3 +87,16 @@ def test_truncation_drops_eigenvalues_below_cutoff():
     assert lam[r - 1] > 1e-8 * lam[0] >= lam[r]
     # retained features are orthonormal in the landmark inner product: W^T K_mm W = I_r
     np.testing.assert_allclose(w.T @ nystrom.landmark_gram(tl, 1.0) @ w, np.eye(r), atol=1e-7)
+
+
+def test_random_landmarks_contract():
+    """The seeded random landmark sets are m distinct, ascending, in-range grid indices,
+    hold both end points when asked to, and repeat for the same seed."""
+    from paper_2510_04094_amd import workloads
+    for n, m, ends in [(200, 20, True), (237, 40, False), (100, 100, True), (50, 2, True)]:
+        idx = workloads.random_landmarks(7, n, m, ends=ends)
+        assert idx.size == m and np.all(np.diff(idx) > 0) and idx[0] >= 0 and idx[-1] < n
+        if ends:
+            assert idx[0] == 0 and idx[-1] == n - 1
+        np.testing.assert_array_equal(idx, workloads.random_landmarks(7, n, m, ends=ends))
+    assert not np.array_equal(workloads.random_landmarks(1, 500, 30), workloads.random_landmarks(2, 500, 30))
