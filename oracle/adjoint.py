@@ -13,7 +13,14 @@ For l = loss(y_hat(s_1..s_J)) with g_j = dl/dy_hat(s_j):
   3. dl/df_{k,i} = gamma (e_i zh^(p-k)_i + nu_i yh^(p-k)_i)      (i in I, zero elsewhere)
      dl/dr_i     = gamma nu_i
      dl/dv_j     = mu_lam_j
-     dl/dgamma   = -sum_i nu_i e_i
+     dl/dgamma   = -sum_i nu_i e_i = mu_omega^T omega / gamma.
+     The second form follows from the KKT conditions: the first two block rows of
+     A x = rhs say gamma G^T e = -(omega + H lam) and gamma c^T e = -delta^T lam, and the
+     last block row of A mu = x_bar says H^T mu_omega + delta mu_b = 0, so
+     sum_i nu_i e_i = mu_omega^T G^T e + mu_b c^T e = -mu_omega^T omega / gamma.  At large
+     gamma the residuals e_i are tiny and the sum over the points cancels by orders of
+     magnitude, so the product of the two small vectors is the one evaluated (the sum is
+     kept as dl_dgamma_direct).
   4. sigma enters through k^(d)(.) at fixed W (closed form d/dsigma of the
      kernel derivatives) and through W.  The problem depends on W only via
      Q = W W^T = f(K_mm), f(lam) = 1/lam above the cut-off and 0 below, so the
@@ -68,7 +75,8 @@ def grad(prob, t_obs, g_obs):
     dl_dr = np.zeros(n)
     dl_dr[idx] = gam * nu
     dl_dv = mu_l.copy()
-    dl_dgamma = -float(np.sum(nu * e))
+    dl_dgamma_direct = -float(np.sum(nu * e))
+    dl_dgamma = float(mu_w @ sol["omega"]) / gam
 
     # 4a. sigma at fixed W: observation kernel, operator rows, condition rows
     dks = [nystrom_dsigma(d, ti, t_land, sig) for d in range(p + 1)]
@@ -115,7 +123,7 @@ def grad(prob, t_obs, g_obs):
     dl_dsigma = direct + via_kmm
 
     return dict(dl_df=dl_df, dl_dr=dl_dr, dl_dv=dl_dv, dl_dsigma=dl_dsigma,
-                dl_dgamma=dl_dgamma, sol=sol, mu=mu, e=e, nu=nu,
+                dl_dgamma=dl_dgamma, dl_dgamma_direct=dl_dgamma_direct, sol=sol, mu=mu, e=e, nu=nu,
                 sigma_direct=direct, sigma_kmm=via_kmm,
                 sigma_terms=np.array([term_obs, term_pts, term_cond, via_kmm]))
 

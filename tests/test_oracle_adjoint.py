@@ -50,13 +50,14 @@ def test_data_gradients_match_complex_step(p, inst):
         assert abs(got - ref) <= 1e-7 * abs(ref) + 1e-14, (key, got, ref)
 
 
-@pytest.mark.parametrize("p,inst,gamma", [(1, 1, 1e3), (2, 1, 1e2), (2, 4, None)])
+@pytest.mark.parametrize("p,inst,gamma", [(1, 1, 1e3), (2, 1, 1e2), (2, 4, 1e4)])
 def test_gamma_gradient_matches_complex_step(p, inst, gamma):
-    """At the configs' gamma (1e7-1e8) dl/dgamma is ~1e-16 and the adjoint sum carries
-    cancellation, hence the looser bound there; moderate gamma pins the formula tightly."""
+    """At moderate gamma the complex step pins both forms of dl/dgamma: the sum over the
+    points -sum nu_i e_i and the KKT identity mu_omega^T omega / gamma."""
     prob = setup(p, inst, gamma=gamma)
-    tol = 1e-7 if gamma is not None else 1e-3
+    tol = 1e-7
     gr = gradient(prob)
+    assert abs(gr["dl_dgamma_direct"] - gr["dl_dgamma"]) <= 1e-7 * abs(gr["dl_dgamma"])
     pc = dict(prob)
     h = 1e-30 * prob["gamma"]
     pc["gamma"] = prob["gamma"] + 1j * h
@@ -97,3 +98,18 @@ def test_sigma_gradient_has_both_parts(sigma, m, tau):
     gr = gradient(setup(2, 6 if sigma is None else 7, gamma=1.0, sigma=sigma, m=m, tau=tau))
     assert gr["sol"]["r"] < m or sigma is None
     assert abs(gr["sigma_kmm"]) > 1e-3 * abs(gr["sigma_direct"])
+
+
+@pytest.mark.parametrize("inst", [0, 1])
+def test_gamma_and_sigma_gradients_match_high_precision(inst):
+    """At gamma = 1e7 (the second-order family's) dl/dgamma is a product of residual-sized
+    quantities: pinned against a 50-digit solve of the same tiny instance (tests/
+    hp_reference.py) differentiated by a central difference, together with dl/dsigma (its
+    K_mm eigenbasis part included)."""
+    import hp_reference
+    prob = workloads.linear_second_order(inst, n=60, m=10, obs=20, config=5)
+    gr = gradient(prob)
+    ref_g = hp_reference.dloss(prob, "gamma")
+    ref_s = hp_reference.dloss(prob, "sigma")
+    assert abs(gr["dl_dgamma"] - ref_g) <= 1e-10 * abs(ref_g), (gr["dl_dgamma"], ref_g)
+    assert abs(gr["dl_dsigma"] - ref_s) <= 1e-10 * abs(ref_s), (gr["dl_dsigma"], ref_s)
