@@ -66,7 +66,8 @@ enum {
   NYLS_E_LANDMARK = -8,   /* landmark indices not strictly ascending inside [0, n) */
   NYLS_E_COND = -9,       /* condition order outside 0..p-1, index outside [0, n), or a
                              duplicated (order, index) pair */
-  NYLS_E_NONLINEAR = -10, /* Newton step on a plan that is not first order */
+  NYLS_E_NONLINEAR = -10, /* Newton call on a plan whose instances are not all of order 1, or
+                             all of order 2 */
   NYLS_E_HIP = -11,       /* a HIP runtime call failed */
   NYLS_E_ARG = -12        /* another argument is out of range (e.g. dmax, refine steps) */
 };
@@ -152,6 +153,28 @@ int nyls_features(const nyls_plan* plan, const double* t_eval, const int64_t* ev
                   int32_t dmax, double* phi, double* eigval, int32_t* rank, void* ws,
                   hipStream_t stream);
 
+/* Leverage-score landmark sampling (Sec. 4.1 compares equidistant, random and
+ * leverage-score landmarks; the paper gives no score formula).  Ridge leverage scores of
+ * every grid point in the feature space of the plan's own (pilot) basis,
+ *     l_i = phi(t_i)^T (Phi^T Phi + ridge I)^{-1} phi(t_i),   Phi = [phi(t_i)]_{i < n},
+ *   ridge   > 0, or 0 for 1/gamma of each instance (the ridge of the LS-SVM objective)
+ *   scores  [total points] output
+ * Builds the basis in `ws` first (as nyls_features does) and leaves intermediate products in
+ * it, so nyls_predict and nyls_backward need a new nyls_solve afterwards. */
+int nyls_leverage_scores(const nyls_plan* plan, double ridge, double* scores, void* ws,
+                         hipStream_t stream);
+
+/* m distinct landmarks per instance (m of its plan) drawn with probabilities proportional to
+ * scores, without replacement, by exponential keys ln(u_i) / scores_i (the m largest; ties
+ * to the lower index; Efraimidis and Spirakis, 2006):
+ *   u     [total points] caller-drawn uniforms in (0, 1]
+ *   ends  nonzero: grid points 0 and n-1 are always landmarks and m - 2 keys are taken
+ *         from the interior
+ *   lidx  [batch][MAXM] int32 output, ascending; entries past m are -1.
+ * A new plan with these indices as nyls_problem.lidx solves on the sampled basis. */
+int nyls_leverage_sample(const nyls_plan* plan, const double* scores, const double* u,
+                         int32_t ends, int32_t* lidx, hipStream_t stream);
+
 /* Assemble the Lemma 1 system (Sec. 3.1) in feature coordinates (omega, b, lambda):
  *   kkt [batch][KN*KN]: instance i's N = m+1+p system in the leading N x N block
  *       (row stride N), rows/columns of dropped eigen-directions replaced by identity;
@@ -162,11 +185,12 @@ int nyls_assemble(const nyls_plan* plan, double* kkt, double* rhs, void* ws, hip
  *   refine_steps  most FP64 iterative-refinement steps after the solve, 0..8.  Each step
  *                 forms the exact residual matrix-free from one pass over the points (and
  *                 writes y_hat of the current solution).  The iteration stops once the
- *                 change of y_hat (measured, bounded by |d omega|_2 + |d b|, or predicted
- *                 for the correction just solved as the last measured change times the
- *                 ratio of the two latest corrections' bounds) falls below 1e-11
- *                 max|y_hat|, or once a change is more than half the previous one
- *                 (rounding floor reached).  The fused modes
+ *                 change of y_hat (measured, or bounded by |d omega|_2 + |d b|) falls below
+ *                 1e-11 max|y_hat|, or once a change is more than half the previous one
+ *                 (rounding floor reached); when the correction just solved is predicted
+ *                 to be that small (the last measured change times the ratio of the two
+ *                 latest corrections' bounds) no further residual is formed, and a pass
+ *                 that only evaluates y_hat applies and measures it.  The fused modes
  *                 factor an approximation of the system (a kernel-space FP64 Gram, or an
  *                 FP32 Gram), so >= 2 steps are recommended when K_mm is ill-conditioned;
  *                 NYLS_FP64_EXPLICIT assembles the exact system (0 steps suffice).
@@ -181,33 +205,48 @@ int nyls_solve(const nyls_plan* plan, int32_t refine_steps, double* omega, doubl
 int nyls_predict(const nyls_plan* plan, const double* t_eval, const int64_t* eval_off,
                  int32_t d, double* out, const void* ws, hipStream_t stream);
 
-/* Newton iteration on the Lemma 2 system of y' = F(t, y) (p = 1, App. A.5), unknowns
- * (omega, b, lambda, y_i over the residual set).  State x is [batch][XS] with
- * XS = nyls_newton_state_stride(plan) = MAXM + 2 + NMAX (NMAX = max n):
- * x = (omega[MAXM], b, lambda, y[n]) with y indexed by grid point (entries at condition
+/* Newton iteration on the Lemma 2 system (Sec. 3.2) of a nonlinear ODE
+ *     p = 1:  y'  = F(t, y)          (App. A.5)
+ *     p = 2:  y'' = F(t, y, y')      (the appendix section on Problem 15)
+ * with unknowns (omega, b, lambda_1..lambda_p, y_i over the residual set): y itself enters F
+ * through the auxiliary unknown y_i, y' through the model, omega^T phi'(t_i).  Every
+ * instance of the plan must have the same order, 1 or 2 (else NYLS_E_NONLINEAR), and its p
+ * conditions as in nyls_problem (IVP or two-point BVP).  State x is [batch][XS] with
+ * XS = nyls_newton_state_stride(plan) = MAXM + 1 + p + NMAX (NMAX = max n):
+ * x = (omega[MAXM], b, lambda[p], y[n]) with y indexed by grid point (entries at condition
  * points are unused).
  *
- * nyls_newton_init: build the basis and the constant Jacobian blocks in `ws` and write the
- * starting point omega = 0, b = v, lambda = 0, y_i = v into x.  Every instance must be
- * first order with one condition y(t_{i_1}) = v. */
+ * nyls_newton_init: build the basis (and, for p = 1, the constant Jacobian blocks) in `ws`
+ * and write the starting point omega = 0, lambda = 0, b = y_i = the value of the first
+ * condition on y itself (0 if there is none) into x. */
 int nyls_newton_init(const nyls_plan* plan, double* x, void* ws, hipStream_t stream);
 int64_t nyls_newton_state_stride(const nyls_plan* plan);
 
+/* The state values F is evaluated at, for the current x: u [p][total points] with
+ * u[0][i] = y_i (y_hat(t_i) at condition points) and, for p = 2, u[1][i] = y_hat'(t_i). */
+int nyls_newton_state(const nyls_plan* plan, const double* x, double* u, const void* ws,
+                      hipStream_t stream);
+
 /* One step x <- x - J^{-1} Y of Lemma 2's Newton method (Sec. 3.2).
- *   F, Fy, Fyy  [total points] F(t_i, y_i), dF/dy, d2F/dy2 at the current y_i (the caller
- *               owns the nonlinearity; passing Fyy = 0 gives the Gauss-Newton y-block)
- *   x           [batch][XS] in/out
- *   step_inf    [batch] |dx|_inf of this step (may be NULL)
- * The diagonal y-block d_i = gamma (1 + Fy^2 - rho_i Fyy) is eliminated first (Schur
- * complement on (omega, b, lambda)), so a step costs O(n m^2 + m^3); |d_i| < 1e-10 gamma
- * sets NYLS_S_SMALL_PIVOT.  Afterwards nyls_predict evaluates the current y_hat. */
-int nyls_newton_step(const nyls_plan* plan, const double* F, const double* Fy,
-                     const double* Fyy, double* x, double* step_inf, int32_t* status,
+ *   F    [total points] F at the state values u of nyls_newton_state
+ *   dF   [p][total points] dF/du_a (a = 0: y, a = 1: y')
+ *   d2F  [p][p][total points] d2F/du_a du_b (symmetric; zero gives the Gauss-Newton step)
+ *        (for p = 1 these are F, Fy and Fyy)
+ *   x    [batch][XS] in/out
+ *   step_inf  [batch] |dx|_inf of this step (may be NULL)
+ * The diagonal y-block d_i = gamma (1 + F_y^2 - rho_i F_yy) is eliminated first (Schur
+ * complement on (omega, b, lambda)), so a step costs O(n m^2 + m^3); for p = 2 the whole
+ * weighted Gram is formed again each step (the y' dependence makes every block depend on
+ * the iterate).  |d_i| < 1e-10 gamma sets NYLS_S_SMALL_PIVOT.  Afterwards nyls_predict
+ * evaluates the current y_hat. */
+int nyls_newton_step(const nyls_plan* plan, const double* F, const double* dF,
+                     const double* d2F, double* x, double* step_inf, int32_t* status,
                      void* ws, hipStream_t stream);
 
-/* The Riccati right-hand side F(t, y) = q(t) - y^2 of the nonlinear workload, evaluated
- * at the current Newton state x: F = q_i - y_i^2, Fy = -2 y_i, Fyy = -2 (0 when
- * gauss_newton != 0, i.e. the Gauss-Newton y-block).  q, F, Fy, Fyy are [total points]. */
+/* The Riccati right-hand side F(t, y) = q(t) - y^2 of the first-order nonlinear workload,
+ * evaluated at the current Newton state x: F = q_i - y_i^2, Fy = -2 y_i, Fyy = -2 (0 when
+ * gauss_newton != 0, i.e. the Gauss-Newton y-block).  q, F, Fy, Fyy are [total points].
+ * First-order plans only (else NYLS_E_NONLINEAR). */
 int nyls_riccati_eval(const nyls_plan* plan, const double* q, const double* x,
                       int32_t gauss_newton, double* F, double* Fy, double* Fyy,
                       hipStream_t stream);

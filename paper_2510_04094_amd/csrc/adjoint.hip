@@ -10,7 +10,10 @@
 //   2. beta = W mu_omega, nu_i = beta^T p_i + c_i mu_b,
 //      yh^(q)_i = alpha^T k^(q)_i + [q=0] b,  zh^(q)_i = beta^T k^(q)_i + [q=0] mu_b;
 //   3. dl/df_k(t_i) = gamma (e_i zh^(p-k)_i + nu_i yh^(p-k)_i), dl/dr(t_i) = gamma nu_i,
-//      dl/dv_j = mu_lambda_j, dl/dgamma = -sum_i nu_i e_i;
+//      dl/dv_j = mu_lambda_j, dl/dgamma = -sum_i nu_i e_i = mu_omega^T omega / gamma
+//      (the KKT rows give gamma G^T e = -(omega + H lambda), gamma c^T e = -delta^T lambda
+//      and H^T mu_omega + delta mu_b = 0; the sum over the points cancels by orders of
+//      magnitude at large gamma, the product of the two solution vectors does not);
 //   4. dl/dsigma = (terms through k^(q)(.) at fixed W, closed-form d/dsigma of the kernel
 //      derivatives) + (the K_mm term): the problem depends on W only via Q = W W^T =
 //      f(K_mm), f(l) = 1/l above the cut-off, so with dl/dW = g1 omega^T - g2 mu_omega^T
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(64) void k_backward(
   double* const an = ae + ML;
   double* const ug1 = an + ML;
   double* const ug2 = ug1 + ML;
-  double* const hkv = ug2 + ML;  // hkv[j * ML + s] = hkv[j * ML + s]
+  double* const hkv = ug2 + ML;  // hkv[j * ML + s]: k^(d_j)(t_{i_j}) at landmark s
   double* const xv = hkv + P * ML;
   double* const mu = xv + NKL;
   double* const R = mu + NKL;
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(64) void k_backward(
   __syncthreads();
 
   // 3. gradient pass
-  double aeacc[NB], anacc[NB], sne = 0.0, t2 = 0.0;
+  double aeacc[NB], anacc[NB], t2 = 0.0;
 #pragma unroll
   for (int b = 0; b < NB; ++b) aeacc[b] = anacc[b] = 0.0;
   {
@@ -367,7 +370,6 @@ __global__ __launch_bounds__(64) void k_backward(
       const double ei = okp ? tot[0] + st.c * bias - st.r : 0.0;
       const double nui = okp ? tot[1] + st.c * mub : 0.0;
       if (lane < 16 && ip < n) {
-        sne += nui * ei;
         t2 += half_sigma * (ei * tot[3] + nui * tot[2]);
         if (dl_dr) dl_dr[d.goff + ip] = gam * nui;
         if (dl_df) {
@@ -409,7 +411,6 @@ __global__ __launch_bounds__(64) void k_backward(
       an[16 * b + sl] = vn;
     }
   }
-  const double sum_nu_e = nyls_wave_sum(sne);
   t2 = nyls_wave_sum(t2);
   __syncthreads();
   for (int s = lane; s < m; s += 64) {
@@ -491,9 +492,12 @@ __global__ __launch_bounds__(64) void k_backward(
     tk += (k < r ? 1.0 : 2.0) * fkl * qb * dkl;
   }
   tk = nyls_wave_sum(tk);
+  double mw = 0.0;
+  for (int k = lane; k < r; k += 64) mw += mu[k] * xv[k];
+  mw = nyls_wave_sum(mw);
   if (lane == 0) {
     ws[L.info + 6] = (double)passes;
-    if (dl_dgamma) dl_dgamma[inst] = -sum_nu_e;
+    if (dl_dgamma) dl_dgamma[inst] = mw / gam;
     if (dl_dsigma) dl_dsigma[inst] = t1 - gam * t2 - t3 + tk;
   }
   if (dl_dv && lane < NYLS_MAX_P) dl_dv[inst * NYLS_MAX_P + lane] = lane < P ? mu[m + 1 + lane] : 0.0;

@@ -90,6 +90,9 @@ nyls_plan_view view(const nyls_plan* pl) {
   v.gcls_mask = pl->gcls_mask;
   v.tl_mask = pl->tl_mask;
   v.ntl_mask = pl->ntl_mask;
+  v.eig_ql = 0;
+  v.ql_lanes = 64;
+  v.overlap = 1;
   v.only = 0;
   return v;
 }
@@ -137,9 +140,15 @@ void nyls_prof_end(int k, hipStream_t st) {
 
 // accessors used by the other translation units
 int64_t nyls_plan_newton_stride(const nyls_plan* pl) {
-  return pl ? (int64_t)pl->maxm + 2 + pl->maxn : 0;
+  return pl ? (int64_t)pl->maxm + 1 + pl->maxp + pl->maxn : 0;
 }
 bool nyls_plan_first_order(const nyls_plan* pl) { return pl && pl->all_first_order; }
+// The ODE order shared by every instance of the plan, or 0 when the orders differ.
+int nyls_plan_common_order(const nyls_plan* pl) {
+  if (!pl) return 0;
+  const unsigned pm = pl->p_mask;
+  return (pm & (pm - 1)) ? 0 : __builtin_ctz(pm);
+}
 nyls_plan_view nyls_plan_get_view(const nyls_plan* pl) { return view(pl); }
 
 extern "C" {
@@ -176,7 +185,8 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
     {
       const double a = q.uniform ? q.dt / q.sigma : 0.0;
       d.rec = (q.uniform && a <= 0.25) ? 1 : 0;
-      d.pad_ = 0;
+      d.flags = (d.rec == 1 && nyls_walk_tail(q.m) != 0 ? NYLS_DF_TAIL : 0) |
+                ((nyls_gram_class(q.m) & 1) ? NYLS_DF_GRAM_TAIL : 0);
     }
     d.ws = wsd;
     d.goff = goff;
@@ -316,13 +326,13 @@ int nyls_assemble(const nyls_plan* pl, double* kkt, double* rhs, void* ws, hipSt
   return hip_rc(e);
 }
 
-int nyls_solve(const nyls_plan* pl, int32_t refine_steps, double* omega, double* bias,
-               double* lambda, double* yhat, int32_t* status, void* ws, hipStream_t stream) {
-  if (!pl || !yhat || !ws) return NYLS_E_NULL;
-  if (!pl->linear_ok) return NYLS_E_NULL;
-  if (refine_steps < 0 || refine_steps > 8) return NYLS_E_ARG;
+}  // extern "C"
+
+namespace {
+// The solve of nyls_solve with the workspace at w.
+int solve_impl(const nyls_plan* pl, int32_t refine_steps, double* omega, double* bias,
+               double* lambda, double* yhat, int32_t* status, double* w, hipStream_t stream) {
   const nyls_plan_view pv = view(pl);
-  double* w = static_cast<double*>(ws);
   hipError_t e = hipSuccess;
   if (pl->mode == NYLS_FP64_EXPLICIT) {
     double* scratch = w + pl->scratch_off;
@@ -403,6 +413,18 @@ int nyls_solve(const nyls_plan* pl, int32_t refine_steps, double* omega, double*
   }
   return hip_rc(e);
 }
+}  // namespace
+
+extern "C" {
+
+int nyls_solve(const nyls_plan* pl, int32_t refine_steps, double* omega, double* bias,
+               double* lambda, double* yhat, int32_t* status, void* ws, hipStream_t stream) {
+  if (!pl || !yhat || !ws) return NYLS_E_NULL;
+  if (!pl->linear_ok) return NYLS_E_NULL;
+  if (refine_steps < 0 || refine_steps > 8) return NYLS_E_ARG;
+  return solve_impl(pl, refine_steps, omega, bias, lambda, yhat, status, static_cast<double*>(ws),
+                    stream);
+}
 
 int nyls_predict(const nyls_plan* pl, const double* t_eval, const int64_t* eval_off, int32_t d,
                  double* out, const void* ws, hipStream_t stream) {
@@ -453,7 +475,7 @@ const char* nyls_error_string(int32_t code) {
     case NYLS_E_GRID: return "grid: dt <= 0 or explicit times missing / not ascending";
     case NYLS_E_LANDMARK: return "landmark indices not strictly ascending inside [0, n)";
     case NYLS_E_COND: return "condition order or index out of range, or duplicated";
-    case NYLS_E_NONLINEAR: return "Newton steps need first-order instances";
+    case NYLS_E_NONLINEAR: return "Newton calls need instances all of order 1 or all of order 2";
     case NYLS_E_HIP: return "HIP runtime error";
     case NYLS_E_ARG: return "argument out of range";
     case NYLS_S_TRUNCATED: return "basis truncated (r < m)";
@@ -462,6 +484,7 @@ const char* nyls_error_string(int32_t code) {
     case NYLS_S_EIG_NOCONV: return "eigensolver hit its sweep limit";
     case NYLS_S_SMALL_PIVOT: return "Newton diagonal block entry below 1e-10 gamma";
     case NYLS_S_REFINE_NOCONV: return "iterative refinement did not reach rounding level";
+    case NYLS_S_FP64_RESOLVED: return "solved again with the FP64 Gram";
     default: return "unknown code";
   }
 }

@@ -21,7 +21,16 @@
 struct nyls_plan;
 int64_t nyls_plan_newton_stride(const nyls_plan* pl);
 bool nyls_plan_first_order(const nyls_plan* pl);
+int nyls_plan_common_order(const nyls_plan* pl);
 nyls_plan_view nyls_plan_get_view(const nyls_plan* pl);
+// second-order nonlinear path (newton_gen.hip)
+hipError_t nyls_launch_newton2_init(const nyls_plan_view& pv, double* ws, double* x, int64_t xs,
+                                    hipStream_t st);
+hipError_t nyls_launch_newton_state(const nyls_plan_view& pv, const double* ws, const double* x,
+                                    int64_t xs, double* u, hipStream_t st);
+hipError_t nyls_launch_newton2_step(const nyls_plan_view& pv, double* ws, const double* F,
+                                    const double* dF, const double* d2F, double* x, int64_t xs,
+                                    double* step_inf, int32_t* status, hipStream_t st);
 
 namespace {
 
@@ -386,6 +395,7 @@ extern "C" int nyls_riccati_eval(const nyls_plan* pl, const double* q, const dou
                                  int32_t gauss_newton, double* F, double* Fy, double* Fyy,
                                  hipStream_t stream) {
   if (!pl || !q || !x || !F || !Fy || !Fyy) return NYLS_E_NULL;
+  if (!nyls_plan_first_order(pl)) return NYLS_E_NONLINEAR;
   const nyls_plan_view pv = nyls_plan_get_view(pl);
   int gx = (pv.maxn + NYLS_BLOCK - 1) / NYLS_BLOCK;
   gx = gx > 64 ? 64 : gx;
@@ -398,11 +408,16 @@ extern "C" int64_t nyls_newton_state_stride(const nyls_plan* pl) { return nyls_p
 
 extern "C" int nyls_newton_init(const nyls_plan* pl, double* x, void* ws, hipStream_t stream) {
   if (!pl || !x || !ws) return NYLS_E_NULL;
-  if (!nyls_plan_first_order(pl)) return NYLS_E_NONLINEAR;
+  const int order = nyls_plan_common_order(pl);
+  if (order != 1 && order != 2) return NYLS_E_NONLINEAR;
   const nyls_plan_view pv = nyls_plan_get_view(pl);
   double* w = static_cast<double*>(ws);
   hipError_t e = nyls_launch_eig(pv, w, -1, stream);
   if (e != hipSuccess) return NYLS_E_HIP;
+  if (order == 2) {
+    e = nyls_launch_newton2_init(pv, w, x, (int64_t)nyls_plan_newton_stride(pl), stream);
+    return e == hipSuccess ? NYLS_OK : NYLS_E_HIP;
+  }
   const size_t lds = init_lds_bytes(pv.maxm);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_newton_init),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -411,12 +426,31 @@ extern "C" int nyls_newton_init(const nyls_plan* pl, double* x, void* ws, hipStr
   return hipGetLastError() == hipSuccess ? NYLS_OK : NYLS_E_HIP;
 }
 
+extern "C" int nyls_newton_state(const nyls_plan* pl, const double* x, double* u, const void* ws,
+                                 hipStream_t stream) {
+  if (!pl || !x || !u || !ws) return NYLS_E_NULL;
+  const int order = nyls_plan_common_order(pl);
+  if (order != 1 && order != 2) return NYLS_E_NONLINEAR;
+  const hipError_t e = nyls_launch_newton_state(nyls_plan_get_view(pl), static_cast<const double*>(ws),
+                                                x, (int64_t)nyls_plan_newton_stride(pl), u, stream);
+  return e == hipSuccess ? NYLS_OK : NYLS_E_HIP;
+}
+
 extern "C" int nyls_newton_step(const nyls_plan* pl, const double* F, const double* Fy,
                                 const double* Fyy, double* x, double* step_inf, int32_t* status,
                                 void* ws, hipStream_t stream) {
   if (!pl || !F || !Fy || !Fyy || !x || !ws) return NYLS_E_NULL;
-  if (!nyls_plan_first_order(pl)) return NYLS_E_NONLINEAR;
+  const int order = nyls_plan_common_order(pl);
+  if (order != 1 && order != 2) return NYLS_E_NONLINEAR;
   const nyls_plan_view pv = nyls_plan_get_view(pl);
+  if (order == 2) {
+    nyls_prof_begin(NYLS_K_NEWTON, stream);
+    const hipError_t e = nyls_launch_newton2_step(pv, static_cast<double*>(ws), F, Fy, Fyy, x,
+                                                  (int64_t)nyls_plan_newton_stride(pl), step_inf,
+                                                  status, stream);
+    nyls_prof_end(NYLS_K_NEWTON, stream);
+    return e == hipSuccess ? NYLS_OK : NYLS_E_HIP;
+  }
   const size_t lds = step_lds_bytes(pv.maxm);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_newton_step),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

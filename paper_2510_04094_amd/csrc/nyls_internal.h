@@ -20,10 +20,17 @@ struct nyls_desc {
   int32_t cond_i[NYLS_MAX_P];
   int32_t rec;           // 1: uniform grid with dt <= sigma / 4: the strided Gaussian
                          // recurrence of the one-wave passes needs no exact exponentials
-  int32_t pad_;
+  int32_t flags;         // NYLS_DF_* launch choices of the plan's tuning for this instance
   double sigma, gamma, tau;
   int64_t ws;            // first double of this instance's workspace block
   int64_t goff;          // first grid point of this instance in per-point outputs
+};
+
+// nyls_desc::flags: which kernel variant takes the instance (set from the plan's tuning).
+enum {
+  NYLS_DF_TAIL = 1,       // one-wave passes walk a last block of <= 4 landmarks in the tail layout
+  NYLS_DF_GRAM_TAIL = 2,  // one-wave MFMA Gram accumulates a last block of <= 4 columns on the VALU
+  NYLS_DF_GRAM_VALU = 4   // FP64 Gram on the LDS-tile VALU kernel even when m + 2 <= 64
 };
 
 // Per-instance workspace block (offsets in doubles from nyls_desc::ws).
@@ -179,14 +186,21 @@ __device__ inline double nyls_bload(__amdgpu_buffer_rsrc_t r, int off_bytes) {
 }
 
 // Start of a run of `len` uniform-grid points k0, k0 + stride, ... (offsets from a landmark,
-// a = dt / sigma) for the recurrence e(k + stride) = e(k) rv(k), rv(k + stride) = rv(k) q,
-// q = exp(-2 a^2 stride^2).  Returns true when the run must use exact exponentials instead: the
-// ratio would overflow, or the run starts below exp(-700) (denormal or zero, so the
-// relative precision is gone) while approaching the landmark and rising above that level
-// inside the run.  Runs that stay below exp(-700) keep the recurrence: their values are
-// negligible in absolute terms.
+// a = dt / sigma) for the Gaussian recurrence.  With Q = exp(-2 a^2 stride^2) and
+// R(k) = exp(-a^2 stride (2 k + stride)) the exact identities are
+//     e(k + stride) = e(k) R(k),   R(k + stride) = R(k) Q.
+// The walk carries rho = R - 1 instead of R (from expm1), and steps with
+//     e <- fma(e, rho, e),   rho <- fma(rho, Q, Q - 1)   (Q - 1 also from expm1):
+// where the values matter |rho| is small, so the roundings of rho (and of Q) perturb R by
+// about |rho| eps rather than eps.  Carrying R itself lets a rounding of R tilt the relative
+// error of all later values of the run by the same amount, a smooth error that the
+// ill-conditioned solves amplify much more than independent per-value roundings.
+// Returns true when the run must use exact exponentials instead: the ratio would overflow,
+// or the run starts below exp(-700) (denormal or zero, so the relative precision is gone)
+// while approaching the landmark and rising above that level inside the run.  Runs that
+// stay below exp(-700) keep the recurrence: their values are negligible in absolute terms.
 __device__ inline bool nyls_gauss_start(int k0, int len, int stride, double a, double& ev,
-                                        double& rv) {
+                                        double& rho) {
   const double z0 = (double)k0 * a;
   const double rexp = -a * a * (double)stride * (2.0 * k0 + stride);
   if (rexp > 700.0) return true;
@@ -196,36 +210,41 @@ __device__ inline bool nyls_gauss_start(int k0, int len, int stride, double a, d
     if (ke >= 0 || ze * ze < 700.0) return true;
   }
   ev = exp(-z0 * z0);
-  rv = exp(rexp);
+  rho = expm1(rexp);
   return false;
+}
+
+// One step of the recurrence above: e(k + stride) and rho(k + stride) from e(k), rho(k).
+__device__ inline void nyls_gauss_step(double& ev, double& rho, double q, double qm1) {
+  ev = fma(ev, rho, ev);
+  rho = fma(rho, q, qm1);
 }
 
 // Gaussian values over a tile of TP consecutive grid points i = i0 + pt and all landmarks:
 // calls emit(pt, s, z, e) with z = (t_i - t_s)/sigma and e = exp(-z^2) (e = 0 for i >= n).
 // Work is split as thread -> (landmark s, chunk of CH points).  On a uniform grid
 // t_i - t_s = (i - i_s) dt, so along a chunk, with a = dt/sigma and k = i - i_s,
-//     e(k+1) = e(k) R(k),  R(k) = exp(-a^2 (2k+1)),  R(k+1) = R(k) exp(-2 a^2):
-// two multiplies per value after two exponentials per chunk (relative error <= ~CH^2 eps).
-// Chunks that nyls_gauss_start rejects use one exponential per point instead.
+//     e(k+1) = e(k) R(k),  R(k) = exp(-a^2 (2k+1)),  R(k+1) = R(k) exp(-2 a^2),
+// stepped as in nyls_gauss_start (two multiply-adds per value after two exponentials per
+// chunk).  Chunks that nyls_gauss_start rejects use one exponential per point instead.
 template <int TP, int CH, typename Emit>
 __device__ inline void nyls_gauss_tile(const nyls_desc& d, int i0, const double* tl,
                                        double inv_sigma, Emit emit) {
   constexpr int NC = TP / CH;
   const int m = d.m, n = d.n;
   const double a = d.dt * inv_sigma;
-  const double q2 = exp(-2.0 * a * a);
+  const double q2 = exp(-2.0 * a * a), q2m1 = expm1(-2.0 * a * a);
   for (int e = threadIdx.x; e < m * NC; e += NYLS_BLOCK) {
     const int s = e % m, c = e / m;
     const int ib = i0 + c * CH;
     if (d.uniform) {
       const int k0 = ib - d.lidx[s];
-      double ev = 0.0, rv = 0.0;
-      if (!nyls_gauss_start(k0, CH, 1, a, ev, rv)) {
+      double ev = 0.0, rho = 0.0;
+      if (!nyls_gauss_start(k0, CH, 1, a, ev, rho)) {
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
           emit(c * CH + j, s, (double)(k0 + j) * a, (ib + j < n) ? ev : 0.0);
-          ev *= rv;
-          rv *= q2;
+          nyls_gauss_step(ev, rho, q2, q2m1);
         }
       } else {
 #pragma unroll
@@ -316,6 +335,9 @@ struct nyls_plan_view {
   unsigned gcls_mask;       // bit nyls_gram_class(m) for the instances with m + 2 <= 64
   unsigned tl_mask;         // bit b: some rec == 1 instance of slot class b walks a tail layout
   unsigned ntl_mask;        // bit b: some instance of slot class b does not
+  int32_t eig_ql;           // tuning: 1 QL inside one wavefront per instance (m <= 64)
+  int32_t ql_lanes;         // tuning: instances per wavefront of the lane-parallel QL
+  int32_t overlap;          // tuning: FP64 kernel-space Gram beside the eigensolver
 };
 
 // `single` >= 0 restricts a launch to that one instance (one workgroup).
@@ -344,38 +366,3 @@ hipError_t nyls_launch_explicit_rows(const nyls_plan_view& pv, int inst, const d
                                      hipStream_t st);
 hipError_t nyls_launch_explicit_kkt(const nyls_plan_view& pv, int inst, double* ws,
                                     const double* phi, const double* C, hipStream_t st);
-
-// Single-wavefront form of the Gaussian recurrence: the calling lane owns landmark grid
-// index `ls` and walks CP consecutive points i0..i0+CP-1, calling emit(jj, z, e) with
-// z = (t_i - t_s)/sigma and e = exp(-z^2) (0 past the grid).  Same recurrence and guards
-// as nyls_gauss_tile (two exponentials per chunk on a uniform grid).
-template <int CP, typename Emit>
-__device__ inline void nyls_wave_gauss(const nyls_desc& d, int i0, int ls, double tls, double a,
-                                       double q2, double inv_sigma, Emit emit) {
-  const int n = d.n;
-  if (d.uniform) {
-    const int k0 = i0 - ls;
-    double ev = 0.0, rv = 0.0;
-    if (!nyls_gauss_start(k0, CP, 1, a, ev, rv)) {
-#pragma unroll
-      for (int j = 0; j < CP; ++j) {
-        emit(j, (double)(k0 + j) * a, (i0 + j < n) ? ev : 0.0);
-        ev *= rv;
-        rv *= q2;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < CP; ++j) {
-        const double z = (double)(k0 + j) * a;
-        emit(j, z, (i0 + j < n) ? exp(-z * z) : 0.0);
-      }
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < CP; ++j) {
-      const int i = i0 + j;
-      const double z = i < n ? (d.t[i] - tls) * inv_sigma : 0.0;
-      emit(j, z, i < n ? exp(-z * z) : 0.0);
-    }
-  }
-}

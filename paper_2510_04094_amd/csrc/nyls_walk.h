@@ -15,9 +15,10 @@
 // Kernel values: on a uniform grid t_i - t_s = k dt with k = i - i_s.  Along one lane's
 // points k advances by 4, so with a = dt / sigma
 //     e(k + 4) = e(k) R(k),  R(k) = exp(-a^2 (8 k + 16)),  R(k + 4) = R(k) exp(-32 a^2),
-// restarted with two exponentials every 64 points (runs of 16 values per lane).  Next to e
-// the walk carries g = -2 (t_i - t_s) / sigma^2, the first Hermite factor, which also
-// advances by a constant.
+// restarted with two exponentials every 64 points (runs of 16 values per lane).  R is
+// carried as rho = R - 1 (nyls_gauss_start / nyls_gauss_step), which keeps the run's
+// relative error at the level of independent roundings.  Next to e the walk carries
+// g = -2 (t_i - t_s) / sigma^2, the first Hermite factor, which also advances by a constant.
 #pragma once
 #include "nyls_internal.h"
 
@@ -105,8 +106,9 @@ __device__ inline double nyls_horner(double g, const double (&c)[D]) {
 // lane = 4 pt + ts takes tail slot ts (landmark 16 (NB - 1) + ts, used when below m) for the
 // single chunk point i0 + pt, 16 points further each chunk:
 //     e(k + 16) = e(k) R16(k),  R16(k) = exp(-a^2 (32 k + 256)),  R16(k + 16) = R16(k) exp(-512 a^2),
-// restarted with the other runs every 64 points.  The per-lane arrays keep all NB blocks (the
-// landmark data of the last block stays usable in the block layout).
+// (R16 carried as R16 - 1), restarted with the other runs every 64 points.  The per-lane
+// arrays keep all NB blocks (the landmark data of the last block stays usable in the block
+// layout).
 template <int NB, bool EX, bool TL = false>
 struct nyls_walk {
   static_assert(!(TL && EX), "the tail layout is for instances with rec == 1");
@@ -114,13 +116,13 @@ struct nyls_walk {
   int sl, ph, n;
   bool lv[NB];
   int ls[NB];
-  double ev[NB], rv[NB], gc[NB];
+  double ev[NB], rv[NB], gc[NB];  // e, rho = R - 1 and g of the lane's run per block
   bool exact;  // wave-uniform: this run of 64 points uses one exponential per value
-  double ga4, q4, inv_sigma, a, gk;  // gk: g per grid step k
+  double ga4, q4, q4m1, inv_sigma, a, gk;  // gk: g per grid step k; q4m1 = q4 - 1
   __amdgpu_buffer_rsrc_t tr;  // grid times (non-uniform grids)
   int tpt, tts, tls;          // tail layout: chunk point, tail slot, landmark grid index
   bool tlv;
-  double te, tr16, tg, q16, g16;
+  double te, tr16, tg, q16, q16m1, g16;
 
   __device__ void init(const nyls_desc& d, int lane) {
     sl = lane & 15;
@@ -131,6 +133,7 @@ struct nyls_walk {
     gk = -2.0 * inv_sigma * a;
     ga4 = 4.0 * gk;
     q4 = exp(-32.0 * a * a);
+    q4m1 = expm1(-32.0 * a * a);
     exact = EX && !d.uniform;
     tr = nyls_rsrc(EX && !d.uniform ? d.t : nullptr, EX && !d.uniform ? n * 8 : 0);
 #pragma unroll
@@ -145,6 +148,7 @@ struct nyls_walk {
     tlv = TL && 16 * (NB - 1) + tts < d.m;
     tls = tlv ? d.lidx[16 * (NB - 1) + tts] : 0;
     q16 = TL ? exp(-512.0 * a * a) : 0.0;
+    q16m1 = TL ? expm1(-512.0 * a * a) : 0.0;
     g16 = 16.0 * gk;
     te = tr16 = tg = 0.0;
   }
@@ -161,9 +165,9 @@ struct nyls_walk {
         const int k0 = i0 + tpt - tls;
         const double z0 = (double)k0 * a;
         const bool far = k0 < 0 && z0 * z0 > 700.0;
-        const double e0 = exp(-z0 * z0), r0 = exp(-a * a * (32.0 * k0 + 256.0));
+        const double e0 = exp(-z0 * z0), r0 = expm1(-a * a * (32.0 * k0 + 256.0));
         te = far ? 0.0 : e0;
-        tr16 = far ? 0.0 : r0;
+        tr16 = far ? -1.0 : r0;
         tg = (double)k0 * gk;
       }
 #pragma unroll
@@ -177,9 +181,9 @@ struct nyls_walk {
           // zero; every other run starts from normal numbers and its ratio cannot overflow.
           const double z0 = (double)k0 * a;
           const bool far = k0 < 0 && z0 * z0 > 700.0;
-          const double e0 = exp(-z0 * z0), r0 = exp(-a * a * 4.0 * (2.0 * k0 + 4.0));
+          const double e0 = exp(-z0 * z0), r0 = expm1(-a * a * 4.0 * (2.0 * k0 + 4.0));
           ev[b] = far ? 0.0 : e0;
-          rv[b] = far ? 0.0 : r0;
+          rv[b] = far ? -1.0 : r0;
         }
         gc[b] = (double)k0 * gk;
       }
@@ -201,16 +205,14 @@ struct nyls_walk {
 #pragma unroll
         for (int b = 0; b < NM; ++b) {
           emit(b, j, gc[b], ev[b]);
-          ev[b] *= rv[b];
-          rv[b] *= q4;
+          nyls_gauss_step(ev[b], rv[b], q4, q4m1);
           gc[b] += ga4;
         }
         done(j);
       }
       if (TL) {
         tail(tg, te);
-        te *= tr16;
-        tr16 *= q16;
+        nyls_gauss_step(te, tr16, q16, q16m1);
         tg += g16;
       }
     } else {

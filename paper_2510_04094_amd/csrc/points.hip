@@ -199,7 +199,9 @@ __global__ __launch_bounds__(64) void k_points(
   //  * after a solve, when the change this correction will make is predicted below
   //    tol_stop: the change just measured (of the previous correction) times the ratio of
   //    the two corrections' bounds, i.e. the contraction of the iteration seen so far.
-  // Otherwise the last correction is followed by an output pass (which also measures it).
+  //    Then no further residual is formed, but the output pass still applies the correction.
+  // Otherwise (or when the step limit is reached) the last correction is followed by an
+  // output pass, which also measures it.
   double corr = 0.0, dprev = 0.0, ymax = 0.0, bprev = 0.0;
   bool need_output = true;
   int passes = 0;
@@ -271,12 +273,15 @@ __global__ __launch_bounds__(64) void k_points(
     double dsq = 0.0;
     for (int k = lane; k < r; k += 64) dsq += Rv[k] * Rv[k];
     const double bound = sqrt(nyls_wave_sum(dsq)) + fabs(Rv[m]);
-    const double pred = step > 0 && bprev > 0.0 ? corr * (bound / bprev) : bound;
-    if (bound <= tol_stop * ymax || pred <= tol_stop * ymax) {
-      corr = fmin(bound, pred);
+    if (bound <= tol_stop * ymax) {
+      corr = bound;
       need_output = false;
       break;
     }
+    // predicted to be the last correction: the output pass below applies it to y_hat and
+    // measures it (so y_hat, x and alpha agree, and the recorded change is a measured one)
+    const double pred = step > 0 && bprev > 0.0 ? corr * (bound / bprev) : bound;
+    if (pred <= tol_stop * ymax) break;
     bprev = bound;
   }
   if (need_output) {

@@ -61,11 +61,17 @@ EXPORTS = {
                                         ctypes.c_void_p]),
     "nyls_newton_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nyls_newton_state_stride": (ctypes.c_int64, [ctypes.c_void_p]),
+    "nyls_newton_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
     "nyls_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nyls_riccati_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nyls_leverage_scores": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
+    "nyls_leverage_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
     "nyls_profile_enable": (None, [ctypes.c_int32]),
     "nyls_profile_read": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "nyls_profile_reset": (None, []),
@@ -204,6 +210,8 @@ class Batch:
         self.total = int(lib.nyls_total_points(handle))
         nbytes = int(lib.nyls_workspace_size(handle))
         self.ws = torch.zeros(max(nbytes, 8), dtype=torch.uint8, device=self.device)
+        # bumped by every call that leaves a new basis / factorisation / solution in ws
+        self.ws_version = 0
 
     def __del__(self):
         if getattr(self, "plan", None) is not None and _lib is not None:
@@ -230,6 +238,7 @@ class Batch:
         _check(_lib.nyls_solve(self.plan, refine, _ptr(out["omega"]), _ptr(out["bias"]), _ptr(out["lam"]),
                                _ptr(out["yhat"]), _ptr(out["status"]), _ptr(self.ws), _stream()),
                "nyls_solve")
+        self.ws_version += 1
         return out
 
     def assemble(self):
@@ -237,6 +246,7 @@ class Batch:
         kkt = torch.zeros(self.batch, kn * kn, dtype=torch.float64, device=self.device)
         rhs = torch.zeros(self.batch, kn, dtype=torch.float64, device=self.device)
         _check(_lib.nyls_assemble(self.plan, _ptr(kkt), _ptr(rhs), _ptr(self.ws), _stream()), "nyls_assemble")
+        self.ws_version += 1
         return kkt, rhs
 
     def _offsets(self, t_eval_list):
@@ -255,6 +265,7 @@ class Batch:
         rank = torch.empty(self.batch, dtype=torch.int32, device=self.device)
         _check(_lib.nyls_features(self.plan, _ptr(t), _ptr(o), dmax, _ptr(phi), _ptr(eig), _ptr(rank),
                                   _ptr(self.ws), _stream()), "nyls_features")
+        self.ws_version += 1
         return phi, eig, rank, off
 
     def predict(self, t_eval_list, d=0):
@@ -264,22 +275,76 @@ class Batch:
                "nyls_predict")
         return out, off
 
+    # --- landmark sampling ---------------------------------------------------------------
+    def leverage_scores(self, ridge=0.0):
+        """nyls_leverage_scores: ridge leverage scores [total] of every grid point in the
+        feature space of this plan's basis (ridge 0: 1/gamma per instance)."""
+        out = torch.empty(self.total, dtype=torch.float64, device=self.device)
+        _check(_lib.nyls_leverage_scores(self.plan, float(ridge), _ptr(out), _ptr(self.ws), _stream()),
+               "nyls_leverage_scores")
+        self.ws_version += 1
+        return out
+
+    def leverage_landmarks(self, uniforms, ends=True, ridge=0.0):
+        """Leverage-score landmarks of every instance (nyls_leverage_scores, then
+        nyls_leverage_sample with the caller's uniforms [total] or per-instance list):
+        returns (scores, list of ascending int64 index arrays) for new instances' lidx."""
+        scores = self.leverage_scores(ridge)
+        if not torch.is_tensor(uniforms):
+            uniforms = torch.tensor(np.concatenate([np.asarray(u, dtype=np.float64) for u in uniforms]),
+                                    dtype=torch.float64, device=self.device)
+        lidx = torch.empty(self.batch, self.maxm, dtype=torch.int32, device=self.device)
+        _check(_lib.nyls_leverage_sample(self.plan, _ptr(scores), _ptr(uniforms.contiguous()),
+                                         1 if ends else 0, _ptr(lidx), _stream()), "nyls_leverage_sample")
+        host = lidx.cpu().numpy()
+        return scores, [host[i, :int(self.m[i])].astype(np.int64) for i in range(self.batch)]
+
     # --- nonlinear (Lemma 2) -----------------------------------------------------------
     def newton_init(self):
         """nyls_newton_init: returns the state tensor x [batch, stride]."""
         stride = int(_lib.nyls_newton_state_stride(self.plan))
         x = torch.zeros(self.batch, stride, dtype=torch.float64, device=self.device)
         _check(_lib.nyls_newton_init(self.plan, _ptr(x), _ptr(self.ws), _stream()), "nyls_newton_init")
+        self.ws_version += 1
         self._newton_bufs = [torch.empty(self.total, dtype=torch.float64, device=self.device) for _ in range(3)]
         self._step_inf = torch.empty(self.batch, dtype=torch.float64, device=self.device)
         self._status = torch.empty(self.batch, dtype=torch.int32, device=self.device)
         return x
 
-    def newton_step(self, x, F, Fy, Fyy):
-        """nyls_newton_step with caller-evaluated F, Fy, Fyy [total points]; returns step_inf."""
-        _check(_lib.nyls_newton_step(self.plan, _ptr(F), _ptr(Fy), _ptr(Fyy), _ptr(x), _ptr(self._step_inf),
+    def newton_step(self, x, F, dF, d2F):
+        """nyls_newton_step with caller-evaluated F [total], dF [p, total], d2F [p, p, total]
+        (contiguous; for first-order plans Fy and Fyy [total]); returns step_inf [batch]."""
+        _check(_lib.nyls_newton_step(self.plan, _ptr(F), _ptr(dF), _ptr(d2F), _ptr(x), _ptr(self._step_inf),
                                      _ptr(self._status), _ptr(self.ws), _stream()), "nyls_newton_step")
+        self.ws_version += 1
         return self._step_inf
+
+    def newton_state(self, x):
+        """nyls_newton_state: u [p, total] with u[0] = y_i and, for p = 2, u[1] = y_hat'(t_i)."""
+        p = int(self.p.max())
+        u = torch.empty(p, self.total, dtype=torch.float64, device=self.device)
+        _check(_lib.nyls_newton_state(self.plan, _ptr(x), _ptr(u), _ptr(self.ws), _stream()),
+               "nyls_newton_state")
+        return u
+
+    def newton_solve(self, fun, max_iter=30, tol=1e-12, gauss_newton_steps=5):
+        """Newton on y^(p) = F(t, y, .., y^(p-1)) for every instance.  fun(u, gauss_newton)
+        maps the state values u [p, total] (nyls_newton_state) to (F [total], dF [p, total],
+        d2F [p, p, total]) on the device; the first `gauss_newton_steps` steps pass zero
+        second derivatives (Gauss-Newton).  Stops when every instance's |dx|_inf <= tol *
+        max(1, |x|_inf).  Returns (x, steps [iters, batch])."""
+        x = self.newton_init()
+        hist = []
+        for k in range(max_iter):
+            F, dF, d2F = fun(self.newton_state(x), k < gauss_newton_steps)
+            if k < gauss_newton_steps:
+                d2F = torch.zeros_like(d2F)
+            si = self.newton_step(x, F.contiguous(), dF.contiguous(), d2F.contiguous()).clone()
+            hist.append(si)
+            xinf = torch.clamp(torch.max(torch.abs(x), dim=1).values, min=1.0)
+            if bool(torch.all(si <= tol * xinf)):
+                break
+        return x, torch.stack(hist)
 
     def riccati_eval(self, q, x, gauss_newton):
         F, Fy, Fyy = self._newton_bufs
@@ -376,7 +441,7 @@ class SolveAtObservations(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, batch, t_obs_list, f, r, v, sigma, gamma):
+    def _load_and_solve(batch, f, r, v, sigma, gamma):
         with torch.no_grad():
             batch.f.copy_(f.detach().reshape(-1))
             batch.r.copy_(r.detach().reshape(-1))
@@ -387,15 +452,26 @@ class SolveAtObservations(torch.autograd.Function):
             if not (np.array_equal(s_new, s_old) and np.array_equal(g_new, g_old)):
                 batch.set_params(sigma=s_new, gamma=g_new)
             batch.solve()
+        return batch.ws_version
+
+    @staticmethod
+    def forward(ctx, batch, t_obs_list, f, r, v, sigma, gamma):
+        ctx.ws_version = SolveAtObservations._load_and_solve(batch, f, r, v, sigma, gamma)
+        with torch.no_grad():
             y, _ = batch.predict(t_obs_list, 0)
         ctx.batch = batch
         ctx.t_obs_list = t_obs_list
         ctx.shapes = (f.shape, r.shape, v.shape)
+        ctx.save_for_backward(f.detach(), r.detach(), v.detach(), sigma.detach(), gamma.detach())
         return y
 
     @staticmethod
     def backward(ctx, grad_y):
         b = ctx.batch
+        if b.ws_version != ctx.ws_version:
+            # the batch's workspace holds another solve (e.g. a second forward before this
+            # backward): solve this graph's inputs again so the adjoint reuses its own factors
+            SolveAtObservations._load_and_solve(b, *ctx.saved_tensors)
         out = b.backward(ctx.t_obs_list, grad_y.detach())
         fs, rs, vs = ctx.shapes
         df = out["dl_df"].reshape(-1)[b.f_index()].reshape(fs)

@@ -50,7 +50,7 @@ def test_backward_matches_oracle(gpu_lib, mode_name):
         # a truncated basis): bound the error by 1e-5 of the value plus 1e-8 of its terms
         scale = 1e-5 * abs(ref["dl_dsigma"]) + 1e-8 * np.max(np.abs(ref["sigma_terms"]))
         assert abs(out["dl_dsigma"][i] - ref["dl_dsigma"]) <= scale, ("dsigma", i, out["dl_dsigma"][i], ref["dl_dsigma"])
-        assert rel(out["dl_dgamma"][i], ref["dl_dgamma"]) <= 1e-3, ("dgamma", i)
+        assert rel(out["dl_dgamma"][i], ref["dl_dgamma"]) <= 1e-5, ("dgamma", i)
 
 
 def test_backward_with_random_landmarks(gpu_lib):
@@ -71,6 +71,7 @@ def test_backward_with_random_landmarks(gpu_lib):
             assert rel(out["dl_dv"][i, j], ref["dl_dv"][j]) <= 1e-5, ("dv", i, j)
         scale = 1e-5 * abs(ref["dl_dsigma"]) + 1e-8 * np.max(np.abs(ref["sigma_terms"]))
         assert abs(out["dl_dsigma"][i] - ref["dl_dsigma"]) <= scale, ("dsigma", i)
+        assert rel(out["dl_dgamma"][i], ref["dl_dgamma"]) <= 1e-5, ("dgamma", i)
 
 
 def gpu_loss(gpu_lib, insts):
@@ -83,9 +84,24 @@ def gpu_loss(gpu_lib, insts):
 
 def test_parameter_gradients_match_central_differences(gpu_lib):
     """Config-5 style check: alpha_0, alpha_1 (a(t) = a0 + a1 cos t enters as f_2 = -a),
-    y0, y'0 with h = 1e-6, sigma with a relative step, all through GPU forward solves."""
+    y0, y'0 with h = 1e-6, sigma with a relative step, all through GPU forward solves.
+    gamma: dl/dlog(gamma) is 1e-11..1e-9 on these instances, so a 1e-6 step changes the loss
+    by less than the FP64 rounding of the loss itself (the FP64 oracle's own difference at
+    that step is off by 10..100x); it is checked with steps of 0.2 and 0.1 in log(gamma) and
+    Richardson extrapolation (the oracle's own such difference agrees with its gradient to
+    4e-4 on these instances), against a 2e-3 bar.  The oracle's dl/dgamma is pinned to a
+    50-digit solve, and the kernel's to the oracle at 1e-5, in the other tests."""
     insts = instances(4)
     b, out, _ = gpu_gradients(gpu_lib, insts, gpu_lib.FP64)
+    g_rich = []
+    for hg in (0.2, 0.1):
+        plus = [dict(q, gamma=q["gamma"] * np.exp(hg)) for q in insts]
+        minus = [dict(q, gamma=q["gamma"] * np.exp(-hg)) for q in insts]
+        g_rich.append((gpu_loss(gpu_lib, plus) - gpu_loss(gpu_lib, minus)) / (2 * hg))
+    fd_g = (4 * g_rich[1] - g_rich[0]) / 3
+    for i, q in enumerate(insts):
+        got = out["dl_dgamma"][i] * q["gamma"]
+        assert abs(got - fd_g[i]) <= 2e-3 * abs(fd_g[i]), ("gamma", i, got, fd_g[i])
     h = 1e-6
     for name in ["a0", "a1", "y0", "dy0", "sigma"]:
         plus, minus = [], []
@@ -171,3 +187,32 @@ def test_autograd_function_matches_directional_differences(gpu_lib):
         tol = 1e-2 if which == 4 else 1e-4
         scale = float(torch.sum(torch.abs(grads[which] * direction)))
         assert abs(ad - fd) <= tol * max(abs(fd), 1e-12) + 1e-9 * scale, (which, ad, fd)
+
+
+def test_autograd_two_forwards_then_one_backward(gpu_lib):
+    """Two losses from two forwards of one Batch at different data, summed into one
+    backward: each graph's gradient must come from its own solve, not from whatever the
+    shared workspace holds last."""
+    insts = instances(2)
+    b = gpu_lib.Batch(insts, mode=gpu_lib.FP64)
+    dev = b.f.device
+    t_obs = [q["t_obs"] for q in insts]
+    y_obs = torch.tensor(np.concatenate([q["y_obs"] for q in insts]), device=dev)
+    f0, r0, v0 = b.f.clone(), b.r.clone(), b.v.clone().reshape(b.batch, gpu_lib.MAX_P)
+    s0 = torch.tensor([q["sigma"] for q in insts], dtype=torch.float64, device=dev)
+    g0 = torch.tensor([q["gamma"] for q in insts], dtype=torch.float64, device=dev)
+
+    def grads(fs):
+        xs = [f.clone().requires_grad_(True) for f in fs]
+        total = 0
+        for f in xs:
+            y = gpu_lib.solve_at_observations(b, t_obs, f, r0, v0, s0, g0)
+            total = total + torch.mean((y - y_obs) ** 2)
+        total.backward()
+        return [x.grad.clone() for x in xs]
+
+    f1 = f0 * 1.05
+    both = grads([f0, f1])
+    alone = [grads([f0])[0], grads([f1])[0]]
+    for got, ref in zip(both, alone):
+        assert torch.max(torch.abs(got - ref)).item() <= 1e-9 * torch.max(torch.abs(ref)).item()

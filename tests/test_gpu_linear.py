@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 import torch
 
+import fp64_floor
 import oracle
 from paper_2510_04094_amd import workloads
 
@@ -98,17 +99,17 @@ def test_fp64_solve_config1_ragged(gpu_lib):
 
 
 def test_fp64_solve_config2_ragged(gpu_lib):
-    """Second order, several tiles and a ragged last tile (n not a multiple of 64).  For this
-    family K_mm keeps eigenvalues down to 1e-8 lambda_1, and kernel values with relative
-    error ~1e-14 (FP64 recurrence) move y_hat by up to ~3e-10: the bar is 1e-9 here (the
-    family's own bar is 1e-6; the 1e-10 bar holds for the well-conditioned FP64 configs)."""
+    """Second order, several tiles and a ragged last tile (n not a multiple of 64), at the
+    FP64 bar (1e-10, or the oracle's own 1-ulp K_mm floor where larger: instance 1 keeps an
+    eigenvalue at 1.5e-8 lambda_1, just above the cut-off)."""
     insts = [workloads.linear_second_order(i, n=1237 + 97 * i, m=50) for i in range(6)]
     b = gpu_lib.Batch(insts, mode=gpu_lib.FP64)
     out = b.solve()
     torch.cuda.synchronize()
     ys = gpu_yhat(b, out)
     for i, sol in enumerate(oracle_solutions(insts)):
-        assert rel_inf(ys[i], sol["yhat"]) <= 1e-9, (i, rel_inf(ys[i], sol["yhat"]))
+        bar = fp64_floor.bar(insts[i], sol["yhat"])
+        assert rel_inf(ys[i], sol["yhat"]) <= bar, (i, rel_inf(ys[i], sol["yhat"]), bar)
 
 
 def test_fp64_ill_conditioned_uses_eigenbasis_gram(gpu_lib):
@@ -124,7 +125,7 @@ def test_fp64_ill_conditioned_uses_eigenbasis_gram(gpu_lib):
     e0 = [rel_inf(y0[i], s["yhat"]) for i, s in enumerate(sols)]
     e8 = [rel_inf(y8[i], s["yhat"]) for i, s in enumerate(sols)]
     print("refine 0:", e0, "refine 8:", e8)
-    assert max(e0) <= 1e-9 and max(e8) <= 1e-9
+    assert max(e0) <= 1e-9 and max(e8) <= 1e-10
     assert np.all(out["status"].cpu().numpy() & gpu_lib.S_REFINE_NOCONV == 0)
 
 
@@ -139,8 +140,8 @@ def test_explicit_time_arrays(gpu_lib, mode_name):
     torch.cuda.synchronize()
     ys = gpu_yhat(b, out)
     for i, sol in enumerate(oracle_solutions(insts)):
-        tol = (1e-10 if insts[i]["p"] == 1 else 1e-9) if mode_name == "FP64" else 1e-6
-        assert rel_inf(ys[i], sol["yhat"]) <= tol, (i, rel_inf(ys[i], sol["yhat"]))
+        tol = fp64_floor.bar(insts[i], sol["yhat"]) if mode_name == "FP64" else 1e-6
+        assert rel_inf(ys[i], sol["yhat"]) <= tol, (i, rel_inf(ys[i], sol["yhat"]), tol)
 
 
 @pytest.mark.parametrize("mode_name", ["FP64", "MIXED"])
@@ -162,9 +163,9 @@ def test_random_landmarks_match_oracle(gpu_lib, mode_name):
     out = b.solve()
     torch.cuda.synchronize()
     ys = gpu_yhat(b, out)
-    bar = 1e-9 if mode_name == "FP64" else 1e-6
     for i, sol in enumerate(oracle_solutions(insts)):
-        assert rel_inf(ys[i], sol["yhat"]) <= bar, (i, rel_inf(ys[i], sol["yhat"]))
+        bar = fp64_floor.bar(insts[i], sol["yhat"]) if mode_name == "FP64" else 1e-6
+        assert rel_inf(ys[i], sol["yhat"]) <= bar, (i, rel_inf(ys[i], sol["yhat"]), bar)
 
 
 @pytest.mark.parametrize("mode_name", ["FP64", "MIXED"])
@@ -214,10 +215,8 @@ def test_explicit_and_fused_agree(gpu_lib, mode_name):
     torch.cuda.synchronize()
     ys = gpu_yhat(b, out)
     for i, sol in enumerate(oracle_solutions(insts)):
-        # FP64 bars: 1e-10 for the first-order family, 1e-9 for the second-order family
-        # (eigenvalues kept down to 1e-8 lambda_1 amplify FP64 rounding to ~3e-10 in y_hat)
-        bar = 1e-10 if insts[i]["p"] == 1 else 1e-9
-        assert rel_inf(ys[i], sol["yhat"]) <= bar, (i, rel_inf(ys[i], sol["yhat"]))
+        bar = fp64_floor.bar(insts[i], sol["yhat"])
+        assert rel_inf(ys[i], sol["yhat"]) <= bar, (i, rel_inf(ys[i], sol["yhat"]), bar)
 
 
 def test_mixed_solve_config2(gpu_lib):
@@ -325,6 +324,54 @@ def test_paper_problems_orders_2_and_4_with_boundary_conditions(gpu_lib):
     for i, q in enumerate(insts):
         ref = oracle.linear.solve(q)["yhat"]
         assert rel_inf(ys[i], ref) <= 1e-7, (i, q["p"], rel_inf(ys[i], ref))
+
+
+# (problem or family, cut-off) pairs whose oracle solution is stable far below the FP64 bar:
+# switching LAPACK's symmetric eigensolver driver (evd / evr / ev / evx) moves the oracle's
+# y_hat by at most the figure in the comment.  Where the cut-off falls between close
+# eigenvalues (e.g. problem 16 at 1e-12: 6e-10) the truncated basis itself is that unstable
+# and no implementation can be held to 1e-10 there.
+FP64_HIGHER_ORDER = [
+    ("problem 7", 1e-12),   # second-order IVP, full rank: 2e-14
+    ("problem 9", 1e-8),    # second-order IVP: 3e-12
+    ("problem 10", 1e-8),   # second-order IVP: 2e-13
+    ("problem 12", 1e-10),  # second-order two-point BVP: 4e-12
+    ("problem 16", 1e-6),   # fourth-order BVP, clamped at both ends: 5e-12
+    ("order 3 IVP", 1e-8),  # sigma 0.2: 7e-13
+    ("order 3 BVP", 1e-12), # sigma 0.7, y, y' at t0 and y at the end: 1e-11
+]
+
+
+def higher_order_instance(name, tau, k=0):
+    import json
+    import os
+    from test_oracle_linear import paper_problem
+    if name.startswith("problem"):
+        pid = int(name.split()[1])
+        path = os.path.join(os.path.dirname(__file__), "golden", "paper_problems.json")
+        entry = [e for e in json.load(open(path))["problems"] if e["id"] == pid][0]
+        q, _ = paper_problem(entry, tau)
+        q["t0"], q["dt"] = float(q["t"][0]), float(q["t"][1] - q["t"][0])
+        q["t"] = q["t0"] + np.arange(q["n"]) * q["dt"]
+        return q
+    bvp = name.endswith("BVP")
+    return workloads.linear_order_p(k, 3, sigma=0.7 if bvp else 0.2, tau=tau, bvp=bvp)
+
+
+def test_fp64_orders_2_to_4_and_boundary_problems_at_fp64_bar(gpu_lib):
+    """Second-, third- and fourth-order problems, initial and two-point boundary conditions,
+    in one batch at the FP64 bar 1e-10 (cut-offs where the oracle itself is stable)."""
+    insts = [higher_order_instance(name, tau) for name, tau in FP64_HIGHER_ORDER]
+    insts += [workloads.linear_order_p(k, 3, sigma=0.2, tau=1e-8) for k in (1, 2)]
+    assert {q["p"] for q in insts} == {2, 3, 4}
+    b = gpu_lib.Batch(insts, mode=gpu_lib.FP64)
+    out = b.solve()
+    torch.cuda.synchronize()
+    ys = gpu_yhat(b, out)
+    names = [n for n, _ in FP64_HIGHER_ORDER] + ["order 3 IVP #1", "order 3 IVP #2"]
+    for i, q in enumerate(insts):
+        ref = oracle.linear.solve(q)["yhat"]
+        assert rel_inf(ys[i], ref) <= 1e-10, (names[i], rel_inf(ys[i], ref))
 
 
 def test_instance_info_reports_rank_and_passes(gpu_lib):

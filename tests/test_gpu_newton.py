@@ -68,8 +68,10 @@ def test_newton_first_steps_track_oracle(gpu_lib):
         np.testing.assert_allclose(got[:, i], steps, rtol=1e-4)
 
 
-def test_newton_requires_first_order(gpu_lib):
-    insts = [workloads.linear_second_order(0, n=300)]
+def test_riccati_evaluator_requires_first_order(gpu_lib):
+    insts = [workloads.nonlinear_second_order(0, n=300)]
     b = gpu_lib.Batch(insts, mode=gpu_lib.FP64)
+    x = b.newton_init()
+    q = torch.zeros(b.total, dtype=torch.float64, device="cuda")
     with pytest.raises(gpu_lib.NylsError):
-        b.newton_init()
+        b.riccati_eval(q, x, True)
