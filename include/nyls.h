@@ -200,6 +200,23 @@ int nyls_assemble(const nyls_plan* plan, double* kkt, double* rhs, void* ws, hip
 int nyls_solve(const nyls_plan* plan, int32_t refine_steps, double* omega, double* bias,
                double* lambda, double* yhat, int32_t* status, void* ws, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): nyls_solve with its workspace in a
+ * library-owned device array of NYLS_STATIC_WS_BYTES per GPU (held from library load until
+ * the process ends) instead of a caller-allocated `ws`.  Same kernels, arguments and
+ * results as nyls_solve; the call allocates nothing.
+ *   - Returns NYLS_E_SIZE when nyls_workspace_size(plan) exceeds NYLS_STATIC_WS_BYTES
+ *     (about 350 instances at m = 50), NYLS_E_MODE for NYLS_FP64_EXPLICIT plans (their GEMM
+ *     library may allocate), NYLS_E_HIP when the array's device address cannot be found.
+ *   - The used part of the array is cleared (by a kernel on `stream`) before the solve.
+ *   - All calls on one GPU share that GPU's array: calls that overlap in time on one GPU
+ *     (different streams or threads) race and give wrong results; serialise them.  The
+ *     array keeps the last call's basis, factors and solution, but nyls_predict and
+ *     nyls_backward take a caller workspace, so they cannot continue from this call. */
+#define NYLS_STATIC_WS_BYTES ((size_t)64 << 20)
+int nyls_solve_static(const nyls_plan* plan, int32_t refine_steps, double* omega, double* bias,
+                      double* lambda, double* yhat, int32_t* status, hipStream_t stream);
+
 /* y_hat^(d)(t) = alpha^T k_m^(d)(t) + [d == 0] b at caller times, from the solution a
  * previous nyls_solve or nyls_newton_step left in `ws` (d = 0..4). */
 int nyls_predict(const nyls_plan* plan, const double* t_eval, const int64_t* eval_off,

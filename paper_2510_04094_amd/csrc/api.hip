@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -137,6 +138,39 @@ void nyls_prof_end(int k, hipStream_t st) {
   g_prof.pending.push_back({k, {g_prof.open[k], e}});
   g_prof.open[k] = nullptr;
 }
+
+// Workspace of nyls_solve_static: a file-scope device array, one copy per GPU for the life
+// of the process.  Host code never uses the array's name as an address (on the host it is a
+// stand-in symbol); the device address of each GPU's copy is looked up once, with that GPU
+// current, and kept in g_scratch_ptr.
+constexpr size_t NYLS_SCRATCH_DOUBLES = NYLS_STATIC_WS_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[NYLS_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch array, or nullptr on failure.
+double* scratch_for_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Clears n doubles at p (a kernel rather than hipMemsetAsync, so a captured graph replays it
+// faithfully).
+__global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0;
+}
+}  // namespace
 
 // accessors used by the other translation units
 int64_t nyls_plan_newton_stride(const nyls_plan* pl) {
@@ -329,7 +363,7 @@ int nyls_assemble(const nyls_plan* pl, double* kkt, double* rhs, void* ws, hipSt
 }  // extern "C"
 
 namespace {
-// The solve of nyls_solve with the workspace at w.
+// The solve of nyls_solve / nyls_solve_static with the workspace at w.
 int solve_impl(const nyls_plan* pl, int32_t refine_steps, double* omega, double* bias,
                double* lambda, double* yhat, int32_t* status, double* w, hipStream_t stream) {
   const nyls_plan_view pv = view(pl);
@@ -424,6 +458,24 @@ int nyls_solve(const nyls_plan* pl, int32_t refine_steps, double* omega, double*
   if (refine_steps < 0 || refine_steps > 8) return NYLS_E_ARG;
   return solve_impl(pl, refine_steps, omega, bias, lambda, yhat, status, static_cast<double*>(ws),
                     stream);
+}
+
+int nyls_solve_static(const nyls_plan* pl, int32_t refine_steps, double* omega, double* bias,
+                      double* lambda, double* yhat, int32_t* status, hipStream_t stream) {
+  if (!pl || !yhat) return NYLS_E_NULL;
+  if (!pl->linear_ok) return NYLS_E_NULL;
+  if (pl->mode == NYLS_FP64_EXPLICIT) return NYLS_E_MODE;  // its GEMM library may allocate
+  if (refine_steps < 0 || refine_steps > 8) return NYLS_E_ARG;
+  const size_t bytes = nyls_workspace_size(pl);
+  if (bytes > NYLS_STATIC_WS_BYTES) return NYLS_E_SIZE;
+  double* w = scratch_for_current_device();
+  if (!w) return NYLS_E_HIP;
+  // the array keeps the previous call's contents: start from zeros, as a fresh workspace
+  const int64_t nd = (int64_t)(bytes / sizeof(double));
+  const int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nd + 255) / 256));
+  hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, stream, w, nd);
+  if (hipGetLastError() != hipSuccess) return NYLS_E_HIP;
+  return solve_impl(pl, refine_steps, omega, bias, lambda, yhat, status, w, stream);
 }
 
 int nyls_predict(const nyls_plan* pl, const double* t_eval, const int64_t* eval_off, int32_t d,

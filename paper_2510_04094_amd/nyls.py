@@ -54,6 +54,8 @@ EXPORTS = {
     "nyls_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p]),
+    "nyls_solve_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nyls_predict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nyls_newton_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -239,6 +241,24 @@ class Batch:
                                _ptr(out["yhat"]), _ptr(out["status"]), _ptr(self.ws), _stream()),
                "nyls_solve")
         self.ws_version += 1
+        return out
+
+    def solve_static(self, refine=None):
+        """nyls_solve_static: the solve with the library's own device workspace (no
+        allocation inside the call); same outputs as solve().  Leaves self.ws untouched."""
+        if refine is None:
+            refine = 4
+        dev = self.device
+        out = dict(
+            yhat=torch.empty(self.total, dtype=torch.float64, device=dev),
+            omega=torch.empty(self.batch, self.maxm, dtype=torch.float64, device=dev),
+            bias=torch.empty(self.batch, dtype=torch.float64, device=dev),
+            lam=torch.empty(self.batch, MAX_P, dtype=torch.float64, device=dev),
+            status=torch.empty(self.batch, dtype=torch.int32, device=dev),
+        )
+        _check(_lib.nyls_solve_static(self.plan, refine, _ptr(out["omega"]), _ptr(out["bias"]),
+                                      _ptr(out["lam"]), _ptr(out["yhat"]), _ptr(out["status"]),
+                                      _stream()), "nyls_solve_static")
         return out
 
     def assemble(self):
