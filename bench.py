@@ -180,9 +180,16 @@ def check_all(fn, jobs, procs):
     return np.array(pool_map(fn, jobs, procs))
 
 
-def run_mode(nyls, insts, mode, steps, warmup):
+def run_mode(nyls, insts, mode, steps, warmup, tune):
     import torch
     b = nyls.Batch(insts, mode=mode)
+    tuned = None
+    if tune:
+        # launch choices for this batch: coordinate search over nyls_tuning, timing nyls_solve
+        from paper_2510_04094_amd import autotune
+        res = autotune.autotune(b, reps=3, save=False, log=log)
+        tuned = {"tuning": res["tuning"], "solve_ms": res["ms"], "default_solve_ms": res["default_ms"],
+                 "candidates": len(res["tried"])}
     t_obs = [q["t_obs"] for q in insts]
     y_obs = torch.tensor(np.concatenate([q["y_obs"] for q in insts]), dtype=torch.float64, device="cuda")
     tt, oo, off = b._offsets(t_obs)
@@ -222,7 +229,7 @@ def run_mode(nyls, insts, mode, steps, warmup):
     nyls.profile_enable(False)
     prof = nyls.profile_read()
     info = b.info().cpu().numpy()
-    return b, out, (t1 - t0) / steps, prof, info
+    return b, out, (t1 - t0) / steps, prof, info, tuned
 
 
 EXP_FLOP = 28.0  # flop per FP64 exponential implied by the per-pass figure below
@@ -298,13 +305,18 @@ def long_single_ms(nyls, steps=3):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
-def uneven_batch_rate(nyls, mode, count, steps, procs, check):
+def uneven_batch_rate(nyls, mode, count, steps, procs, check, tune):
     """Solves/s of the uneven batch (orders 1 and 2, n ~ U{500..1e4}, m in {20, 50, 100}),
     forward only, one nyls_solve captured in a HIP graph and replayed; every instance checked
     against the oracle (rel. 1e-6) after the timed replays."""
     import torch
     insts = _uneven_instances(count)
     b = nyls.Batch(insts, mode=mode)
+    tuned = None
+    if tune:
+        from paper_2510_04094_amd import autotune
+        r = autotune.autotune(b, reps=2, save=False, log=log)
+        tuned = {"tuning": r["tuning"], "solve_ms": r["ms"], "default_solve_ms": r["default_ms"]}
     b.solve()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -324,7 +336,8 @@ def uneven_batch_rate(nyls, mode, count, steps, procs, check):
     counts, good = status_summary(out["status"].cpu().numpy())
     res = {"solves_per_s": None, "ms_per_step": sec * 1e3, "instances": count, "status_counts": counts,
            "orders": {"1": int(np.sum(b.p == 1)), "2": int(np.sum(b.p == 2))},
-           "mean_n": float(np.mean(b.n)), "note": "forward only, nyls_solve replayed from a HIP graph"}
+           "mean_n": float(np.mean(b.n)), "note": "forward only, nyls_solve replayed from a HIP graph",
+           "autotune": tuned}
     if check:
         y = out["yhat"].cpu().numpy()
         errs = check_all(_oracle_err_uneven, [(i, count, y[b.goff[i]:b.goff[i + 1]]) for i in range(count)], procs)
@@ -348,6 +361,7 @@ def main():
     ap.add_argument("--m", type=int, default=50)
     ap.add_argument("--modes", default="fp64,mixed")
     ap.add_argument("--check", type=int, default=1, help="1: check every instance against the oracle")
+    ap.add_argument("--tune", type=int, default=1, help="1: autotune the launch choices of each mode first")
     ap.add_argument("--plain", type=int, default=32, help="instances for the plain FP64 comparator")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle instances per timed run (0: 6 per process)")
     ap.add_argument("--cpu-runs", type=int, default=5, help="timed CPU runs (median reported)")
@@ -379,7 +393,7 @@ def main():
     results = {}
     for name in args.modes.split(","):
         mode = {"fp64": nyls.FP64, "mixed": nyls.MIXED}[name]
-        b, out, sec, prof, info = run_mode(nyls, insts, mode, args.steps, args.warmup)
+        b, out, sec, prof, info, tuned = run_mode(nyls, insts, mode, args.steps, args.warmup, args.tune)
         log("%s: %.2f ms per step; checking every instance against the oracle" % (name, sec * 1e3))
         counts, good = status_summary(out["status"].cpu().numpy())
         # every instance's y_hat against the oracle, after the timed steps (--check 0 skips
@@ -403,7 +417,7 @@ def main():
                 above["max_err_over_bar"] = float(np.max(errs[hi] / bars))
         else:
             ok, max_err, above = good, None, None
-        results[name] = dict(sec=sec, prof=prof, max_err=max_err, frac_ok=float(np.mean(ok)), above=above,
+        results[name] = dict(sec=sec, prof=prof, max_err=max_err, frac_ok=float(np.mean(ok)), above=above, tuned=tuned,
                              n_ok=int(np.sum(ok)), status=counts,
                              rate=float(np.sum(ok)) / sec, rank=float(info[:, 0].mean()),
                              passes_fw=float(info[:, 5].mean()), passes_bw=float(info[:, 6].mean()),
@@ -458,13 +472,14 @@ def main():
                       "errors": v["above"],
                       "status_counts": v["status"], "mean_rank": v["rank"], "mean_sweeps": v["sweeps"],
                       "refinement_passes": v["passes_fw"], "adjoint_passes": v["passes_bw"],
+                      "autotune": v["tuned"],
                       "kernel_ms": {kk: vv[0] / max(vv[1], 1) for kk, vv in v["prof"].items() if vv[1]}}
                   for k, v in results.items()},
     }
     if args.uneven > 0:
         log("uneven batch")
         line["uneven_batch"] = {name: uneven_batch_rate(nyls, {"fp64": nyls.FP64, "mixed": nyls.MIXED}[name],
-                                                        args.uneven, args.steps, procs, args.check)
+                                                        args.uneven, args.steps, procs, args.check, args.tune)
                                 for name in args.modes.split(",")}
     if args.plain > 0:
         log("plain per-instance FP64 solve")

@@ -126,6 +126,29 @@ typedef struct nyls_plan nyls_plan;
  * into them are picked up by the next call.  Returns 0 or a NYLS_E* code (then *out = NULL). */
 int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyls_plan** out);
 void nyls_plan_destroy(nyls_plan* plan);
+/* Launch choices of a plan (set by nyls_plan_set_tuning, e.g. from an autotuner's cache).
+ * Every combination computes the same method; they differ in speed, and in rounding only
+ * where the arithmetic order differs (the Gram path and its last column block).
+ *   eig_ql       m <= 64: 0 = tridiagonal QL one lane per instance (ql_lanes instances per
+ *                wavefront) with the plane rotations replayed onto Q by one wavefront per
+ *                instance; 1 = the whole QL inside one wavefront per instance
+ *   ql_lanes     1..64 (default 64)
+ *   gram_valu    FP64 Gram for m + 2 <= 64: 0 = one wavefront per instance on the matrix
+ *                cores; 1 = 256-thread LDS tiles on the VALU
+ *   tail_layout  1 = a last block of at most four landmarks (m = 16 k + 1..4) is walked in
+ *                the tail layout by the refinement/output passes and accumulated on the VALU by
+ *                the matrix-core Gram; 0 = treated as a full 16-slot block
+ *   overlap      FP64 solves: 1 = kernel-space Gram on the plan's side stream beside the
+ *                eigensolver; 0 = everything in order on the caller's stream
+ * Defaults: {0, 64, 0, 1, 1}. */
+typedef struct nyls_tuning {
+  int32_t eig_ql, ql_lanes, gram_valu, tail_layout, overlap;
+} nyls_tuning;
+/* Apply `tuning` to the plan (host call: updates the device descriptors synchronously; no
+ * work of this plan may be in flight).  Returns NYLS_E_ARG for out-of-range fields. */
+int nyls_plan_set_tuning(nyls_plan* plan, const nyls_tuning* tuning);
+int nyls_plan_get_tuning(const nyls_plan* plan, nyls_tuning* tuning);
+
 /* Bytes of device workspace every work function of this plan needs. */
 size_t nyls_workspace_size(const nyls_plan* plan);
 /* Sum of n over the batch: length of per-grid-point outputs (yhat, dL/dr, ...).

@@ -26,6 +26,7 @@ struct nyls_plan {
   unsigned gcls_mask = 0;
   unsigned tl_mask = 0;
   unsigned ntl_mask = 0;
+  nyls_tuning tune = {0, 64, 0, 1, 1};
   nyls_desc* d_desc = nullptr;
   int32_t* d_lidx = nullptr;
   int32_t* d_order = nullptr;
@@ -91,9 +92,9 @@ nyls_plan_view view(const nyls_plan* pl) {
   v.gcls_mask = pl->gcls_mask;
   v.tl_mask = pl->tl_mask;
   v.ntl_mask = pl->ntl_mask;
-  v.eig_ql = 0;
-  v.ql_lanes = 64;
-  v.overlap = 1;
+  v.eig_ql = pl->tune.eig_ql;
+  v.ql_lanes = pl->tune.ql_lanes;
+  v.overlap = pl->tune.overlap;
   v.only = 0;
   return v;
 }
@@ -172,6 +173,24 @@ __global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
 }
 }  // namespace
 
+namespace {
+// Per-instance kernel choices (nyls_desc::flags) and the launch masks that follow from the
+// plan's tuning.
+void apply_tuning(nyls_plan* pl) {
+  pl->gcls_mask = pl->tl_mask = pl->ntl_mask = 0;
+  for (nyls_desc& d : pl->h_desc) {
+    int f = 0;
+    if (pl->tune.tail_layout && d.rec == 1 && nyls_walk_tail(d.m) != 0) f |= NYLS_DF_TAIL;
+    if (pl->tune.tail_layout && (nyls_gram_class(d.m) & 1)) f |= NYLS_DF_GRAM_TAIL;
+    if (pl->tune.gram_valu && d.m + 2 <= 64) f |= NYLS_DF_GRAM_VALU;
+    d.flags = f;
+    if (d.m + 2 <= 64 && !(f & NYLS_DF_GRAM_VALU)) pl->gcls_mask |= 1u << nyls_gram_class_of(d);
+    if (f & NYLS_DF_TAIL) pl->tl_mask |= 1u << nyls_slot_blocks(d.m);
+    else pl->ntl_mask |= 1u << nyls_slot_blocks(d.m);
+  }
+}
+}  // namespace
+
 // accessors used by the other translation units
 int64_t nyls_plan_newton_stride(const nyls_plan* pl) {
   return pl ? (int64_t)pl->maxm + 1 + pl->maxp + pl->maxn : 0;
@@ -219,8 +238,7 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
     {
       const double a = q.uniform ? q.dt / q.sigma : 0.0;
       d.rec = (q.uniform && a <= 0.25) ? 1 : 0;
-      d.flags = (d.rec == 1 && nyls_walk_tail(q.m) != 0 ? NYLS_DF_TAIL : 0) |
-                ((nyls_gram_class(q.m) & 1) ? NYLS_DF_GRAM_TAIL : 0);
+      d.flags = 0;  // apply_tuning
     }
     d.ws = wsd;
     d.goff = goff;
@@ -233,13 +251,11 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
     pl->rec_mask |= 1u << d.rec;
     pl->nb_mask |= 1u << nyls_slot_blocks(q.m);
     pl->gnb_mask |= 1u << nyls_slot_blocks(q.m + 2);
-    if (q.m + 2 <= 64) pl->gcls_mask |= 1u << nyls_gram_class(q.m);
-    if (d.rec == 1 && nyls_walk_tail(q.m) != 0) pl->tl_mask |= 1u << nyls_slot_blocks(q.m);
-    else pl->ntl_mask |= 1u << nyls_slot_blocks(q.m);
     pl->maxm = std::max(pl->maxm, q.m);
     pl->maxp = std::max(pl->maxp, q.p);
     pl->maxn = std::max(pl->maxn, q.n);
   }
+  apply_tuning(pl);
   pl->total = goff;
   pl->ws_doubles = wsd;
   pl->scratch_off = wsd;
@@ -302,6 +318,24 @@ void nyls_plan_destroy(nyls_plan* pl) {
   if (pl->d_lidx) (void)hipFree(pl->d_lidx);
   if (pl->d_order) (void)hipFree(pl->d_order);
   delete pl;
+}
+
+int nyls_plan_set_tuning(nyls_plan* pl, const nyls_tuning* t) {
+  if (!pl || !t) return NYLS_E_NULL;
+  if ((t->eig_ql != 0 && t->eig_ql != 1) || t->ql_lanes < 1 || t->ql_lanes > 64 ||
+      (t->gram_valu != 0 && t->gram_valu != 1) || (t->tail_layout != 0 && t->tail_layout != 1) ||
+      (t->overlap != 0 && t->overlap != 1))
+    return NYLS_E_ARG;
+  pl->tune = *t;
+  apply_tuning(pl);
+  return hipMemcpy(pl->d_desc, pl->h_desc.data(), sizeof(nyls_desc) * pl->batch,
+                   hipMemcpyHostToDevice) == hipSuccess ? NYLS_OK : NYLS_E_HIP;
+}
+
+int nyls_plan_get_tuning(const nyls_plan* pl, nyls_tuning* t) {
+  if (!pl || !t) return NYLS_E_NULL;
+  *t = pl->tune;
+  return NYLS_OK;
 }
 
 size_t nyls_workspace_size(const nyls_plan* pl) {
@@ -395,7 +429,14 @@ int solve_impl(const nyls_plan* pl, int32_t refine_steps, double* omega, double*
     }
     return hip_rc(e);
   }
-  if (pl->mode == NYLS_FP64) {
+  if (pl->mode == NYLS_FP64 && !pl->tune.overlap) {
+    nyls_prof_begin(NYLS_K_EIG, stream);
+    e = nyls_launch_eig(pv, w, -1, stream);
+    nyls_prof_end(NYLS_K_EIG, stream);
+    nyls_prof_begin(NYLS_K_GRAM64, stream);
+    if (e == hipSuccess) e = nyls_launch_gram64(pv, w, stream);
+    nyls_prof_end(NYLS_K_GRAM64, stream);
+  } else if (pl->mode == NYLS_FP64) {
     // The kernel-space Grams need nothing from the eigensolver, and the eigensolver is
     // latency-bound (part of it runs one lane per instance on a few CUs): the Grams run on
     // the side stream meanwhile, and the eigenbasis Grams that replace them where K_mm is

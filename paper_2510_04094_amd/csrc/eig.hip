@@ -198,9 +198,9 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig(const nyls_desc* __restrict_
 //     |d_{i+1}|) is evaluated by all lanes at once; the scalar recurrences read d and e with
 //     lane broadcasts and are evaluated by every lane (they are uniform).
 constexpr int kQlMaxIter = 60;  // QL sweeps per eigenvalue
-// Instances per wavefront of k_ql_lanes (at most 64).  Fewer would spread a batch over more
-// CUs and shorten the lockstep of a wavefront's lanes, but 32, 16 and 8 all measured slower
-// than 64 on batches of thousands of m = 50 instances.
+// Instances per wavefront of k_ql_lanes: at most 64; the plan's tuning picks the number
+// (default 64: 32, 16 and 8 all measured slower on batches of thousands of m = 50 instances,
+// fewer spread a small batch over more CUs).
 constexpr int kQlLaneInst = 64;
 
 __device__ inline double sel_lane(double x, int lane, int i, double v) { return lane == i ? v : x; }
@@ -640,14 +640,15 @@ hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hip
     hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_ql),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const dim3 grid(single >= 0 ? 1 : pv.batch);
-    if (single >= 0) {
+    if (single >= 0 || pv.eig_ql) {
       hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
                          (int)QL_FULL);
     } else {
+      const int ipw = pv.ql_lanes >= 1 && pv.ql_lanes <= kQlLaneInst ? pv.ql_lanes : kQlLaneInst;
       hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
                          (int)QL_REDUCE);
-      hipLaunchKernelGGL(k_ql_lanes, dim3((pv.batch + kQlLaneInst - 1) / kQlLaneInst), dim3(64), 0,
-                         st, pv.d_desc, ws, pv.batch, kQlLaneInst);
+      hipLaunchKernelGGL(k_ql_lanes, dim3((pv.batch + ipw - 1) / ipw), dim3(64), 0, st, pv.d_desc,
+                         ws, pv.batch, ipw);
       hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
                          (int)QL_REPLAY);
       hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,

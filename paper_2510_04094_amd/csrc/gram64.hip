@@ -76,7 +76,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
   // accumulated in the eigenbasis (the KKT kernel then scales by Lambda^{-1/2}).
   const int rank = (int)ws[L.info + 0];
   const bool rotate = only || (rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam]);
-  if (nyls_slot_blocks(m + 2) <= 4) return;  // the one-wave MFMA kernels handle it
+  // m + 2 <= 64: the one-wave MFMA kernels take the instance unless its tuning asks for this one
+  if (nyls_slot_blocks(m + 2) <= 4 && !(d.flags & NYLS_DF_GRAM_VALU)) return;
   const double* Ug = ws + L.U;
   const bool ulds = maxm <= 64;
   if (rotate && ulds)
@@ -213,7 +214,7 @@ __device__ inline double row_bcast(double v) {
 }
 
 // NB = ceil((m + 2) / 16) column blocks with data; TLG: the last holds at most four columns
-// and is accumulated on the VALU (nyls_gram_class).
+// and is accumulated on the VALU (nyls_gram_class_of: the instance's NYLS_DF_GRAM_TAIL flag).
 template <int NB, int P, bool EX, bool TLG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_gram64_mfma(const nyls_desc* __restrict__ desc,
                                                     const int32_t* __restrict__ order,
@@ -221,8 +222,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   constexpr int NF = TLG ? NB - 1 : NB;  // blocks on the matrix cores
   constexpr int T = NF * (NF + 1) / 2;
   const nyls_desc& d = desc[instance_of(order)];
-  if (d.p != P || d.rec != (EX ? 0 : 1) || d.m + 2 > 64 ||
-      nyls_gram_class(d.m) != 2 * NB + (TLG ? 1 : 0))
+  if (d.p != P || d.rec != (EX ? 0 : 1) || d.m + 2 > 64 || (d.flags & NYLS_DF_GRAM_VALU) ||
+      nyls_gram_class_of(d) != 2 * NB + (TLG ? 1 : 0))
     return;
   const int m = d.m, n = d.n, g = m + 2;
   const nyls_wsl L = nyls_layout(m, P, 0);
@@ -372,7 +373,9 @@ __global__ __launch_bounds__(64) void k_gram64_rot_mfma(const nyls_desc* __restr
   constexpr int LDX = 16 * NB + 2;  // row stride of the staged rows
   __shared__ double X[16 * LDX];
   const nyls_desc& d = desc[instance_of(order)];
-  if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m + 2) != NB) return;
+  if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m + 2) != NB ||
+      (d.flags & NYLS_DF_GRAM_VALU))
+    return;
   const int m = d.m, n = d.n, g = m + 2;
   const nyls_wsl L = nyls_layout(m, P, 0);
   double* ws = wsbase + d.ws;

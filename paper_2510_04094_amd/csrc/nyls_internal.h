@@ -309,6 +309,12 @@ __host__ __device__ inline int nyls_gram_class(int m) {
   return 2 * nbu + ((nbu > 1 && g - 16 * (nbu - 1) <= 4) ? 1 : 0);
 }
 
+// Column-block class of the kernel-space MFMA Gram that takes instance d (its descriptor's
+// NYLS_DF_GRAM_TAIL flag says whether the last block goes to the VALU).
+__host__ __device__ inline int nyls_gram_class_of(const nyls_desc& d) {
+  return 2 * ((d.m + 2 + 15) >> 4) + ((d.flags & NYLS_DF_GRAM_TAIL) ? 1 : 0);
+}
+
 // Landmarks in the last 16-slot block when there are at most four of them (m = 16 (NB - 1)
 // + 1 .. 4, NB = nyls_slot_blocks(m) > 1), else 0.  On instances with rec == 1 the one-wave
 // passes walk such a block in a tail layout (one (point, landmark) pair per lane and chunk)

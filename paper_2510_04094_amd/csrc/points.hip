@@ -47,7 +47,7 @@ __global__ __launch_bounds__(64) void k_points(
   const int inst = instance_of(order, single);
   const nyls_desc& d = desc[inst];
   if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB ||
-      (!EX && nyls_walk_tail(d.m) != 0) != TL)
+      (!EX && (d.flags & NYLS_DF_TAIL)) != TL)
     return;  // another launch handles this instance
   if (only && !((int)wsbase[d.ws + nyls_layout(d.m, P, 0).info + 1] & only)) return;
   const int m = d.m, n = d.n;

@@ -39,7 +39,19 @@ class Problem(ctypes.Structure):
     ]
 
 
+class Tuning(ctypes.Structure):
+    """nyls_tuning: the plan's launch choices (include/nyls.h)."""
+    _fields_ = [("eig_ql", ctypes.c_int32), ("ql_lanes", ctypes.c_int32), ("gram_valu", ctypes.c_int32),
+                ("tail_layout", ctypes.c_int32), ("overlap", ctypes.c_int32)]
+
+
+TUNING_FIELDS = tuple(name for name, _ in Tuning._fields_)
+DEFAULT_TUNING = dict(eig_ql=0, ql_lanes=64, gram_valu=0, tail_layout=1, overlap=1)
+
+
 EXPORTS = {
+    "nyls_plan_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "nyls_plan_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "nyls_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "nyls_plan_destroy": (None, [ctypes.c_void_p]),
     "nyls_workspace_size": (ctypes.c_size_t, [ctypes.c_void_p]),
@@ -141,9 +153,11 @@ class Batch:
     the plan points into.  `mode` is FP64, MIXED or FP64_EXPLICIT.
     """
 
-    def __init__(self, instances, mode=FP64, device="cuda", explicit_grid=False):
+    def __init__(self, instances, mode=FP64, device="cuda", explicit_grid=False, tuning=None):
         """explicit_grid: pass every grid as its time array (nyls_problem.uniform = 0)
-        instead of (t0, dt)."""
+        instead of (t0, dt).  tuning: None (the library's defaults), a dict of nyls_tuning
+        fields, or "cached" (the autotuner's cached choice for this batch's key, defaults
+        when there is none)."""
         lib = load()
         self.mode = mode
         self.device = torch.device(device)
@@ -214,6 +228,27 @@ class Batch:
         self.ws = torch.zeros(max(nbytes, 8), dtype=torch.uint8, device=self.device)
         # bumped by every call that leaves a new basis / factorisation / solution in ws
         self.ws_version = 0
+        if tuning == "cached":
+            from . import autotune
+            tuning = autotune.lookup(autotune.batch_key(self))
+        if tuning:
+            self.set_tuning(**tuning)
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(_lib.nyls_plan_get_tuning(self.plan, ctypes.byref(t)), "nyls_plan_get_tuning")
+        return {k: int(getattr(t, k)) for k in TUNING_FIELDS}
+
+    def set_tuning(self, **fields):
+        """nyls_plan_set_tuning with the given fields changed (host call; no work of this
+        plan may be in flight)."""
+        cur = self.get_tuning()
+        for k, v in fields.items():
+            if k not in cur:
+                raise NylsError("unknown tuning field %r" % k)
+            cur[k] = int(v)
+        t = Tuning(**cur)
+        _check(_lib.nyls_plan_set_tuning(self.plan, ctypes.byref(t)), "nyls_plan_set_tuning")
 
     def __del__(self):
         if getattr(self, "plan", None) is not None and _lib is not None:
