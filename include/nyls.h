@@ -128,10 +128,12 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
 void nyls_plan_destroy(nyls_plan* plan);
 /* Launch choices of a plan (set by nyls_plan_set_tuning, e.g. from an autotuner's cache).
  * Every combination computes the same method; they differ in speed, and in rounding only
- * where the arithmetic order differs (the Gram path and its last column block).
- *   eig_ql       m <= 64: 0 = tridiagonal QL one lane per instance (ql_lanes instances per
- *                wavefront) with the plane rotations replayed onto Q by one wavefront per
- *                instance; 1 = the whole QL inside one wavefront per instance
+ * where the arithmetic order differs (the Gram path and its last column block, the point
+ * ranges of split passes).
+ *   eig_ql       0 = tridiagonal QL one lane per instance (ql_lanes instances per wavefront)
+ *                with the plane rotations replayed onto Q by one wavefront per instance (for
+ *                m > 64 only when the plan has at least 32 such instances, else as 1);
+ *                1 = the whole QL inside one wavefront per instance
  *   ql_lanes     1..64 (default 64)
  *   gram_valu    FP64 Gram for m + 2 <= 64: 0 = one wavefront per instance on the matrix
  *                cores; 1 = 256-thread LDS tiles on the VALU
@@ -140,12 +142,18 @@ void nyls_plan_destroy(nyls_plan* plan);
  *                the matrix-core Gram; 0 = treated as a full 16-slot block
  *   overlap      FP64 solves: 1 = kernel-space Gram on the plan's side stream beside the
  *                eigensolver; 0 = everything in order on the caller's stream
- * Defaults: {0, 64, 0, 1, 1}. */
+ *   split        FP64 solves of long instances: grid points per workgroup when the Gram and
+ *                the refinement/output passes of one instance are split over many
+ *                workgroups (a multiple of 64, at least 512; instances with n >= 2 x split
+ *                are split), 0 = never split, -1 = automatic (1024 when the plan has at most
+ *                64 instances, for those with n >= 4096; else never)
+ * Defaults: {0, 64, 0, 1, 1, -1}. */
 typedef struct nyls_tuning {
-  int32_t eig_ql, ql_lanes, gram_valu, tail_layout, overlap;
+  int32_t eig_ql, ql_lanes, gram_valu, tail_layout, overlap, split;
 } nyls_tuning;
 /* Apply `tuning` to the plan (host call: updates the device descriptors synchronously; no
- * work of this plan may be in flight).  Returns NYLS_E_ARG for out-of-range fields. */
+ * work of this plan may be in flight).  Returns NYLS_E_ARG for out-of-range fields.  The
+ * workspace size (nyls_workspace_size) depends on `split`: query it again afterwards. */
 int nyls_plan_set_tuning(nyls_plan* plan, const nyls_tuning* tuning);
 int nyls_plan_get_tuning(const nyls_plan* plan, nyls_tuning* tuning);
 

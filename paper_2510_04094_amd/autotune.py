@@ -93,7 +93,7 @@ def lookup(key, path=None):
     return {k: int(tun[k]) for k in nyls.TUNING_FIELDS}
 
 
-def knob_values(max_m, min_m, mode):
+def knob_values(max_m, min_m, mode, max_n=0):
     """The values worth trying per knob for a batch (others are no-ops there)."""
     knobs = {}
     if min_m <= 64:
@@ -104,6 +104,8 @@ def knob_values(max_m, min_m, mode):
     knobs["tail_layout"] = [1, 0]
     if mode == nyls.FP64:
         knobs["overlap"] = [1, 0]
+        if max_n >= 4096:
+            knobs["split"] = [-1, 0, 2048, 512]
     return knobs
 
 
@@ -136,7 +138,7 @@ def autotune(batch, refine=4, reps=3, save=True, path=None, log=None, min_gain=0
     best_ms = _time_solve(batch, refine, reps)
     tried.append((dict(best), best_ms))
     default_ms = best_ms
-    knobs = knob_values(int(np.max(batch.m)), int(np.min(batch.m)), batch.mode)
+    knobs = knob_values(int(np.max(batch.m)), int(np.min(batch.m)), batch.mode, int(np.max(batch.n)))
     for name, values in knobs.items():
         if name == "ql_lanes" and best.get("eig_ql", 0) == 1:
             continue  # the lane-parallel QL is not used then

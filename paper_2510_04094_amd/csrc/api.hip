@@ -26,7 +26,11 @@ struct nyls_plan {
   unsigned gcls_mask = 0;
   unsigned tl_mask = 0;
   unsigned ntl_mask = 0;
-  nyls_tuning tune = {0, 64, 0, 1, 1};
+  int32_t n_big = 0;        // instances with m > 64
+  int32_t n_split = 0, max_chunks = 0;
+  int64_t split_off = 0;       // partial sums of split instances (doubles from ws)
+  int64_t split_doubles = 0;
+  nyls_tuning tune = {0, 64, 0, 1, 1, -1};
   nyls_desc* d_desc = nullptr;
   int32_t* d_lidx = nullptr;
   int32_t* d_order = nullptr;
@@ -92,6 +96,9 @@ nyls_plan_view view(const nyls_plan* pl) {
   v.gcls_mask = pl->gcls_mask;
   v.tl_mask = pl->tl_mask;
   v.ntl_mask = pl->ntl_mask;
+  v.n_big = pl->n_big;
+  v.n_split = pl->n_split;
+  v.max_chunks = pl->max_chunks;
   v.eig_ql = pl->tune.eig_ql;
   v.ql_lanes = pl->tune.ql_lanes;
   v.overlap = pl->tune.overlap;
@@ -176,11 +183,36 @@ __global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
 namespace {
 // Per-instance kernel choices (nyls_desc::flags) and the launch masks that follow from the
 // plan's tuning.
+// Grid points per workgroup of split instances for the plan's `split` setting (0: none).
+int split_chunk(const nyls_plan* pl) {
+  if (pl->mode != NYLS_FP64) return 0;
+  if (pl->tune.split > 0) return pl->tune.split;
+  if (pl->tune.split == 0 || pl->batch > 64) return 0;
+  return 1024;
+}
+
 void apply_tuning(nyls_plan* pl) {
   pl->gcls_mask = pl->tl_mask = pl->ntl_mask = 0;
+  pl->n_split = pl->max_chunks = 0;
+  pl->split_off = pl->ws_doubles + pl->scratch_doubles;
+  pl->split_doubles = 0;
+  const int ch = split_chunk(pl);
+  const int min_n = pl->tune.split > 0 ? 2 * ch : 4096;
   for (nyls_desc& d : pl->h_desc) {
     int f = 0;
-    if (pl->tune.tail_layout && d.rec == 1 && nyls_walk_tail(d.m) != 0) f |= NYLS_DF_TAIL;
+    d.chunk = d.nchunks = 0;
+    d.part = 0;
+    if (ch > 0 && d.n >= min_n) {
+      f |= NYLS_DF_SPLIT;
+      d.chunk = ch;
+      d.nchunks = (d.n + ch - 1) / ch;
+      d.part = pl->split_off + pl->split_doubles;
+      pl->split_doubles += nyls_split_doubles(d.m, d.nchunks);
+      ++pl->n_split;
+      pl->max_chunks = std::max(pl->max_chunks, d.nchunks);
+    }
+    if (pl->tune.tail_layout && d.rec == 1 && nyls_walk_tail(d.m) != 0 && !(f & NYLS_DF_SPLIT))
+      f |= NYLS_DF_TAIL;
     if (pl->tune.tail_layout && (nyls_gram_class(d.m) & 1)) f |= NYLS_DF_GRAM_TAIL;
     if (pl->tune.gram_valu && d.m + 2 <= 64) f |= NYLS_DF_GRAM_VALU;
     d.flags = f;
@@ -251,11 +283,11 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
     pl->rec_mask |= 1u << d.rec;
     pl->nb_mask |= 1u << nyls_slot_blocks(q.m);
     pl->gnb_mask |= 1u << nyls_slot_blocks(q.m + 2);
+    if (q.m > 64) ++pl->n_big;
     pl->maxm = std::max(pl->maxm, q.m);
     pl->maxp = std::max(pl->maxp, q.p);
     pl->maxn = std::max(pl->maxn, q.n);
   }
-  apply_tuning(pl);
   pl->total = goff;
   pl->ws_doubles = wsd;
   pl->scratch_off = wsd;
@@ -264,6 +296,7 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
     const int64_t nn = pl->maxn, mm = pl->maxm;
     pl->scratch_doubles = nn * (NYLS_MAX_P + 1) * mm + nn * (mm + 2) + (mm + 2) * (mm + 2) + 64;
   }
+  apply_tuning(pl);
   // explicit grids must be strictly ascending (checked on a host copy)
   for (int i = 0; i < batch; ++i) {
     if (probs[i].uniform) continue;
@@ -324,7 +357,8 @@ int nyls_plan_set_tuning(nyls_plan* pl, const nyls_tuning* t) {
   if (!pl || !t) return NYLS_E_NULL;
   if ((t->eig_ql != 0 && t->eig_ql != 1) || t->ql_lanes < 1 || t->ql_lanes > 64 ||
       (t->gram_valu != 0 && t->gram_valu != 1) || (t->tail_layout != 0 && t->tail_layout != 1) ||
-      (t->overlap != 0 && t->overlap != 1))
+      (t->overlap != 0 && t->overlap != 1) ||
+      (t->split != -1 && t->split != 0 && (t->split < 512 || t->split % 64 != 0 || t->split > (1 << 24))))
     return NYLS_E_ARG;
   pl->tune = *t;
   apply_tuning(pl);
@@ -340,7 +374,7 @@ int nyls_plan_get_tuning(const nyls_plan* pl, nyls_tuning* t) {
 
 size_t nyls_workspace_size(const nyls_plan* pl) {
   if (!pl) return 0;
-  return (size_t)(pl->ws_doubles + pl->scratch_doubles) * sizeof(double);
+  return (size_t)(pl->ws_doubles + pl->scratch_doubles + pl->split_doubles) * sizeof(double);
 }
 
 int64_t nyls_total_points(const nyls_plan* pl) { return pl ? pl->total : 0; }

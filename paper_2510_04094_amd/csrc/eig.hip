@@ -1,184 +1,20 @@
 // Nystrom basis: landmark kernel matrix K_mm, its eigendecomposition and the feature
-// transform W = U_r Lambda_r^{-1/2} (App. A.2, eq32), one workgroup per instance.
+// transform W = U_r Lambda_r^{-1/2} (App. A.2, eq32), one wavefront per instance.
 //
-// K_mm is at most 128 x 128, so each workgroup keeps it in LDS and diagonalises it with
-// the two-sided cyclic Jacobi method in parallel (round-robin) order: every round rotates
-// m/2 disjoint index pairs at once, each thread updating whole 2 x 2 blocks J_i^T A J_j.
-// Eigenvectors accumulate in LDS when both matrices fit (m <= 96), else in the instance's
-// global scratch block.  Afterwards eigenvalues are sorted descending, each eigenvector is
+// K_mm (at most 128 x 128) is kept in LDS, reduced to tridiagonal form by Householder
+// reflections and diagonalised by implicit QL (k_eig_ql for m <= 64 with one row per lane,
+// staged with the lane-parallel QL of k_ql_lanes for batches; k_eig_ql2 for 64 < m <= 128
+// with two rows per lane).  Afterwards eigenvalues are sorted descending, each eigenvector is
 // signed so its largest-magnitude entry (first on ties) is positive, and eigenpairs with
 // lambda_k <= tau * lambda_1 are dropped (the retained rank r goes to info[0]).
 #include "nyls_dense.h"
 
 namespace {
 
-constexpr int kMaxSweeps = 40;
-constexpr int kQlMaxM = 64;       // bases up to this size use k_eig_ql
-constexpr int kVldsMaxM = 96;
+constexpr int kQlMaxM = 64;  // bases up to this size use k_eig_ql, up to twice it k_eig_ql2
 
 __device__ inline int instance_of(const int32_t* order, int single) {
   return single >= 0 ? single : (order ? order[blockIdx.x] : (int)blockIdx.x);
-}
-
-template <bool VLDS>
-__global__ __launch_bounds__(NYLS_BLOCK) void k_eig(const nyls_desc* __restrict__ desc,
-                                                    const int32_t* __restrict__ order,
-                                                    double* __restrict__ wsbase, int single) {
-  extern __shared__ double sm[];
-  const int inst = instance_of(order, single);
-  const nyls_desc& d = desc[inst];
-  const int m = d.m;
-  if (m <= kQlMaxM) return;  // k_eig_ql handles it
-  const nyls_wsl L = nyls_layout(m, d.p, 0);
-  double* ws = wsbase + d.ws;
-  const int tid = threadIdx.x;
-  const int ld = m + 1;
-  const int npair = (m + 1) >> 1;
-  const int m2 = npair << 1;
-
-  double* A = sm;
-  double* V = VLDS ? (A + m * ld) : (ws + L.tmp);
-  const int vld = VLDS ? ld : m;
-  double* tail = VLDS ? (A + 2 * m * ld) : (A + m * ld);
-  double* cs = tail;              // [64] cosines of this round
-  double* sn = cs + 64;           // [64] sines
-  double* tn = sn + 64;           // [64] tangents
-  double* red = tn + 64;          // [8]  reductions
-  double* tl = red + 8;           // [m]  landmark times, later eigenvalues
-  int* pidx = reinterpret_cast<int*>(tl + NYLS_MAX_M);
-  int* qidx = pidx + 64;
-  int* pos = qidx + 64;           // [m] sorted position of eigenpair k
-  double* sgn = reinterpret_cast<double*>(pos + NYLS_MAX_M);  // [m]
-
-  const double inv_sigma = 1.0 / d.sigma;
-  for (int s = tid; s < m; s += NYLS_BLOCK) tl[s] = nyls_grid_t(d, d.lidx[s]);
-  __syncthreads();
-  for (int e = tid; e < m * m; e += NYLS_BLOCK) {
-    const int a = e / m, b = e - a * m;
-    const double z = (tl[a] - tl[b]) * inv_sigma;
-    A[a * ld + b] = exp(-z * z);
-    V[a * vld + b] = (a == b) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-
-  // Cyclic sweeps until a whole sweep finds no off-diagonal entry above 1e-17 ||diag||_2
-  // (the backward-error level of a dense FP64 eigensolver).
-  int* rotflag = pos;  // reused below for the sort
-  int sweep = 0;
-  bool converged = false;
-  for (; sweep < kMaxSweeps; ++sweep) {
-    double dia = 0.0;
-    for (int k = tid; k < m; k += NYLS_BLOCK) dia += A[k * ld + k] * A[k * ld + k];
-    const double thresh = 1e-17 * sqrt(nyls_block_sum(dia, red));
-    if (tid == 0) rotflag[0] = 0;
-    __syncthreads();
-
-    for (int rd = 0; rd < m2 - 1; ++rd) {
-      if (tid < npair) {
-        int a, b;
-        if (tid == 0) { a = rd; b = m2 - 1; }
-        else { a = (rd + tid) % (m2 - 1); b = (rd - tid + (m2 - 1)) % (m2 - 1); }
-        const int p = a < b ? a : b, q = a < b ? b : a;
-        double c = 1.0, s = 0.0, t = 0.0;
-        if (q < m) {
-          const double apq = A[p * ld + q];
-          if (fabs(apq) > thresh) {
-            const double theta = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
-            t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-            rotflag[0] = 1;
-          }
-        }
-        pidx[tid] = p; qidx[tid] = q; cs[tid] = c; sn[tid] = s; tn[tid] = t;
-      }
-      __syncthreads();
-      // A <- J^T A J on every 2 x 2 block (pair i rows, pair j columns).
-      for (int e = tid; e < npair * npair; e += NYLS_BLOCK) {
-        const int i = e / npair, j = e - i * npair;
-        const int p1 = pidx[i], q1 = qidx[i], p2 = pidx[j], q2 = qidx[j];
-        const bool r1 = q1 < m, r2 = q2 < m;
-        const double c1 = cs[i], s1 = sn[i], c2 = cs[j], s2 = sn[j];
-        const double app = A[p1 * ld + p2];
-        const double apq = r2 ? A[p1 * ld + q2] : 0.0;
-        const double aqp = r1 ? A[q1 * ld + p2] : 0.0;
-        const double aqq = (r1 && r2) ? A[q1 * ld + q2] : 0.0;
-        const double bpp = c1 * app - s1 * aqp, bpq = c1 * apq - s1 * aqq;
-        const double bqp = s1 * app + c1 * aqp, bqq = s1 * apq + c1 * aqq;
-        double npp = c2 * bpp - s2 * bpq, npq = s2 * bpp + c2 * bpq;
-        double nqp = c2 * bqp - s2 * bqq, nqq = s2 * bqp + c2 * bqq;
-        if (i == j && r1) {
-          // the rotated pair is annihilated; diagonal in the accurate form a -+ t a_pq
-          const double t = tn[i];
-          npp = app - t * apq;
-          nqq = aqq + t * apq;
-          npq = 0.0;
-          nqp = 0.0;
-        }
-        A[p1 * ld + p2] = npp;
-        if (r2) A[p1 * ld + q2] = npq;
-        if (r1) A[q1 * ld + p2] = nqp;
-        if (r1 && r2) A[q1 * ld + q2] = nqq;
-      }
-      // V <- V J
-      for (int e = tid; e < m * npair; e += NYLS_BLOCK) {
-        const int row = e / npair, j = e - row * npair;
-        const int p2 = pidx[j], q2 = qidx[j];
-        if (q2 < m) {
-          const double c2 = cs[j], s2 = sn[j];
-          const double vp = V[row * vld + p2], vq = V[row * vld + q2];
-          V[row * vld + p2] = c2 * vp - s2 * vq;
-          V[row * vld + q2] = s2 * vp + c2 * vq;
-        }
-      }
-      __syncthreads();
-    }
-    if (rotflag[0] == 0) { converged = true; break; }
-    __syncthreads();
-  }
-
-  // Sort eigenvalues descending (ties by index) and pick each eigenvector's sign.
-  for (int k = tid; k < m; k += NYLS_BLOCK) {
-    const double lk = A[k * ld + k];
-    int ps = 0;
-    for (int j = 0; j < m; ++j) {
-      const double lj = A[j * ld + j];
-      ps += (lj > lk) || (lj == lk && j < k);
-    }
-    pos[k] = ps;
-    int jmax = 0;
-    double vmax = -1.0;
-    for (int s = 0; s < m; ++s) {
-      const double a = fabs(V[s * vld + k]);
-      if (a > vmax) { vmax = a; jmax = s; }
-    }
-    sgn[k] = V[jmax * vld + k] < 0.0 ? -1.0 : 1.0;
-  }
-  __syncthreads();
-  for (int k = tid; k < m; k += NYLS_BLOCK) tl[pos[k]] = A[k * ld + k];
-  __syncthreads();
-  const double lam1 = tl[0];
-  int rank = 0;
-  for (int k = 0; k < m; ++k) rank += (tl[k] > d.tau * lam1) ? 1 : 0;
-  // W[s][pos] = sign * U[s][k] / sqrt(lam_k) for retained positions, 0 otherwise.
-  // With V in global scratch (ws + tmp) the output region ws + W does not alias it.
-  for (int e = tid; e < m * m; e += NYLS_BLOCK) {
-    const int s = e / m, k = e - s * m;
-    const int ps = pos[k];
-    const double lk = A[k * ld + k];
-    ws[L.W + s * m + ps] = (ps < rank) ? sgn[k] * V[s * vld + k] / sqrt(lk) : 0.0;
-    ws[L.U + s * m + ps] = sgn[k] * V[s * vld + k];
-  }
-  for (int k = tid; k < m; k += NYLS_BLOCK) ws[L.lam + k] = tl[k];
-  if (tid == 0) {
-    int bits = 0;
-    if (rank < m) bits |= NYLS_S_TRUNCATED;
-    if (!converged) bits |= NYLS_S_EIG_NOCONV;
-    if (!(lam1 == lam1) || rank == 0) bits |= NYLS_S_NONFINITE;
-    ws[L.info + 0] = (double)rank;
-    ws[L.info + 1] = (double)bits;
-    ws[L.info + 2] = (double)sweep;
-  }
 }
 
 // ---- one wavefront per instance, m <= 64: Householder tridiagonalisation + implicit QL ----
@@ -191,7 +27,11 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig(const nyls_desc* __restrict_
 //     w = p - (beta/2)(v^T p) v.  v is kept in column k below the diagonal.
 //  2. Q = H_0 ... H_{m-3} is formed in place, last reflector first: each step applies H_k
 //     to the trailing block from the left and sets row and column k to e_k.
-//  3. Implicit QL on (d, e) with the shift from the leading 2 x 2 block of the active part;
+//  3. Implicit QL on (d, e) with the shift from the leading 2 x 2 block of the active part
+//     (the published implicit QL method for symmetric tridiagonal matrices of Bowdler,
+//     Martin, Reinsch and Wilkinson, "The QR and QL algorithms for symmetric matrices",
+//     Numer. Math. 11, 1968, known as tql2: the same shift, bulge chase and split test,
+//     re-organised for wavefront lanes);
 //     each sweep chases the bulge from the bottom of the unreduced block upwards with plane
 //     rotations, applied to the columns of Z = Q as they are formed (the column shared by
 //     consecutive rotations stays in a register).  The split test |e_i| <= eps (|d_i| +
@@ -202,6 +42,8 @@ constexpr int kQlMaxIter = 60;  // QL sweeps per eigenvalue
 // (default 64: 32, 16 and 8 all measured slower on batches of thousands of m = 50 instances,
 // fewer spread a small batch over more CUs).
 constexpr int kQlLaneInst = 64;
+// Fewest m > 64 instances for which the staged QL (one lane per instance) is used.
+constexpr int kQlStagedMin = 32;
 
 __device__ inline double sel_lane(double x, int lane, int i, double v) { return lane == i ? v : x; }
 
@@ -516,12 +358,15 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
 // those of step 3 of k_eig_ql; the plane rotations are logged to the instance's workspace
 // (its rotation-log region) for the replay on Q.  An instance whose log
 // would overflow is marked (info[7] = 2) and redone by k_eig_ql(QL_REDO).
+// MAXM = 64 takes the instances with m <= 64, MAXM = 128 those with 64 < m <= 128.
+template <int MAXM>
 __global__ __launch_bounds__(64) void k_ql_lanes(const nyls_desc* __restrict__ desc,
                                                  double* __restrict__ wsbase, int batch, int ipw) {
-  __shared__ double dv[kQlMaxM][64], ev[kQlMaxM][64];  // [index][lane]: conflict-free
+  __shared__ double dv[MAXM][64], ev[MAXM][64];  // [index][lane]: conflict-free
   const int lane = threadIdx.x;
   const int inst = blockIdx.x * ipw + lane;  // ipw <= 64 instances per wavefront
-  const bool act = lane < ipw && inst < batch && desc[inst < batch ? inst : 0].m <= kQlMaxM;
+  const int mi = desc[inst < batch ? inst : 0].m;
+  const bool act = lane < ipw && inst < batch && mi <= MAXM && mi > MAXM - kQlMaxM;
   const nyls_desc& d = desc[act ? inst : 0];
   const int m = act ? d.m : 0;
   const nyls_wsl L = nyls_layout(d.m, d.p, 0);
@@ -622,11 +467,352 @@ __global__ __launch_bounds__(64) void k_ql_lanes(const nyls_desc* __restrict__ d
   ws[L.info + 7] = overflow ? 2.0 : (converged ? 0.0 : 1.0);
 }
 
-size_t eig_lds_bytes(int maxm, bool vlds) {
-  const size_t mats = (size_t)(vlds ? 2 : 1) * maxm * (maxm + 1) * sizeof(double);
-  const size_t tail = (64 * 3 + 8 + NYLS_MAX_M) * sizeof(double) + (64 * 2 + NYLS_MAX_M) * sizeof(int) +
-                      NYLS_MAX_M * sizeof(double);
-  return mats + tail;
+// ---- one wavefront per instance, 64 < m <= 128: the steps of k_eig_ql with two rows per lane ----
+//
+// Lane l owns rows (and d, e entries) l and l + 64 of the same LDS layout; values indexed by
+// a wave-uniform i are read from the half that holds them.  The QL sweeps need no exchange
+// between the halves beyond those reads, so the whole solver stays inside one wavefront
+// (about 9 m^3 flop against the tens of cyclic Jacobi sweeps of m^3 each it replaces).
+__device__ inline double rd2(double v0, double v1, int i) {
+  return i < 64 ? nyls_rdlane(v0, i) : nyls_rdlane(v1, i - 64);
+}
+__device__ inline void wr2(double& v0, double& v1, int lane, int i, double x) {
+  v0 = lane == i ? x : v0;
+  v1 = lane + 64 == i ? x : v1;
+}
+
+__global__ __launch_bounds__(64) void k_eig_ql2(const nyls_desc* __restrict__ desc,
+                                                const int32_t* __restrict__ order,
+                                                double* __restrict__ wsbase, int single, int lda,
+                                                int stage) {
+  extern __shared__ double sm[];
+  const int inst = instance_of(order, single);
+  const nyls_desc& d = desc[inst];
+  const int m = d.m;
+  if (m <= kQlMaxM || m > 2 * kQlMaxM) return;
+  const nyls_wsl L = nyls_layout(m, d.p, 0);
+  double* ws = wsbase + d.ws;
+  if (stage == QL_REDO && ws[L.info + 7] != 2.0) return;
+  if (stage == QL_REPLAY && ws[L.info + 7] == 2.0) return;  // log overflow: QL_REDO
+  const int lane = threadIdx.x;
+  double* A = sm;                    // [lda][lda]: K_mm, then Q, then Z
+  double* vv = A + lda * lda;        // [128] reflector / signs
+  double* tt = vv + 128;             // [128] column products / sorted eigenvalues
+  double* tl = tt + 128;             // [128] landmark times
+  double* ww = tl;                   // [128] Householder w (after tl's last use)
+  int* pos = reinterpret_cast<int*>(tl + 128);  // [128] sorted position
+  const int j0 = lane, j1 = lane + 64;  // the lane's rows
+  const bool own0 = j0 < m, own1 = j1 < m;
+  double* A0 = A + j0 * lda;
+  double* A1 = A + (own1 ? j1 : j0) * lda;  // lanes without a second row alias the first
+  const double eps = 2.220446049250313e-16;
+  double d0 = 0.0, d1 = 0.0, e0 = 0.0, e1 = 0.0, b0 = 0.0, b1 = 0.0;
+  int iters = 0;
+  bool converged = true;
+
+  if (stage == QL_REPLAY) {
+    // Q and the eigenvalues from the workspace, then the sweeps k_ql_lanes logged: each is a
+    // header (mm, number of rotations k) and k pairs (c, s) for columns i = mm - 1, mm - 2, ...
+    // A sweep's window (header and at most m - 1 <= 127 rotations) is two entries per lane;
+    // the next window is loaded while this one is applied.
+    for (int j = 0; j < m; ++j) A0[j] = ws[L.U + j0 * m + j];
+    if (own1)
+      for (int j = 0; j < m; ++j) A1[j] = ws[L.U + j1 * m + j];
+    d0 = ws[L.lam + j0];
+    d1 = own1 ? ws[L.lam + j1] : 0.0;
+    iters = (int)ws[L.info + 2];
+    converged = ws[L.info + 7] == 0.0;
+    const double* lg = ws + L.log;
+    const int nsw = (int)ws[L.info + 6];
+    const int cap = (int)((L.aux - L.log) / 2);
+    auto fetch = [&](int e0, double& a0, double& b0, double& a1, double& b1) {
+      const int e = e0 + lane;
+      a0 = e < cap ? lg[2 * e] : 0.0;
+      b0 = e < cap ? lg[2 * e + 1] : 0.0;
+      a1 = e + 64 < cap ? lg[2 * (e + 64)] : 0.0;
+      b1 = e + 64 < cap ? lg[2 * (e + 64) + 1] : 0.0;
+    };
+    double ca0, cb0, ca1, cb1;
+    fetch(0, ca0, cb0, ca1, cb1);
+    int hdr = 0;
+    for (int sw = 0; sw < nsw; ++sw) {
+      const int mm = (int)nyls_rdlane(ca0, 0), nrot = (int)nyls_rdlane(cb0, 0);
+      const int nxt = hdr + 1 + nrot;
+      double na0, nb0, na1, nb1;
+      fetch(nxt, na0, nb0, na1, nb1);
+      double c0 = A0[mm], c1 = own1 ? A1[mm] : 0.0;
+      for (int k = 0; k < nrot; ++k) {
+        const int i = mm - 1 - k;
+        const double cs = rd2(ca0, ca1, k + 1), sn = rd2(cb0, cb1, k + 1);
+        const double z0 = A0[i];
+        A0[i + 1] = sn * z0 + cs * c0;
+        c0 = cs * z0 - sn * c0;
+        if (own1) {
+          const double z1 = A1[i];
+          A1[i + 1] = sn * z1 + cs * c1;
+          c1 = cs * z1 - sn * c1;
+        }
+      }
+      A0[mm - nrot] = c0;
+      if (own1) A1[mm - nrot] = c1;
+      ca0 = na0;
+      cb0 = nb0;
+      ca1 = na1;
+      cb1 = nb1;
+      hdr = nxt;
+    }
+    nyls_wave_lds_sync();
+  } else {
+  const double inv_sigma = 1.0 / d.sigma;
+  tl[j0] = nyls_grid_t(d, d.lidx[j0]);
+  if (own1) tl[j1] = nyls_grid_t(d, d.lidx[j1]);
+  nyls_wave_lds_sync();
+  for (int j = 0; j < m; ++j) {
+    const double tj = tl[j];
+    const double z0 = (tl[j0] - tj) * inv_sigma;
+    A0[j] = exp(-z0 * z0);
+    if (own1) {
+      const double z1 = (tl[j1] - tj) * inv_sigma;
+      A1[j] = exp(-z1 * z1);
+    }
+  }
+  nyls_wave_lds_sync();
+
+  // 1. tridiagonalisation
+  for (int k = 0; k + 2 < m; ++k) {
+    const bool a0 = j0 > k, a1 = own1 && j1 > k;
+    const double x0 = a0 ? A0[k] : 0.0, x1v = a1 ? A1[k] : 0.0;
+    const double sig2 = nyls_wave_sum_dpp(x0 * x0 + x1v * x1v);
+    const double xk1 = rd2(x0, x1v, k + 1);
+    wr2(d0, d1, lane, k, A[k * lda + k]);
+    if (!(sig2 - xk1 * xk1 > 0.0)) {
+      wr2(e0, e1, lane, k, xk1);
+      if (a0) A0[k] = 0.0;
+      if (a1) A1[k] = 0.0;
+      nyls_wave_lds_sync();
+      continue;
+    }
+    const double alpha = xk1 >= 0.0 ? -sqrt(sig2) : sqrt(sig2);
+    const double beta = 1.0 / (sig2 - alpha * xk1);
+    const double v0 = a0 ? (j0 == k + 1 ? x0 - alpha : x0) : 0.0;
+    const double v1 = a1 ? (j1 == k + 1 ? x1v - alpha : x1v) : 0.0;
+    wr2(e0, e1, lane, k, alpha);
+    wr2(b0, b1, lane, k, beta);
+    vv[j0] = v0;
+    vv[j1] = v1;
+    if (a0) A0[k] = v0;
+    if (a1) A1[k] = v1;
+    nyls_wave_lds_sync();
+    double p0 = a0 ? beta * nyls_row_dot(A0, vv, k + 1, m) : 0.0;
+    double p1 = a1 ? beta * nyls_row_dot(A1, vv, k + 1, m) : 0.0;
+    const double K = 0.5 * beta * nyls_wave_sum_dpp(v0 * p0 + v1 * p1);
+    const double w0 = p0 - K * v0, w1 = p1 - K * v1;
+    ww[j0] = w0;
+    ww[j1] = w1;
+    nyls_wave_lds_sync();
+    if (a0) nyls_row_rank2(A0, v0, ww, w0, vv, k + 1, m);
+    if (a1) nyls_row_rank2(A1, v1, ww, w1, vv, k + 1, m);
+    nyls_wave_lds_sync();
+  }
+  {
+    const double a22 = A[(m - 2) * lda + m - 2], a32 = A[(m - 1) * lda + m - 2],
+                 a33 = A[(m - 1) * lda + m - 1];
+    wr2(d0, d1, lane, m - 2, a22);
+    wr2(e0, e1, lane, m - 2, a32);
+    wr2(d0, d1, lane, m - 1, a33);
+    wr2(e0, e1, lane, m - 1, 0.0);
+  }
+  nyls_wave_lds_sync();
+
+  // 2. Q in place (the trailing 2 x 2 block starts as the identity)
+  if (j0 >= m - 2) {
+    A0[m - 2] = j0 == m - 2 ? 1.0 : 0.0;
+    A0[m - 1] = j0 == m - 1 ? 1.0 : 0.0;
+  }
+  if (own1 && j1 >= m - 2) {
+    A1[m - 2] = j1 == m - 2 ? 1.0 : 0.0;
+    A1[m - 1] = j1 == m - 1 ? 1.0 : 0.0;
+  }
+  nyls_wave_lds_sync();
+  for (int k = m - 3; k >= 0; --k) {
+    const bool a0 = j0 > k, a1 = own1 && j1 > k;
+    const double v0 = a0 ? A0[k] : 0.0, v1 = a1 ? A1[k] : 0.0;
+    const double beta = rd2(b0, b1, k);
+    if (beta != 0.0) {
+      vv[j0] = v0;
+      vv[j1] = v1;
+      nyls_wave_lds_sync();
+      // t_j = sum_i v_i Q[i][j] for the lane's columns j0 and j1
+      const double t0 = a0 ? nyls_col_dot(vv, A + j0, lda, k + 1, m) : 0.0;
+      const double t1 = a1 ? nyls_col_dot(vv, A + j1, lda, k + 1, m) : 0.0;
+      tt[j0] = beta * t0;
+      tt[j1] = beta * t1;
+      nyls_wave_lds_sync();
+      if (a0) nyls_row_rank1(A0, v0, tt, k + 1, m);
+      if (a1) nyls_row_rank1(A1, v1, tt, k + 1, m);
+    }
+    if (j0 == k)
+      for (int j = k; j < m; ++j) A0[j] = j == k ? 1.0 : 0.0;
+    if (own1 && j1 == k)
+      for (int j = k; j < m; ++j) A1[j] = j == k ? 1.0 : 0.0;
+    if (a0) A0[k] = 0.0;
+    if (a1) A1[k] = 0.0;
+    nyls_wave_lds_sync();
+  }
+
+  if (stage == QL_REDUCE) {
+    // d, e and Q for k_ql_lanes and the replay (W and U are written at the end)
+    ws[L.lam + j0] = d0;
+    ws[L.W + j0] = e0;
+    for (int j = 0; j < m; ++j) ws[L.U + j0 * m + j] = A0[j];
+    if (own1) {
+      ws[L.lam + j1] = d1;
+      ws[L.W + j1] = e1;
+      for (int j = 0; j < m; ++j) ws[L.U + j1 * m + j] = A1[j];
+    }
+    return;
+  }
+
+  // 3. implicit QL on (d, e), rotations accumulated into the rows of Z.  d and e live in LDS
+  //    for the sweeps (vv and tt are free until step 4): every lane runs the scalar chain on
+  //    broadcast reads issued one rotation ahead, lane 0 writes the updated entries, and no
+  //    lane-to-scalar moves sit on the chain.  Rotation i reads d_i, d_{i+1} and e_i, which no
+  //    earlier rotation of the sweep has rewritten (rotation i rewrites d_{i+1}, e_{i+1}).
+  double* dv = vv;
+  double* ev = tt;
+  dv[j0] = d0;
+  ev[j0] = e0;
+  dv[j1] = own1 ? d1 : 0.0;
+  ev[j1] = own1 ? e1 : 0.0;
+  nyls_wave_lds_sync();
+  for (int l = 0; l < m; ++l) {
+    int it = 0;
+    for (;;) {
+      const bool s0 = j0 >= l && (j0 == m - 1 ||
+                                  (j0 < m - 1 && fabs(ev[j0]) <= eps * (fabs(dv[j0]) + fabs(dv[j0 + 1]))));
+      const bool s1 = own1 && j1 >= l &&
+                      (j1 == m - 1 || (j1 < m - 1 && fabs(ev[j1]) <= eps * (fabs(dv[j1]) + fabs(dv[j1 + 1]))));
+      const unsigned long long mk0 = __ballot(s0), mk1 = __ballot(s1);
+      const int mm = mk0 ? __ffsll((long long)mk0) - 1 : 63 + __ffsll((long long)mk1);
+      if (mm == l) break;
+      if (++it > kQlMaxIter) { converged = false; break; }
+      ++iters;
+      const double dL = dv[l], eL = ev[l];
+      double g = (dv[l + 1] - dL) / (2.0 * eL);
+      double r = sqrt(g * g + 1.0);
+      g = dv[mm] - dL + eL / (g + (g >= 0.0 ? r : -r));
+      double sn = 1.0, cs = 1.0, pp = 0.0;
+      double c0 = A0[mm], c1 = own1 ? A1[mm] : 0.0;  // carries
+      double z0 = A0[mm - 1], z1 = own1 ? A1[mm - 1] : 0.0;
+      double ei = ev[mm - 1], di = dv[mm - 1], di1 = dv[mm];
+      bool split = false;
+      for (int i = mm - 1; i >= l; --i) {
+        const int ip = i > 0 ? i - 1 : 0;  // next rotation's entries (unused after the last)
+        const double ein = ev[ip], din = dv[ip];
+        const double f = sn * ei, b = cs * ei;
+        const double x = f * f + g * g;
+        if (x == 0.0) {  // exact deflation: the chase stops here
+          if (lane == 0) {
+            ev[i + 1] = 0.0;
+            dv[i + 1] = di1 - pp;
+            ev[mm] = 0.0;
+          }
+          A0[i + 1] = c0;
+          if (own1) A1[i + 1] = c1;
+          split = true;
+          break;
+        }
+        const double y = nyls_rsqrt(x);
+        const double en = x * y;
+        sn = f * y;
+        cs = g * y;
+        g = di1 - pp;
+        r = (di - g) * sn + 2.0 * cs * b;
+        pp = sn * r;
+        if (lane == 0) {
+          ev[i + 1] = en;
+          dv[i + 1] = g + pp;
+        }
+        g = cs * r - b;
+        A0[i + 1] = sn * z0 + cs * c0;
+        c0 = cs * z0 - sn * c0;
+        if (own1) A1[i + 1] = sn * z1 + cs * c1;
+        c1 = cs * z1 - sn * c1;
+        z0 = i > l ? A0[i - 1] : 0.0;
+        z1 = (own1 && i > l) ? A1[i - 1] : 0.0;
+        di1 = di;
+        di = din;
+        ei = ein;
+      }
+      if (!split) {
+        A0[l] = c0;
+        if (own1) A1[l] = c1;
+        if (lane == 0) {
+          dv[l] -= pp;
+          ev[l] = g;
+          ev[mm] = 0.0;
+        }
+      }
+      nyls_wave_lds_sync();
+    }
+  }
+  d0 = dv[j0];
+  d1 = own1 ? dv[j1] : 0.0;
+  nyls_wave_lds_sync();
+  }  // stage != QL_REPLAY
+
+  // 4. sort descending (ties by index), sign each eigenvector (largest |entry| positive,
+  //    first on ties), cut-off, W = U_r Lambda_r^{-1/2}
+  int ps0 = 0, ps1 = 0;
+  for (int j = 0; j < m; ++j) {
+    const double lj = rd2(d0, d1, j);
+    ps0 += (lj > d0) || (lj == d0 && j < j0);
+    ps1 += (lj > d1) || (lj == d1 && j < j1);
+  }
+  auto col_sign = [&](int c) {
+    int jmax = 0;
+    double vmax = -1.0;
+    for (int s2 = 0; s2 < m; ++s2) {
+      const double a = fabs(A[s2 * lda + c]);
+      if (a > vmax) { vmax = a; jmax = s2; }
+    }
+    return A[jmax * lda + c] < 0.0 ? -1.0 : 1.0;
+  };
+  pos[j0] = ps0;
+  vv[j0] = col_sign(j0);
+  tt[ps0] = d0;
+  if (own1) {
+    pos[j1] = ps1;
+    vv[j1] = col_sign(j1);
+    tt[ps1] = d1;
+  }
+  nyls_wave_lds_sync();
+  const double lam1 = tt[0];
+  int rank = 0;
+  for (int k = 0; k < m; ++k) rank += (tt[k] > d.tau * lam1) ? 1 : 0;
+  for (int h = 0; h < 2; ++h) {
+    const int row = h ? j1 : j0;
+    if (row >= m) continue;
+    const double* Ar = h ? A1 : A0;
+    for (int k = 0; k < m; ++k) {
+      const int pk = pos[k];
+      const double u = vv[k] * Ar[k];
+      ws[L.U + row * m + pk] = u;
+      ws[L.W + row * m + pk] = pk < rank ? u / sqrt(tt[pk]) : 0.0;
+    }
+    ws[L.lam + row] = tt[row];
+  }
+  if (lane == 0) {
+    int bits = 0;
+    if (rank < m) bits |= NYLS_S_TRUNCATED;
+    if (!converged) bits |= NYLS_S_EIG_NOCONV;
+    if (!(lam1 == lam1) || rank == 0) bits |= NYLS_S_NONFINITE;
+    ws[L.info + 0] = (double)rank;
+    ws[L.info + 1] = (double)bits;
+    ws[L.info + 2] = (double)iters;
+    ws[L.info + 6] = 0.0;
+    ws[L.info + 7] = 0.0;
+  }
 }
 
 }  // namespace
@@ -647,8 +833,8 @@ hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hip
       const int ipw = pv.ql_lanes >= 1 && pv.ql_lanes <= kQlLaneInst ? pv.ql_lanes : kQlLaneInst;
       hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
                          (int)QL_REDUCE);
-      hipLaunchKernelGGL(k_ql_lanes, dim3((pv.batch + ipw - 1) / ipw), dim3(64), 0, st, pv.d_desc,
-                         ws, pv.batch, ipw);
+      hipLaunchKernelGGL(k_ql_lanes<kQlMaxM>, dim3((pv.batch + ipw - 1) / ipw), dim3(64), 0, st,
+                         pv.d_desc, ws, pv.batch, ipw);
       hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
                          (int)QL_REPLAY);
       hipLaunchKernelGGL(k_eig_ql, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
@@ -656,19 +842,28 @@ hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hip
     }
   }
   if (!(pv.nb_mask & 256)) return hipGetLastError();
-  const bool vlds = pv.maxm <= kVldsMaxM;
-  const size_t lds = eig_lds_bytes(pv.maxm, vlds);
-  const int grid = single >= 0 ? 1 : pv.batch;
-  if (vlds) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig<true>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_eig<true>, dim3(grid), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order,
-                       ws, single);
+  // 64 < m <= 128: one wavefront per instance, two rows per lane.  With many such instances
+  // the QL is staged like the m <= 64 path (the lane-parallel QL takes up to 64 instances
+  // per wavefront); a few run it inside their own wavefront, where all lanes share the
+  // scalar chain instead of one lane carrying it.
+  const int lda = pv.maxm | 1;
+  const size_t lds = (size_t)lda * lda * sizeof(double) + 3 * 128 * sizeof(double) + 128 * sizeof(int);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_ql2),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const dim3 grid(single >= 0 ? 1 : pv.batch);
+  if (single >= 0 || pv.eig_ql || pv.n_big < kQlStagedMin) {
+    hipLaunchKernelGGL(k_eig_ql2, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
+                       (int)QL_FULL);
   } else {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig<false>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_eig<false>, dim3(grid), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order,
-                       ws, single);
+    const int ipw = pv.ql_lanes >= 1 && pv.ql_lanes <= kQlLaneInst ? pv.ql_lanes : kQlLaneInst;
+    hipLaunchKernelGGL(k_eig_ql2, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
+                       (int)QL_REDUCE);
+    hipLaunchKernelGGL(k_ql_lanes<2 * kQlMaxM>, dim3((pv.batch + ipw - 1) / ipw), dim3(64), 0, st,
+                       pv.d_desc, ws, pv.batch, ipw);
+    hipLaunchKernelGGL(k_eig_ql2, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
+                       (int)QL_REPLAY);
+    hipLaunchKernelGGL(k_eig_ql2, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
+                       (int)QL_REDO);
   }
   return hipGetLastError();
 }

@@ -46,12 +46,19 @@ __device__ inline void block_coords(int blk, int nb, int& bi, int& bj) {
   bj = row + b;
 }
 
+// smode 0: instances without NYLS_DF_SPLIT, the whole grid, into the instance's Gram;
+// smode 1 / 2: split instances, chunk blockIdx.y of the grid, into its partial sum, in
+// kernel space (1, needs nothing from the eigensolver) or, for instances that need the
+// eigenbasis, rotated (2, after the eigensolver).
 __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restrict__ desc,
                                                        const int32_t* __restrict__ order,
                                                        double* __restrict__ wsbase, int maxm,
-                                                       int only) {
+                                                       int only, int smode) {
   extern __shared__ double sm[];
   const nyls_desc& d = desc[instance_of(order)];
+  if (((d.flags & NYLS_DF_SPLIT) != 0) != (smode != 0)) return;
+  const int chunk = (int)blockIdx.y;
+  if (smode && chunk >= d.nchunks) return;
   if (only && !((int)wsbase[d.ws + nyls_layout(d.m, d.p, 0).info + 1] & only)) return;
   const int m = d.m, p = d.p, n = d.n;
   const int g = m + 2;
@@ -74,10 +81,14 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
   // Ill-conditioned K_mm (retained eigenvalues below 1e-9 lambda_1): the kernel-space Gram
   // would lose most digits in W^T S W, so the rows are rotated by U^T first and the Gram is
   // accumulated in the eigenbasis (the KKT kernel then scales by Lambda^{-1/2}).
-  const int rank = (int)ws[L.info + 0];
+  const int rank = smode == 1 ? 0 : (int)ws[L.info + 0];
   const bool rotate = only || (rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam]);
-  // m + 2 <= 64: the one-wave MFMA kernels take the instance unless its tuning asks for this one
-  if (nyls_slot_blocks(m + 2) <= 4 && !(d.flags & NYLS_DF_GRAM_VALU)) return;
+  if (smode == 2 && !rotate) return;  // the kernel-space partials stand
+  // m + 2 <= 64: the one-wave MFMA kernels take the instance unless its tuning asks for this
+  // one (split instances always come here)
+  if (!smode && nyls_slot_blocks(m + 2) <= 4 && !(d.flags & NYLS_DF_GRAM_VALU)) return;
+  const int ibeg = smode ? chunk * d.chunk : 0;
+  const int iend = smode ? min(n, ibeg + d.chunk) : n;
   const double* Ug = ws + L.U;
   const bool ulds = maxm <= 64;
   if (rotate && ulds)
@@ -109,7 +120,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[k][e] = 0.0;
 
-  for (int i0 = 0; i0 < n; i0 += TP) {
+  for (int i0 = ibeg; i0 < iend; i0 += TP) {
     __syncthreads();
     // per-point operator weights w_q (L = d^p - sum f_k d^(p-k)), c_i, r_i, padding
     for (int e = tid; e < TP; e += NYLS_BLOCK) {
@@ -182,7 +193,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
     }
     __syncthreads();
   }
-  double* out = ws + L.gram;
+  double* out = smode ? wsbase + d.part + nyls_split_gram(m, chunk) : ws + L.gram;
   for (int e = tid; e < g * g; e += NYLS_BLOCK) {
     int a = e / g, b = e - a * g;
     if (a > b) { const int t = a; a = b; b = t; }
@@ -190,7 +201,27 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
     const int blk = ia * nb - ia * (ia - 1) / 2 + (ib - ia);
     out[e] = Q[blk * 16 + (a & 3) * 4 + (b & 3)];
   }
-  if (tid == 0) ws[L.info + 4] = rotate ? 1.0 : 0.0;
+  if (tid == 0 && !smode) ws[L.info + 4] = rotate ? 1.0 : 0.0;
+}
+
+// Gram of a split instance: the sum of its chunk partials in chunk order (a fixed order,
+// so the result does not depend on which workgroup finished first), and the basis it is in.
+__global__ __launch_bounds__(NYLS_BLOCK) void k_gram_split_sum(const nyls_desc* __restrict__ desc,
+                                                               double* __restrict__ wsbase) {
+  const nyls_desc& d = desc[blockIdx.x];
+  if (!(d.flags & NYLS_DF_SPLIT)) return;
+  const int m = d.m, g = m + 2;
+  const nyls_wsl L = nyls_layout(m, d.p, 0);
+  double* ws = wsbase + d.ws;
+  const double* part = wsbase + d.part;
+  const int rank = (int)ws[L.info + 0];
+  const bool rotate = rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam];
+  for (int e = threadIdx.x; e < g * g; e += NYLS_BLOCK) {
+    double acc = 0.0;
+    for (int c = 0; c < d.nchunks; ++c) acc += part[nyls_split_gram(m, c) + e];
+    ws[L.gram + e] = acc;
+  }
+  if (threadIdx.x == 0) ws[L.info + 4] = rotate ? 1.0 : 0.0;
 }
 
 
@@ -222,8 +253,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   constexpr int NF = TLG ? NB - 1 : NB;  // blocks on the matrix cores
   constexpr int T = NF * (NF + 1) / 2;
   const nyls_desc& d = desc[instance_of(order)];
-  if (d.p != P || d.rec != (EX ? 0 : 1) || d.m + 2 > 64 || (d.flags & NYLS_DF_GRAM_VALU) ||
-      nyls_gram_class_of(d) != 2 * NB + (TLG ? 1 : 0))
+  if (d.p != P || d.rec != (EX ? 0 : 1) || d.m + 2 > 64 ||
+      (d.flags & (NYLS_DF_GRAM_VALU | NYLS_DF_SPLIT)) || nyls_gram_class_of(d) != 2 * NB + (TLG ? 1 : 0))
     return;
   const int m = d.m, n = d.n, g = m + 2;
   const nyls_wsl L = nyls_layout(m, P, 0);
@@ -374,7 +405,7 @@ __global__ __launch_bounds__(64) void k_gram64_rot_mfma(const nyls_desc* __restr
   __shared__ double X[16 * LDX];
   const nyls_desc& d = desc[instance_of(order)];
   if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m + 2) != NB ||
-      (d.flags & NYLS_DF_GRAM_VALU))
+      (d.flags & (NYLS_DF_GRAM_VALU | NYLS_DF_SPLIT)))
     return;
   const int m = d.m, n = d.n, g = m + 2;
   const nyls_wsl L = nyls_layout(m, P, 0);
@@ -554,13 +585,37 @@ size_t nyls_gram64_lds_bytes(int maxm) {
   return total;
 }
 
+namespace {
+// Chunk partials of the split instances (smode 1: kernel space, 2: eigenbasis where needed).
+void launch_split_parts(const nyls_plan_view& pv, double* ws, hipStream_t st, int smode) {
+  if (!pv.n_split) return;
+  const size_t lds = nyls_gram64_lds_bytes(pv.maxm);
+  hipLaunchKernelGGL(k_gram64, dim3(pv.batch, pv.max_chunks), dim3(NYLS_BLOCK), lds, st, pv.d_desc,
+                     pv.d_order, ws, pv.maxm, 0, smode);
+}
+}  // namespace
+
 hipError_t nyls_launch_gram64_kspace(const nyls_plan_view& pv, double* ws, hipStream_t st) {
   launch_ks_all(pv, ws, st, -1);
+  if (pv.n_split) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)nyls_gram64_lds_bytes(pv.maxm));
+    launch_split_parts(pv, ws, st, 1);
+  }
   return hipGetLastError();
 }
 
 hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t st) {
-  if (!pv.only) launch_ks_all(pv, ws, st, 0);
+  if (!pv.only) {
+    launch_ks_all(pv, ws, st, 0);
+    if (pv.n_split) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)nyls_gram64_lds_bytes(pv.maxm));
+      launch_split_parts(pv, ws, st, 1);
+    }
+  }
   return nyls_launch_gram64_rest(pv, ws, st);
 }
 
@@ -571,6 +626,10 @@ hipError_t nyls_launch_gram64_rest(const nyls_plan_view& pv, double* ws, hipStre
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_gram64, dim3(pv.batch), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws,
-                     pv.maxm, pv.only);
+                     pv.maxm, pv.only, 0);
+  if (pv.n_split && !pv.only) {
+    launch_split_parts(pv, ws, st, 2);
+    hipLaunchKernelGGL(k_gram_split_sum, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws);
+  }
   return hipGetLastError();
 }

@@ -12,13 +12,14 @@
 // factors stay in the workspace for refinement and the adjoint, and the solution x and
 // alpha = W omega are stored.
 //
-// Kernel-space Gram with m + 2 <= 64: the whole (omega, b) block and the right-hand side come
+// Kernel-space Gram with m + 2 <= 128: the whole (omega, b) block and the right-hand side come
 // from one product K~ = W~^T S~ W~ on the matrix cores, with W~ = diag(W[:, :r], 1, 1)
-// zero-padded to 64 x 64: K~[:m+1, :m+1] is the (omega, b) block before scaling by gamma and
-// K~[:m+1, m+1] the right-hand side.  Wave J of the workgroup owns column block J: it forms
-// T = S~ W~[:, 16J:16J+16] with v_mfma_f64_16x16x4f64 and keeps it in its accumulators,
-// which are then exactly the B operands of W~^T T (register v of tile I holds rows
-// 16 I + 4 v + lane / 16), so T never leaves the registers.
+// zero-padded to 16 NT x 16 NT (NT = 4 or 8 column blocks): K~[:m+1, :m+1] is the (omega, b)
+// block before scaling by gamma and K~[:m+1, m+1] the right-hand side.  Wave J of the
+// workgroup takes column blocks J, J + 4: it forms T = S~ W~[:, 16J:16J+16] with
+// v_mfma_f64_16x16x4f64 and keeps it in its accumulators, which are then exactly the B
+// operands of W~^T T (register v of tile I holds rows 16 I + 4 v + lane / 16), so T never
+// leaves the registers.
 #include "nyls_dense.h"
 
 namespace {
@@ -32,43 +33,44 @@ __device__ inline double wext(const double* W, int m, int r, int g, int s, int k
 }
 
 // Writes gamma K~ (+ identity on the landmark diagonal) into K[a][b], a, b <= m, and
-// gamma K~[a][m + 1] into rhs[a], a <= m.  256 threads; wave J takes column block J.
+// gamma K~[a][m + 1] into rhs[a], a <= m, for g = m + 2 <= 16 NT.  256 threads; wave J takes
+// column blocks J, J + 4, ... in turn (NT <= 8).
+template <int NT, class Out>
 __device__ inline void kkt_transform_mfma(const double* __restrict__ S, const double* __restrict__ W,
-                                          int m, int r, double gam, double* K, int lda,
-                                          double* rhs) {
+                                          int m, int r, double gam, Out out) {
   const int g = m + 2;
-  const int lane = threadIdx.x & 63, J = threadIdx.x >> 6;
-  if (16 * J >= g) return;
+  const int lane = threadIdx.x & 63;
   const int row = lane & 15, kq = lane >> 4;
-  nyls_d4 t[4];
+  // NT <= 4: one column block per wavefront (no loop, which keeps k_kkt's registers low)
+  const int J0 = threadIdx.x >> 6, JS = NT <= NYLS_BLOCK / 64 ? NT : NYLS_BLOCK / 64;
+  for (int J = J0; J < NT && 16 * J < g; J += JS) {
+    nyls_d4 t[NT];
 #pragma unroll
-  for (int I = 0; I < 4; ++I) t[I] = nyls_d4{0.0, 0.0, 0.0, 0.0};
+    for (int I = 0; I < NT; ++I) t[I] = nyls_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int ks = 0; ks < 16; ++ks) {
-    const int s = 4 * ks + kq;
-    const double bop = wext(W, m, r, g, s, 16 * J + row);
+    for (int ks = 0; ks < 4 * NT; ++ks) {
+      const int s = 4 * ks + kq;
+      const double bop = wext(W, m, r, g, s, 16 * J + row);
 #pragma unroll
-    for (int I = 0; I < 4; ++I) {
-      const int a = 16 * I + row;
-      const double aop = (a < g && s < g) ? S[a * g + s] : 0.0;
-      t[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, t[I], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int I = 0; I < 4; ++I) {
-    if (16 * I >= g) break;
-    nyls_d4 k4 = nyls_d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int ks = 0; ks < 16; ++ks) {
-      const double aop = wext(W, m, r, g, 4 * ks + kq, 16 * I + row);
-      k4 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, t[ks >> 2][ks & 3], k4, 0, 0, 0);
+      for (int I = 0; I < NT; ++I) {
+        const int a = 16 * I + row;
+        const double aop = (a < g && s < g) ? S[a * g + s] : 0.0;
+        t[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, t[I], 0, 0, 0);
+      }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int a = 16 * I + 4 * v + kq, b = 16 * J + row;
-      if (a <= m) {
-        if (b <= m) K[a * lda + b] = gam * k4[v] + ((a == b && a < m) ? 1.0 : 0.0);
-        else if (b == m + 1) rhs[a] = gam * k4[v];
+    for (int I = 0; I < NT; ++I) {
+      if (16 * I >= g) break;
+      nyls_d4 k4 = nyls_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < 4 * NT; ++ks) {
+        const double aop = wext(W, m, r, g, 4 * ks + kq, 16 * I + row);
+        k4 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, t[ks >> 2][ks & 3], k4, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = 16 * I + 4 * v + kq, b = 16 * J + row;
+        if (a <= m && b <= m + 1) out(a, b, gam * k4[v] + ((a == b && a < m) ? 1.0 : 0.0));
       }
     }
   }
@@ -76,6 +78,28 @@ __device__ inline void kkt_transform_mfma(const double* __restrict__ S, const do
 
 __device__ inline int instance_of(const int32_t* order) {
   return order ? order[blockIdx.x] : (int)blockIdx.x;
+}
+
+// gamma K~ (+ identity) of the kernel-space instances with m + 2 > 64 (nine column blocks
+// cover m <= 128), into the instance's T scratch as rows a <= m, columns b <= m + 1 (row
+// stride m + 2), for k_kkt.  A kernel of its own: its nine accumulator tiles per wavefront
+// would cost k_kkt's other instances their occupancy.
+__global__ __launch_bounds__(NYLS_BLOCK) void k_kkt_mfma_wide(const nyls_desc* __restrict__ desc,
+                                                         const int32_t* __restrict__ order,
+                                                         double* __restrict__ wsbase, int single,
+                                                         int eigbasis, int only) {
+  const int inst = single >= 0 ? single : instance_of(order);
+  const nyls_desc& d = desc[inst];
+  const int m = d.m, g = m + 2;
+  if (g <= 64) return;
+  const nyls_wsl L = nyls_layout(m, d.p, 0);
+  double* ws = wsbase + d.ws;
+  if (only && !((int)ws[L.info + 1] & only)) return;
+  if (eigbasis || ws[L.info + 4] != 0.0) return;
+  const int r = (int)ws[L.info + 0];
+  double* T = ws + L.tmp;
+  kkt_transform_mfma<(NYLS_MAX_M + 2 + 15) / 16>(ws + L.gram, ws + L.W, m, r, d.gamma,
+                        [&](int a, int b, double v) { T[a * g + b] = v; });
 }
 
 __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict__ desc,
@@ -95,7 +119,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
   double* ws = wsbase + d.ws;
   const double* W = ws + L.W;
   const double* S = ws + L.gram;
-  double* T = ws + L.tmp;  // T = S W  (m x m, global scratch)
+  const double* T = ws + L.tmp;  // gamma K~ from k_kkt_mfma_wide (m + 2 > 64)
   const int tid = threadIdx.x;
   const int r = (int)ws[L.info + 0];
   const double gam = d.gamma;
@@ -107,19 +131,22 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
   int* piv = reinterpret_cast<int*>(red + 16);  // [N + 1]
   int* perm = piv + (N + 1);                     // [N + 1]
 
-  // T = S W over the landmark block (kernel-space Gram only); with the eigenbasis Gram
-  // (rows rotated by U^T) the transform is the diagonal Lambda^{-1/2}.
+  // Kernel-space Gram: the (omega, b) block and its rhs are W~^T S~ W~ from the matrix cores
+  // (here for g <= 64, from k_kkt_mfma_wide in the T scratch otherwise); with the eigenbasis
+  // Gram (rows rotated by U^T) the transform is the diagonal Lambda^{-1/2}.
   const double* lamv = ws + L.lam;
   if (!eigbasis) eigbasis = ws[L.info + 4] != 0.0 ? 1 : 0;  // per-instance choice of the FP64 Gram
-  const bool mx = !eigbasis && g <= 64;  // (omega, b) block and rhs from the MFMA product
-  if (mx) kkt_transform_mfma(S, W, m, r, gam, K, lda, rhs);
-  else if (!eigbasis)
-    for (int e = tid; e < m * m; e += NYLS_BLOCK) {
-      const int a = e / m, k = e - a * m;
-      double acc = 0.0;
-      if (k < r)
-        for (int s = 0; s < m; ++s) acc += S[a * g + s] * W[s * m + k];
-      T[a * m + k] = acc;
+  const bool mx = !eigbasis;
+  if (mx && g <= 64)
+    kkt_transform_mfma<4>(S, W, m, r, gam, [&](int a, int b, double v) {
+      if (b <= m) K[a * lda + b] = v;
+      else rhs[a] = v;
+    });
+  else if (mx)
+    for (int e = tid; e < (m + 1) * (m + 2); e += NYLS_BLOCK) {
+      const int a = e / (m + 2), b = e - a * (m + 2);
+      if (b <= m) K[a * lda + b] = T[a * g + b];
+      else rhs[a] = T[a * g + b];
     }
   // condition kernel vectors k^(d_j)(t_{i_j})
   const double inv_sigma = 1.0 / d.sigma;
@@ -158,14 +185,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
     if (mx && a <= m && b <= m) continue;
     double val = 0.0;
     if (a < m && b < m) {
-      if (a < r && b < r) {
-        double acc = 0.0;
-        if (eigbasis) {
-          acc = S[a * g + b] / sqrt(lamv[a] * lamv[b]);
-        } else {
-          for (int s = 0; s < m; ++s) acc += W[s * m + a] * T[s * m + b];
-        }
-        val = gam * acc + (a == b ? 1.0 : 0.0);
+      if (a < r && b < r) {  // eigenbasis Gram (the kernel-space block came from the MFMA product)
+        val = gam * (S[a * g + b] / sqrt(lamv[a] * lamv[b])) + (a == b ? 1.0 : 0.0);
       } else {
         val = (a == b) ? 1.0 : 0.0;
       }
@@ -173,11 +194,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
       const int k = a < m ? a : b, o = a < m ? b : a;  // k: feature index, o: b or lambda
       if (k < r) {
         if (o == m) {
-          double acc = 0.0;
-          if (eigbasis) acc = S[k * g + m] / sqrt(lamv[k]);
-          else
-            for (int s = 0; s < m; ++s) acc += W[s * m + k] * S[s * g + m];
-          val = gam * acc;
+          val = gam * (S[k * g + m] / sqrt(lamv[k]));  // eigenbasis (see above)
         } else {
           val = kc[(o - m - 1) * NYLS_MAX_M + k];  // h_j[k]
         }
@@ -194,11 +211,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
     double val;
     if (a < m) {
       double acc = 0.0;
-      if (a < r) {
-        if (eigbasis) acc = S[a * g + m + 1] / sqrt(lamv[a]);
-        else
-          for (int s = 0; s < m; ++s) acc += W[s * m + a] * S[s * g + m + 1];
-      }
+      if (a < r) acc = S[a * g + m + 1] / sqrt(lamv[a]);  // eigenbasis (see above)
       val = gam * acc;
     } else if (a == m) {
       val = gam * S[m * g + m + 1];
@@ -262,8 +275,11 @@ hipError_t nyls_launch_kkt(const nyls_plan_view& pv, double* ws, double* kkt_out
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_kkt),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const int kn = pv.maxm + 1 + NYLS_MAX_P;
+  const int eb = (pv.mode == NYLS_MIXED && !pv.only) ? 1 : 0;
+  if (pv.maxm + 2 > 64 && !eb)
+    hipLaunchKernelGGL(k_kkt_mfma_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, pv.d_order, ws,
+                       -1, eb, pv.only);
   hipLaunchKernelGGL(k_kkt, dim3(pv.batch), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws,
-                     kkt_out, rhs_out, kn, factor, -1, (pv.mode == NYLS_MIXED && !pv.only) ? 1 : 0,
-                     pv.only);
+                     kkt_out, rhs_out, kn, factor, -1, eb, pv.only);
   return hipGetLastError();
 }

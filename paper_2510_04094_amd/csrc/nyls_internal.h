@@ -24,13 +24,29 @@ struct nyls_desc {
   double sigma, gamma, tau;
   int64_t ws;            // first double of this instance's workspace block
   int64_t goff;          // first grid point of this instance in per-point outputs
+  int32_t chunk;         // NYLS_DF_SPLIT: grid points per workgroup (multiple of 64)
+  int32_t nchunks;       // NYLS_DF_SPLIT: ceil(n / chunk)
+  int64_t part;          // NYLS_DF_SPLIT: first double of the instance's partial sums
 };
+
+// Partial sums of split instances (offsets in doubles from nyls_desc::part): per chunk the
+// (m+2)^2 Gram partial, then per chunk the pass partial (m landmark sums, sum c rho, max |y|,
+// max change of y).
+__host__ __device__ inline int64_t nyls_split_gram(int m, int c) { return (int64_t)c * (m + 2) * (m + 2); }
+__host__ __device__ inline int64_t nyls_split_pass(int m, int nchunks, int c) {
+  return (int64_t)nchunks * (m + 2) * (m + 2) + (int64_t)c * (m + 3);
+}
+__host__ __device__ inline int64_t nyls_split_doubles(int m, int nchunks) {
+  return (int64_t)nchunks * ((m + 2) * (m + 2) + m + 3);
+}
 
 // nyls_desc::flags: which kernel variant takes the instance (set from the plan's tuning).
 enum {
   NYLS_DF_TAIL = 1,       // one-wave passes walk a last block of <= 4 landmarks in the tail layout
   NYLS_DF_GRAM_TAIL = 2,  // one-wave MFMA Gram accumulates a last block of <= 4 columns on the VALU
-  NYLS_DF_GRAM_VALU = 4   // FP64 Gram on the LDS-tile VALU kernel even when m + 2 <= 64
+  NYLS_DF_GRAM_VALU = 4,  // FP64 Gram on the LDS-tile VALU kernel even when m + 2 <= 64
+  NYLS_DF_SPLIT = 8       // Gram and refinement/output passes split over point chunks, one
+                          // workgroup per chunk (FP64 mode; never with NYLS_DF_TAIL)
 };
 
 // Per-instance workspace block (offsets in doubles from nyls_desc::ws).
@@ -59,9 +75,8 @@ __host__ __device__ inline nyls_wsl nyls_layout(int m, int p, int n_newton) {
   L.tmp = L.beta + m;            // g*g   scratch (S W products, eigenvectors when m is large)
   L.U = L.tmp + g * g;           // m*m   all eigenvectors (sorted, signed), U[s*m + k]
   L.log = L.U + (int64_t)m * m;  // plane-rotation log of the lane-parallel QL: 2 m^2 (c, s)
-                                 // entries when m <= 64, else empty
-  L.aux = L.log + (m <= 64 ? 4 * (int64_t)m * m : 0);  // Newton: constant block (m+2)^2 +
-                                                        // weighted Gram (m+2)^2
+                                 // entries
+  L.aux = L.log + 4 * (int64_t)m * m;  // Newton: constant block (m+2)^2 + weighted Gram (m+2)^2
   L.end = L.aux + (n_newton > 0 ? 2 * g * g : 0);
   L.end = (L.end + 7) & ~int64_t(7);
   return L;
@@ -341,7 +356,10 @@ struct nyls_plan_view {
   unsigned gcls_mask;       // bit nyls_gram_class(m) for the instances with m + 2 <= 64
   unsigned tl_mask;         // bit b: some rec == 1 instance of slot class b walks a tail layout
   unsigned ntl_mask;        // bit b: some instance of slot class b does not
-  int32_t eig_ql;           // tuning: 1 QL inside one wavefront per instance (m <= 64)
+  int32_t n_big;            // instances with m > 64
+  int32_t n_split;          // instances with NYLS_DF_SPLIT
+  int32_t max_chunks;       // largest nchunks of a split instance
+  int32_t eig_ql;           // tuning: 1 QL inside one wavefront per instance
   int32_t ql_lanes;         // tuning: instances per wavefront of the lane-parallel QL
   int32_t overlap;          // tuning: FP64 kernel-space Gram beside the eigensolver
 };

@@ -47,7 +47,7 @@ __global__ __launch_bounds__(64) void k_points(
   const int inst = instance_of(order, single);
   const nyls_desc& d = desc[inst];
   if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB ||
-      (!EX && (d.flags & NYLS_DF_TAIL)) != TL)
+      (!EX && (d.flags & NYLS_DF_TAIL)) != TL || (d.flags & NYLS_DF_SPLIT))
     return;  // another launch handles this instance
   if (only && !((int)wsbase[d.ws + nyls_layout(d.m, P, 0).info + 1] & only)) return;
   const int m = d.m, n = d.n;
@@ -313,6 +313,296 @@ __global__ __launch_bounds__(64) void k_points(
   }
 }
 
+// ---- instances split over point chunks (NYLS_DF_SPLIT) ----------------------------------
+//
+// The same passes with one workgroup (one wavefront) per chunk of d.chunk grid points: each
+// pass writes y_hat of its points and its partial sums (sum rho_i p_i per landmark,
+// sum c_i rho_i, max |y_hat|, max change of y_hat) to the instance's partial area;
+// k_combine_split then adds the chunks in chunk order and takes the refinement step of
+// k_points (same stopping rules), keeping the iteration's state in the instance's
+// accumulator block between launches.
+enum { SS_DONE = 0, SS_NEEDOUT, SS_CORR, SS_DPREV, SS_BPREV, SS_PASSES, SS_YMAX };
+
+__global__ void k_split_init(const nyls_desc* __restrict__ desc, double* __restrict__ wsbase, int batch) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  const nyls_desc& d = desc[i];
+  if (!(d.flags & NYLS_DF_SPLIT)) return;
+  double* st = wsbase + d.ws + nyls_layout(d.m, d.p, 0).acc;
+  st[SS_DONE] = 0.0;
+  st[SS_NEEDOUT] = 1.0;
+  st[SS_CORR] = st[SS_DPREV] = st[SS_BPREV] = st[SS_PASSES] = st[SS_YMAX] = 0.0;
+}
+
+template <int NB, int P, bool EX, bool REF>
+__global__ __launch_bounds__(64) void k_pass_split(const nyls_desc* __restrict__ desc,
+                                                   double* __restrict__ wsbase,
+                                                   double* __restrict__ yhat, int track) {
+  __shared__ __align__(16) double tile[2 * 16 * NYLS_WALK_PAD];
+  __shared__ double bc[16];
+  const nyls_desc& d = desc[blockIdx.x];
+  if (!(d.flags & NYLS_DF_SPLIT) || d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB)
+    return;
+  const int c = (int)blockIdx.y;
+  if (c >= d.nchunks) return;
+  const int m = d.m, n = d.n;
+  const nyls_wsl L = nyls_layout(m, P, 0);
+  double* ws = wsbase + d.ws;
+  const double* sst = ws + L.acc;
+  if (REF ? sst[SS_DONE] != 0.0 : sst[SS_NEEDOUT] == 0.0) return;
+  const int lane = threadIdx.x;
+  const int ibeg = c * d.chunk, iend = min(n, ibeg + d.chunk);
+  double* yo = yhat + d.goff;
+
+  nyls_walk<NB, EX> wk;
+  wk.init(d, lane);
+  nyls_cpts cpt;
+  cpt.init(d);
+  const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
+  const __amdgpu_buffer_rsrc_t fr = nyls_rsrc(d.f, P * n * 8), rr = nyls_rsrc(d.r, n * 8);
+  const __amdgpu_buffer_rsrc_t yr = nyls_rsrc(yhat + d.goff, n * 8);
+  double alv[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) alv[b] = wk.lv[b] ? ws[L.alpha + 16 * b + wk.sl] : 0.0;
+  const double bias = ws[L.x + m];
+  nyls_oppoly<P> op;
+  op.init(inv_s2);
+  constexpr int Q = REF ? 2 : 1;
+  double zacc[NB], sacc = 0.0, ymax = 0.0, dmax = 0.0;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) zacc[b] = 0.0;
+  struct stage {
+    double f[P][4];
+    double r, c, y;
+  };
+  auto load = [&](int i0, stage& st) {
+    const int ip = i0 + (lane & 15);
+    if (REF) {
+#pragma unroll
+      for (int k = 0; k < P; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) st.f[k][j] = nyls_bload(fr, (k * n + i0 + 4 * j + wk.ph) * 8);
+      st.r = nyls_bload(rr, ip * 8);
+      st.c = -nyls_bload(fr, ((P - 1) * n + ip) * 8);
+    }
+    st.y = track ? nyls_bload(yr, ip * 8) : 0.0;
+  };
+  auto body = [&](int i0, const stage& st) {
+    wk.advance(d, i0);
+    double cj[4][P];
+    if (REF)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double f[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) f[k] = st.f[k][j];
+        op.coef(f, cj[j]);
+      }
+    double pe[REF ? NB : 1][4];
+    double acc0 = 0.0, acc1 = 0.0;
+    wk.chunk(
+        d, i0,
+        [&](int bb, int j, double g, double e) {
+          if (REF) {
+            const double pv = e * nyls_horner<P>(g, cj[j]);
+            pe[REF ? bb : 0][j] = pv;
+            acc1 += alv[bb] * pv;
+          }
+          acc0 += alv[bb] * e;
+        },
+        [&](int j) {
+          nyls_walk_put(tile, lane, 0, j, acc0);
+          if (REF) nyls_walk_put(tile, lane, 1, j, acc1);
+          acc0 = acc1 = 0.0;
+        });
+    double tot[Q];
+    nyls_walk_sum<Q>(tile, lane, tot);
+    const int ip = i0 + (lane & 15);
+    const double yv = tot[0] + bias;
+    if (ip < n) {
+      if (lane < 16) {
+        if (track) dmax = fmax(dmax, fabs(yv - st.y));
+        yo[ip] = yv;
+      }
+      ymax = fmax(ymax, fabs(yv));
+    }
+    if (REF) {
+      const bool okp = ip < n && !cpt.has(ip);
+      const double rho = okp ? st.r - tot[Q - 1] - st.c * bias : 0.0;
+      if (lane < 16) sacc += st.c * rho;
+      const double w1[1] = {rho};
+      double rj[1][4];
+      nyls_walk_bcast<1>(w1, bc, lane, rj);
+#pragma unroll
+      for (int bb = 0; bb < NB; ++bb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) zacc[bb] += rj[0][j] * pe[REF ? bb : 0][j];
+    }
+  };
+  stage sa, sb;
+  load(ibeg, sa);
+  for (int i0 = ibeg; i0 < iend; i0 += 32) {
+    load(i0 + 16, sb);
+    body(i0, sa);
+    if (i0 + 16 >= iend) break;
+    load(i0 + 32, sa);
+    body(i0 + 16, sb);
+  }
+  double* part = wsbase + d.part + nyls_split_pass(m, d.nchunks, c);
+  ymax = nyls_wave_max(ymax);
+  dmax = nyls_wave_max(dmax);
+  if (REF) {
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      const double zb = nyls_walk_fold(zacc[bb]);
+      if (wk.ph == 0 && wk.lv[bb]) part[16 * bb + wk.sl] = zb;
+    }
+  }
+  const double ssum = nyls_wave_sum(sacc);
+  if (lane == 0) {
+    part[m] = ssum;
+    part[m + 1] = ymax;
+    part[m + 2] = dmax;
+  }
+}
+
+// One refinement step (fin == 0, step `step` of at most `refine`) or the final bookkeeping
+// (fin == 1) of a split instance, one wavefront per instance.
+template <int P>
+__global__ __launch_bounds__(64) void k_combine_split(
+    const nyls_desc* __restrict__ desc, double* __restrict__ wsbase, int step, int refine, int fin,
+    double* __restrict__ omega_out, double* __restrict__ bias_out, double* __restrict__ lambda_out,
+    int32_t* __restrict__ status, int maxm, double tol_stop, double tol_flag) {
+  __shared__ double Rv[NK], xv[NK], zs[NYLS_MAX_M];
+  __shared__ int piv[NK];
+  const int inst = (int)blockIdx.x;
+  const nyls_desc& d = desc[inst];
+  if (!(d.flags & NYLS_DF_SPLIT) || d.p != P) return;
+  const int m = d.m, N = m + 1 + P, nc = d.nchunks;
+  const nyls_wsl L = nyls_layout(m, P, 0);
+  double* ws = wsbase + d.ws;
+  double* sst = ws + L.acc;
+  const double* part = wsbase + d.part;
+  const int lane = threadIdx.x;
+  auto pmax = [&](int k) {  // max over the chunks of pass-partial entry m + k
+    double v = 0.0;
+    for (int c = lane; c < nc; c += 64) v = fmax(v, part[nyls_split_pass(m, nc, c) + m + k]);
+    return nyls_wave_max(v);
+  };
+  if (fin) {
+    double ymax = sst[SS_YMAX], corr = sst[SS_CORR];
+    if (sst[SS_NEEDOUT] != 0.0) {  // the output pass ran: it measured the last correction
+      ymax = pmax(1);
+      corr = pmax(2);
+    }
+    const double bias = ws[L.x + m];
+    if (omega_out)
+      for (int k = lane; k < maxm; k += 64) omega_out[(size_t)inst * maxm + k] = k < m ? ws[L.x + k] : 0.0;
+    if (lambda_out && lane < NYLS_MAX_P)
+      lambda_out[(size_t)inst * NYLS_MAX_P + lane] = lane < P ? ws[L.x + m + 1 + lane] : 0.0;
+    if (lane == 0) {
+      if (bias_out) bias_out[inst] = bias;
+      int bits = (int)ws[L.info + 1] & ~NYLS_S_REFINE_NOCONV;
+      if (!(fabs(bias) <= 1.7976931348623157e308)) bits |= NYLS_S_NONFINITE;
+      if (refine > 0 && corr > tol_flag * ymax) bits |= NYLS_S_REFINE_NOCONV;
+      ws[L.info + 1] = (double)bits;
+      ws[L.info + 3] = corr;
+      ws[L.info + 5] = sst[SS_PASSES];
+      if (status) status[inst] = bits;
+    }
+    return;
+  }
+  if (sst[SS_DONE] != 0.0) return;
+  const double ymax = pmax(1);
+  const double dmax = pmax(2);
+  double corr = sst[SS_CORR], dprev = sst[SS_DPREV], bprev = sst[SS_BPREV];
+  bool done = false, needout = true;
+  auto save = [&]() {
+    if (lane == 0) {
+      sst[SS_DONE] = done ? 1.0 : 0.0;
+      sst[SS_NEEDOUT] = needout ? 1.0 : 0.0;
+      sst[SS_CORR] = corr;
+      sst[SS_DPREV] = dprev;
+      sst[SS_BPREV] = bprev;
+      sst[SS_PASSES] += 1.0;
+      sst[SS_YMAX] = ymax;
+    }
+  };
+  if (step > 0) {
+    const bool stalled = step > 1 && dmax > 0.5 * dprev;
+    dprev = corr = dmax;
+    if (dmax <= tol_stop * ymax || stalled) {
+      done = true;
+      needout = false;
+      save();
+      return;
+    }
+  }
+  // the residual from the chunk sums (added in chunk order), as in k_points
+  const int r = (int)ws[L.info + 0];
+  const double* W = ws + L.W;
+  for (int s = lane; s < m; s += 64) {
+    double acc = 0.0;
+    for (int c = 0; c < nc; ++c) acc += part[nyls_split_pass(m, nc, c) + s];
+    zs[s] = acc;
+  }
+  double ssum = 0.0;
+  if (lane == 0)
+    for (int c = 0; c < nc; ++c) ssum += part[nyls_split_pass(m, nc, c) + m];
+  ssum = nyls_rdlane(ssum, 0);
+  for (int e = lane; e < N; e += 64) {
+    xv[e] = ws[L.x + e];
+    piv[e] = (int)ws[L.piv + e];
+  }
+  __syncthreads();
+  const double gam = d.gamma;
+  for (int e = lane; e < N; e += 64) {
+    double val = 0.0;
+    if (e < m) {
+      if (e < r) {
+        double acc = 0.0;
+        for (int s = 0; s < m; ++s) acc += W[s * m + e] * zs[s];
+        val = gam * acc - xv[e];
+        for (int j = 0; j < P; ++j) val -= ws[L.H + j * m + e] * xv[m + 1 + j];
+      }
+    } else if (e == m) {
+      val = gam * ssum;
+      for (int j = 0; j < P; ++j) val -= (d.cond_d[j] == 0 ? 1.0 : 0.0) * xv[m + 1 + j];
+    } else {
+      const int j = e - m - 1;
+      val = d.v[j] - (d.cond_d[j] == 0 ? xv[m] : 0.0);
+      for (int k = 0; k < r; ++k) val -= ws[L.H + j * m + k] * xv[k];
+    }
+    Rv[e] = val;
+  }
+  __syncthreads();
+  nyls_lu_solve_w(ws + L.lu, N, N, piv, Rv);
+  for (int e = lane; e < N; e += 64) {
+    xv[e] += Rv[e];
+    ws[L.x + e] = xv[e];
+  }
+  __syncthreads();
+  for (int s = lane; s < m; s += 64) {
+    double acc = 0.0;
+    for (int k = 0; k < r; ++k) acc += W[s * m + k] * xv[k];
+    ws[L.alpha + s] = acc;
+  }
+  double dsq = 0.0;
+  for (int k = lane; k < r; k += 64) dsq += Rv[k] * Rv[k];
+  const double bound = sqrt(nyls_wave_sum(dsq)) + fabs(Rv[m]);
+  if (bound <= tol_stop * ymax) {
+    corr = bound;
+    done = true;
+    needout = false;
+  } else {
+    const double pred = step > 0 && bprev > 0.0 ? corr * (bound / bprev) : bound;
+    if (pred <= tol_stop * ymax) done = true;
+    bprev = bound;
+  }
+  if (step + 1 >= refine) done = true;  // step limit: the output pass applies the correction
+  save();
+}
+
 template <int NB, bool EX, bool TL>
 void launch_nbx(const nyls_plan_view& pv, double* ws, int refine, double* yhat, double* omega,
                 double* bias, double* lambda, int32_t* status, int single, double ts, double tf,
@@ -351,11 +641,70 @@ hipError_t launch_nb(const nyls_plan_view& pv, double* ws, int refine, double* y
 
 }  // namespace
 
+namespace {
+template <int NB, int P, bool EX>
+void launch_pass_split(const nyls_plan_view& pv, double* ws, double* yhat, bool ref, int track,
+                       hipStream_t st) {
+  const dim3 grid(pv.batch, pv.max_chunks);
+  if (ref) hipLaunchKernelGGL((k_pass_split<NB, P, EX, true>), grid, dim3(64), 0, st, pv.d_desc, ws, yhat, track);
+  else hipLaunchKernelGGL((k_pass_split<NB, P, EX, false>), grid, dim3(64), 0, st, pv.d_desc, ws, yhat, track);
+}
+
+template <int NB, int P>
+void launch_pass_split_p(const nyls_plan_view& pv, double* ws, double* yhat, bool ref, int track,
+                         hipStream_t st) {
+  if (!(pv.p_mask & (1u << P))) return;
+  if (pv.rec_mask & 2) launch_pass_split<NB, P, false>(pv, ws, yhat, ref, track, st);
+  if (pv.rec_mask & 1) launch_pass_split<NB, P, true>(pv, ws, yhat, ref, track, st);
+}
+
+template <int NB>
+void launch_pass_split_nb(const nyls_plan_view& pv, double* ws, double* yhat, bool ref, int track,
+                          hipStream_t st) {
+  if (!(pv.nb_mask & (1u << NB))) return;
+  launch_pass_split_p<NB, 1>(pv, ws, yhat, ref, track, st);
+  launch_pass_split_p<NB, 2>(pv, ws, yhat, ref, track, st);
+  launch_pass_split_p<NB, 3>(pv, ws, yhat, ref, track, st);
+  launch_pass_split_p<NB, 4>(pv, ws, yhat, ref, track, st);
+}
+
+void launch_combine(const nyls_plan_view& pv, double* ws, int step, int refine, int fin, double* omega,
+                    double* bias, double* lambda, int32_t* status, double ts, double tf, hipStream_t st) {
+  const dim3 grid(pv.batch);
+  if (pv.p_mask & 2) hipLaunchKernelGGL(k_combine_split<1>, grid, dim3(64), 0, st, pv.d_desc, ws, step, refine, fin, omega, bias, lambda, status, pv.maxm, ts, tf);
+  if (pv.p_mask & 4) hipLaunchKernelGGL(k_combine_split<2>, grid, dim3(64), 0, st, pv.d_desc, ws, step, refine, fin, omega, bias, lambda, status, pv.maxm, ts, tf);
+  if (pv.p_mask & 8) hipLaunchKernelGGL(k_combine_split<3>, grid, dim3(64), 0, st, pv.d_desc, ws, step, refine, fin, omega, bias, lambda, status, pv.maxm, ts, tf);
+  if (pv.p_mask & 16) hipLaunchKernelGGL(k_combine_split<4>, grid, dim3(64), 0, st, pv.d_desc, ws, step, refine, fin, omega, bias, lambda, status, pv.maxm, ts, tf);
+}
+
+// The refinement and output passes of the split instances: at most `refine` (pass, step)
+// pairs, then the output pass and the final bookkeeping; launches of instances that have
+// stopped return at once.
+void launch_split_points(const nyls_plan_view& pv, double* ws, int refine, double* yhat, double* omega,
+                         double* bias, double* lambda, int32_t* status, hipStream_t st) {
+  const double ts = 1e-11, tf = 1e-8;  // as in launch_nb
+  hipLaunchKernelGGL(k_split_init, dim3((pv.batch + 255) / 256), dim3(256), 0, st, pv.d_desc, ws, pv.batch);
+  auto pass = [&](bool ref, int track) {
+    launch_pass_split_nb<2>(pv, ws, yhat, ref, track, st);
+    launch_pass_split_nb<4>(pv, ws, yhat, ref, track, st);
+    launch_pass_split_nb<8>(pv, ws, yhat, ref, track, st);
+  };
+  for (int step = 0; step < refine; ++step) {
+    pass(true, step > 0);
+    launch_combine(pv, ws, step, refine, 0, omega, bias, lambda, status, ts, tf, st);
+  }
+  pass(false, refine > 0);
+  launch_combine(pv, ws, 0, refine, 1, omega, bias, lambda, status, ts, tf, st);
+}
+}  // namespace
+
 hipError_t nyls_launch_points(const nyls_plan_view& pv, double* ws, int refine, double* yhat,
                               double* omega, double* bias, double* lambda, int32_t* status,
                               int single, hipStream_t st) {
   if (pv.nb_mask & 4) launch_nb<2>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
   if (pv.nb_mask & 16) launch_nb<4>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
   if (pv.nb_mask & 256) launch_nb<8>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
+  if (pv.n_split && single < 0 && !pv.only)
+    launch_split_points(pv, ws, refine, yhat, omega, bias, lambda, status, st);
   return hipGetLastError();
 }

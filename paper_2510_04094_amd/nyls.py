@@ -42,11 +42,11 @@ class Problem(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """nyls_tuning: the plan's launch choices (include/nyls.h)."""
     _fields_ = [("eig_ql", ctypes.c_int32), ("ql_lanes", ctypes.c_int32), ("gram_valu", ctypes.c_int32),
-                ("tail_layout", ctypes.c_int32), ("overlap", ctypes.c_int32)]
+                ("tail_layout", ctypes.c_int32), ("overlap", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 TUNING_FIELDS = tuple(name for name, _ in Tuning._fields_)
-DEFAULT_TUNING = dict(eig_ql=0, ql_lanes=64, gram_valu=0, tail_layout=1, overlap=1)
+DEFAULT_TUNING = dict(eig_ql=0, ql_lanes=64, gram_valu=0, tail_layout=1, overlap=1, split=-1)
 
 
 EXPORTS = {
@@ -249,6 +249,12 @@ class Batch:
             cur[k] = int(v)
         t = Tuning(**cur)
         _check(_lib.nyls_plan_set_tuning(self.plan, ctypes.byref(t)), "nyls_plan_set_tuning")
+        # the workspace size depends on the split choice: grow it when needed (its contents
+        # are rebuilt by the next solve)
+        nbytes = int(_lib.nyls_workspace_size(self.plan))
+        if nbytes > self.ws.numel():
+            self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=self.device)
+            self.ws_version += 1
 
     def __del__(self):
         if getattr(self, "plan", None) is not None and _lib is not None:

@@ -19,6 +19,8 @@ def test_key_names_arch_bucket_orders_and_mode():
 def test_knob_values_skip_choices_that_cannot_apply():
     k = autotune.knob_values(50, 50, nyls.FP64)
     assert set(k) == {"eig_ql", "ql_lanes", "gram_valu", "tail_layout", "overlap"}
+    k = autotune.knob_values(50, 50, nyls.FP64, max_n=50000)
+    assert "split" in k and k["split"][0] == nyls.DEFAULT_TUNING["split"]
     k = autotune.knob_values(100, 70, nyls.FP64)
     assert "eig_ql" not in k and "gram_valu" not in k  # every basis beyond the one-wave kernels
     k = autotune.knob_values(50, 20, nyls.MIXED)

@@ -172,7 +172,8 @@ def test_random_landmarks_match_oracle(gpu_lib, mode_name):
 def test_long_single_instances(gpu_lib, mode_name):
     """Long-time single instances, each its own batch of one: n = 5e4 points over t in
     [0, 20] and [0, 25] with m = 100 and the largest basis (m = 128, 126 in the mixed mode:
-    Jacobi eigensolver, LDS Gram, 256-thread LU); first-order family, sigma = 0.3, cut-off 1e-10 (K_mm keeps
+    two-rows-per-lane QL eigensolver, LDS Gram, 256-thread LU; the FP64 plan splits the
+    instance over point chunks); first-order family, sigma = 0.3, cut-off 1e-10 (K_mm keeps
     lambda_r / lambda_1 ~ 7e-3, so the first-order FP64 bar applies)."""
     import time
     mmax = 128 if mode_name == "FP64" else 126  # the FP32 Gram holds m + 2 <= 128 columns
@@ -239,7 +240,9 @@ def test_mixed_without_refinement_is_worse(gpu_lib):
     sols = oracle_solutions(insts)
     e0 = max(rel_inf(y0[i], s["yhat"]) for i, s in enumerate(sols))
     e1 = max(rel_inf(y1[i], s["yhat"]) for i, s in enumerate(sols))
-    assert e1 < e0
+    print("mixed rel err without / with refinement: %.2e / %.2e" % (e0, e1))
+    assert e1 <= 1e-6 < e0  # the FP32 Gram alone misses the bound; the refined solve meets it
+    assert e0 >= 100 * e1
 
 
 ASSEMBLE_SETS = {
