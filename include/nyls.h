@@ -77,12 +77,13 @@ enum {
   NYLS_S_TRUNCATED = 1,       /* info: the basis kept r < m eigenpairs */
   NYLS_S_SINGULAR = 2,        /* a zero pivot in the KKT / Schur factorisation */
   NYLS_S_NONFINITE = 4,       /* a NaN or Inf appeared in the solution */
-  NYLS_S_EIG_NOCONV = 8,      /* the Jacobi eigensolver hit its sweep limit */
+  NYLS_S_EIG_NOCONV = 8,      /* the eigensolver hit its iteration limit */
   NYLS_S_SMALL_PIVOT = 16,    /* Newton: a diagonal y-block entry |d_i| < 1e-10 gamma */
   NYLS_S_REFINE_NOCONV = 32,  /* refinement ended with its last change of y_hat above
                                  1e-8 max|y_hat| */
-  NYLS_S_FP64_RESOLVED = 64   /* NYLS_MIXED: refinement on the FP32 Gram did not converge, the
+  NYLS_S_FP64_RESOLVED = 64,  /* NYLS_MIXED: refinement on the FP32 Gram did not converge, the
                                  instance was solved again with the FP64 Gram */
+  NYLS_S_PARAM_KEPT = 128     /* nyls_plan_set_params: the new sigma or gamma was not taken */
 };
 
 /*
@@ -126,6 +127,17 @@ typedef struct nyls_plan nyls_plan;
  * into them are picked up by the next call.  Returns 0 or a NYLS_E* code (then *out = NULL). */
 int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyls_plan** out);
 void nyls_plan_destroy(nyls_plan* plan);
+/* sigma and gamma of every instance from DEVICE arrays [batch] (Sec. 3.1: the kernel width
+ * and the weight of the residual term), written into the plan's device descriptors by a
+ * kernel on `stream`: no host synchronisation, so a training loop or a captured graph can
+ * change them between solves without rebuilding the plan.  Either array may be NULL (kept).
+ * A value that is not finite and positive, or a sigma below 4 dt for an instance whose plan
+ * uses the strided Gaussian recurrence (uniform grid created with dt <= sigma / 4), is not
+ * taken: that instance keeps both previous values and status[i] = NYLS_S_PARAM_KEPT, else
+ * status[i] = 0 (status may be NULL).  The values persist for later calls, including across
+ * nyls_plan_set_tuning.  Returns NYLS_E_NULL for a NULL plan. */
+int nyls_plan_set_params(nyls_plan* plan, const double* sigma, const double* gamma, int32_t* status,
+                         hipStream_t stream);
 /* Launch choices of a plan (set by nyls_plan_set_tuning, e.g. from an autotuner's cache).
  * Every combination computes the same method; they differ in speed, and in rounding only
  * where the arithmetic order differs (the Gram path and its last column block, the point

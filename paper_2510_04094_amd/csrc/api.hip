@@ -353,6 +353,34 @@ void nyls_plan_destroy(nyls_plan* pl) {
   delete pl;
 }
 
+}  // extern "C"
+
+namespace {
+__global__ void k_set_params(nyls_desc* __restrict__ desc, const double* __restrict__ sigma,
+                             const double* __restrict__ gamma, int32_t* __restrict__ status, int batch) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  nyls_desc& d = desc[i];
+  const double s = sigma ? sigma[i] : d.sigma, g = gamma ? gamma[i] : d.gamma;
+  const bool ok = isfinite(s) && s > 0.0 && isfinite(g) && g > 0.0 && (d.rec != 1 || d.dt <= 0.25 * s);
+  if (ok) {
+    d.sigma = s;
+    d.gamma = g;
+  }
+  if (status) status[i] = ok ? 0 : NYLS_S_PARAM_KEPT;
+}
+}  // namespace
+
+extern "C" {
+
+int nyls_plan_set_params(nyls_plan* pl, const double* sigma, const double* gamma, int32_t* status,
+                         hipStream_t stream) {
+  if (!pl) return NYLS_E_NULL;
+  hipLaunchKernelGGL(k_set_params, dim3((pl->batch + 255) / 256), dim3(256), 0, stream, pl->d_desc, sigma,
+                     gamma, status, pl->batch);
+  return hip_rc(hipGetLastError());
+}
+
 int nyls_plan_set_tuning(nyls_plan* pl, const nyls_tuning* t) {
   if (!pl || !t) return NYLS_E_NULL;
   if ((t->eig_ql != 0 && t->eig_ql != 1) || t->ql_lanes < 1 || t->ql_lanes > 64 ||
@@ -360,6 +388,14 @@ int nyls_plan_set_tuning(nyls_plan* pl, const nyls_tuning* t) {
       (t->overlap != 0 && t->overlap != 1) ||
       (t->split != -1 && t->split != 0 && (t->split < 512 || t->split % 64 != 0 || t->split > (1 << 24))))
     return NYLS_E_ARG;
+  // sigma and gamma may have been changed on the device (nyls_plan_set_params): keep them
+  std::vector<nyls_desc> cur(pl->batch);
+  if (hipMemcpy(cur.data(), pl->d_desc, sizeof(nyls_desc) * pl->batch, hipMemcpyDeviceToHost) != hipSuccess)
+    return NYLS_E_HIP;
+  for (int i = 0; i < pl->batch; ++i) {
+    pl->h_desc[i].sigma = cur[i].sigma;
+    pl->h_desc[i].gamma = cur[i].gamma;
+  }
   pl->tune = *t;
   apply_tuning(pl);
   return hipMemcpy(pl->d_desc, pl->h_desc.data(), sizeof(nyls_desc) * pl->batch,
@@ -608,10 +644,11 @@ const char* nyls_error_string(int32_t code) {
     case NYLS_S_TRUNCATED: return "basis truncated (r < m)";
     case NYLS_S_SINGULAR: return "zero pivot in the factorisation";
     case NYLS_S_NONFINITE: return "non-finite value in the solution";
-    case NYLS_S_EIG_NOCONV: return "eigensolver hit its sweep limit";
+    case NYLS_S_EIG_NOCONV: return "eigensolver hit its iteration limit";
     case NYLS_S_SMALL_PIVOT: return "Newton diagonal block entry below 1e-10 gamma";
     case NYLS_S_REFINE_NOCONV: return "iterative refinement did not reach rounding level";
     case NYLS_S_FP64_RESOLVED: return "solved again with the FP64 Gram";
+    case NYLS_S_PARAM_KEPT: return "new sigma or gamma not taken";
     default: return "unknown code";
   }
 }

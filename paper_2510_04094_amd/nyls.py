@@ -19,6 +19,7 @@ MAX_N = 1 << 25
 FP64, MIXED, FP64_EXPLICIT = 0, 1, 2
 S_TRUNCATED, S_SINGULAR, S_NONFINITE, S_EIG_NOCONV, S_SMALL_PIVOT, S_REFINE_NOCONV = 1, 2, 4, 8, 16, 32
 S_FP64_RESOLVED = 64
+S_PARAM_KEPT = 128
 
 _lib = None
 
@@ -51,6 +52,8 @@ DEFAULT_TUNING = dict(eig_ql=0, ql_lanes=64, gram_valu=0, tail_layout=1, overlap
 
 EXPORTS = {
     "nyls_plan_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "nyls_plan_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
     "nyls_plan_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "nyls_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "nyls_plan_destroy": (None, [ctypes.c_void_p]),
@@ -311,11 +314,22 @@ class Batch:
         return kkt, rhs
 
     def _offsets(self, t_eval_list):
+        """Device copies of per-instance evaluation times and their offsets.  The last few
+        time sets are kept on the device, so repeated calls with the same times (a training
+        loop, a graph capture after an eager warm-up) copy nothing from the host."""
         counts = [len(t) for t in t_eval_list]
         off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
-        t = torch.tensor(np.concatenate([np.asarray(x, dtype=np.float64) for x in t_eval_list]),
-                         dtype=torch.float64, device=self.device)
+        host = np.concatenate([np.asarray(x, dtype=np.float64) for x in t_eval_list])
+        key = (host.tobytes(), off.tobytes())
+        cache = self.__dict__.setdefault("_offset_cache", {})
+        hit = cache.get(key)
+        if hit is not None:
+            return hit[0], hit[1], off
+        t = torch.tensor(host, dtype=torch.float64, device=self.device)
         o = torch.tensor(off, dtype=torch.int64, device=self.device)
+        if len(cache) >= 8:
+            cache.pop(next(iter(cache)))
+        cache[key] = (t, o)
         return t, o, off
 
     def features(self, t_eval_list, dmax):
@@ -430,9 +444,11 @@ class Batch:
 
     # --- adjoint --------------------------------------------------------------------------
     def set_params(self, sigma=None, gamma=None):
-        """Change per-instance sigma and/or gamma ([batch] arrays): rebuilds the plan (host
-        validation and descriptor upload); the workspace keeps its size."""
+        """Change per-instance sigma and/or gamma ([batch] host arrays): rebuilds the plan
+        (host validation, which may change the recurrence choice, and descriptor upload) and
+        keeps its tuning."""
         lib = load()
+        tuning = self.get_tuning()
         for i in range(self.batch):
             if sigma is not None:
                 self._probs[i].sigma = float(sigma[i])
@@ -443,9 +459,32 @@ class Batch:
                                     ctypes.byref(handle)), "nyls_plan_create")
         lib.nyls_plan_destroy(self.plan)
         self.plan = handle
+        self.set_tuning(**tuning)
+
+    def set_params_device(self, sigma=None, gamma=None):
+        """nyls_plan_set_params: sigma and/or gamma from device tensors [batch] (float64),
+        without a host synchronisation (capturable).  Returns the int32 status tensor:
+        S_PARAM_KEPT where a value was not taken (see the header)."""
+        status = torch.empty(self.batch, dtype=torch.int32, device=self.device)
+        args = []
+        for x in (sigma, gamma):
+            if x is None:
+                args.append(None)
+            else:
+                x = x.to(device=self.device, dtype=torch.float64).reshape(-1).contiguous()
+                if x.numel() != self.batch:
+                    raise NylsError("set_params_device: expected %d values" % self.batch)
+                args.append(x)
+        self._param_args = args  # keep the tensors alive until the kernel has read them
+        _check(_lib.nyls_plan_set_params(self.plan, _ptr(args[0]), _ptr(args[1]), _ptr(status), _stream()),
+               "nyls_plan_set_params")
+        if sigma is not None or gamma is not None:
+            self._params_on_device = True
+        return status
 
     def params(self):
-        """Current per-instance (sigma, gamma) as numpy arrays."""
+        """Per-instance (sigma, gamma) of the last host-side setting, as numpy arrays (values
+        set with set_params_device live on the device only)."""
         return (np.array([self._probs[i].sigma for i in range(self.batch)]),
                 np.array([self._probs[i].gamma for i in range(self.batch)]))
 
@@ -496,9 +535,11 @@ class SolveAtObservations(torch.autograd.Function):
     forward(batch, t_obs_list, f, r, v, sigma, gamma) -> y_obs [sum of observation counts]
       f [sum p_i n_i] (instance blocks [p][n], the layout of Batch.f), r [total points],
       v [batch, 4] (condition values, zero-padded), sigma [batch], gamma [batch].
-    The values are written into the batch's device arrays (sigma / gamma changes rebuild the
-    plan), then nyls_solve and nyls_predict run; backward calls nyls_backward, which reuses
-    the factorisation, and maps dl/df, dl/dr, dl/dv, dl/dsigma, dl/dgamma onto the inputs.
+    The values are written into the batch's device arrays and sigma / gamma into the plan's
+    device descriptors (nyls_plan_set_params, no host synchronisation), then nyls_solve and
+    nyls_predict run; backward calls nyls_backward, which reuses the factorisation, and maps
+    dl/df, dl/dr, dl/dv, dl/dsigma, dl/dgamma onto the inputs.  Forward and backward can be
+    captured in a HIP graph with static input tensors.
     """
 
     @staticmethod
@@ -507,11 +548,13 @@ class SolveAtObservations(torch.autograd.Function):
             batch.f.copy_(f.detach().reshape(-1))
             batch.r.copy_(r.detach().reshape(-1))
             batch.v.copy_(v.detach().reshape(-1))
-            s_new = sigma.detach().cpu().numpy()
-            g_new = gamma.detach().cpu().numpy()
-            s_old, g_old = batch.params()
-            if not (np.array_equal(s_new, s_old) and np.array_equal(g_new, g_old)):
-                batch.set_params(sigma=s_new, gamma=g_new)
+            # sigma and gamma go to the plan's descriptors on the device (no host round trip,
+            # so forward and backward can be captured in a graph); outside a capture a value
+            # the device update refuses (a sigma that breaks the plan's recurrence choice) is
+            # taken by rebuilding the plan instead
+            status = batch.set_params_device(sigma.detach(), gamma.detach())
+            if not torch.cuda.is_current_stream_capturing() and bool(torch.any(status != 0)):
+                batch.set_params(sigma=sigma.detach().cpu().numpy(), gamma=gamma.detach().cpu().numpy())
             batch.solve()
         return batch.ws_version
 
