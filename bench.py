@@ -103,6 +103,25 @@ def _floor_bar(args):
     return fp64_floor.bar(workloads.linear_second_order(i, n=n, m=m, config=seed_config, obs=100))
 
 
+def _oracle_err_newton(args):
+    """rel. l-inf distance of a GPU Newton y_hat from the oracle's after the same number of
+    Newton steps (Riccati instance i, two Gauss-Newton steps first)."""
+    i, iters, got = args
+    import oracle
+    from paper_2510_04094_amd import workloads
+    p = workloads.riccati(i)
+    st = oracle.newton.setup(p)
+    x = oracle.newton.initial_state(st, p)
+
+    def fun(gn):
+        return lambda idx, y: (p["q"][idx] - y * y, -2.0 * y, (0.0 if gn else -2.0) * np.ones_like(y))
+    for k in range(iters):
+        x, _ = oracle.newton.step_schur(x, st, p, fun(k < 2))
+    r = st["r"]
+    ref = oracle.nystrom.kvec(0, st["t"], st["t_land"], p["sigma"]) @ (st["W"] @ x[:r]) + x[r]
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
 def _oracle_err_uneven(args):
     """The same for instance i of the uneven batch."""
     i, count, got = args
@@ -351,6 +370,43 @@ def uneven_batch_rate(nyls, mode, count, steps, procs, check, tune):
     return res
 
 
+def newton_rate(nyls, count, steps, procs, check):
+    """Lemma 2 Newton on the Riccati batch (count instances of y' = q - y^2, n = 2000, m = 50,
+    sigma = 0.1, gamma = 1e6): whole solves (two Gauss-Newton steps, then Newton to
+    |dx| <= 1e-12 max(1, |x|), the right-hand side evaluated on the device, one host check
+    of the stopping test per step), every instance checked against the oracle after the same
+    number of steps."""
+    import torch
+    from paper_2510_04094_amd import workloads
+    insts = [workloads.riccati(i) for i in range(count)]
+    b = nyls.Batch(insts, mode=nyls.FP64)
+    q = torch.tensor(np.concatenate([p["q"] for p in insts]), dtype=torch.float64, device="cuda")
+    b.riccati_newton(q, max_iter=15, tol=1e-12, gauss_newton_steps=2)
+    torch.cuda.synchronize()
+    nyls.profile_reset()
+    nyls.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x, hist = b.riccati_newton(q, max_iter=15, tol=1e-12, gauss_newton_steps=2)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    nyls.profile_enable(False)
+    prof = nyls.profile_read()
+    iters = int(hist.shape[0])
+    res = {"instances": count, "n": 2000, "m": 50, "ms_per_batch_solve": sec * 1e3, "newton_steps": iters,
+           "solves_per_s": count / sec,
+           "newton_step_kernel_ms": prof["newton"][0] / max(prof["newton"][1], 1),
+           "note": "Riccati y' = q - y^2; whole Newton solves with a host stopping test per step"}
+    if check:
+        yh, off = b.predict([p["t"] for p in insts], 0)
+        yh = yh.cpu().numpy()
+        errs = check_all(_oracle_err_newton, [(i, iters, yh[off[i]:off[i + 1]]) for i in range(count)], procs)
+        res["max_rel_err"] = float(errs.max())
+    del b
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,6 +424,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--long", type=int, default=1, help="time one long single instance (n = 5e4, m = 100)")
     ap.add_argument("--uneven", type=int, default=4096, help="instances of the uneven-batch leg (0: skip)")
+    ap.add_argument("--newton", type=int, default=64, help="instances of the Newton (Riccati) leg (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -481,6 +538,9 @@ def main():
         line["uneven_batch"] = {name: uneven_batch_rate(nyls, {"fp64": nyls.FP64, "mixed": nyls.MIXED}[name],
                                                         args.uneven, args.steps, procs, args.check, args.tune)
                                 for name in args.modes.split(",")}
+    if args.newton > 0:
+        log("Newton leg")
+        line["newton_riccati"] = newton_rate(nyls, args.newton, args.steps, procs, args.check)
     if args.plain > 0:
         log("plain per-instance FP64 solve")
         line["plain_fp64_per_instance"] = {"solves_per_s": plain_fp64_rate(nyls, insts[:args.plain]),
