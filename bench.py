@@ -310,18 +310,31 @@ def plain_fp64_rate(nyls, insts):
 
 def long_single_ms(nyls, steps=3):
     """One long-time instance (first-order family, n = 5e4 over [0, 20], m = 100, sigma = 0.3,
-    FP64 mode): ms per nyls_solve.  Its parity with the oracle is a GPU test."""
+    FP64 mode, split over point chunks automatically): ms per nyls_solve and per nyls_backward
+    (100 observation times), and the same unsplit.  Its parity with the oracle is a GPU test."""
     import torch
     from paper_2510_04094_amd import workloads
     q = workloads.linear_first_order(0, n=50000, m=100, t_end=20.0, sigma=0.3, tau=1e-10)
-    b = nyls.Batch([q], mode=nyls.FP64)
-    b.solve()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    tob = [np.linspace(0.1, 19.9, 100)]
+    g = torch.full((100,), 1e-3, dtype=torch.float64, device="cuda")
+    res = {}
+    for name, split in (("split", -1), ("unsplit", 0)):
+        b = nyls.Batch([q], mode=nyls.FP64, tuning=dict(split=split))
         b.solve()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) * 1e3 / steps
+        b.backward(tob, g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.solve()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            b.backward(tob, g)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res[name] = {"solve_ms": (t1 - t0) * 1e3 / steps, "backward_ms": (t2 - t1) * 1e3 / steps}
+        del b
+    return res
 
 
 def uneven_batch_rate(nyls, mode, count, steps, procs, check, tune):
@@ -546,8 +559,9 @@ def main():
         line["plain_fp64_per_instance"] = {"solves_per_s": plain_fp64_rate(nyls, insts[:args.plain]),
                                            "instances": args.plain, "note": "forward only"}
     if args.long:
-        line["long_single_instance"] = {"ms_per_solve": long_single_ms(nyls), "n": 50000, "m": 100,
-                                        "note": "first-order family on [0, 20], FP64, forward only"}
+        line["long_single_instance"] = dict(long_single_ms(nyls), n=50000, m=100,
+                                            note="first-order family on [0, 20], FP64; solve, and adjoint "
+                                                 "for 100 observations")
     if not args.no_cpu:
         log("CPU oracle baseline")
         count = args.cpu_sample or 6 * procs

@@ -156,9 +156,10 @@ int nyls_plan_set_params(nyls_plan* plan, const double* sigma, const double* gam
  *                eigensolver; 0 = everything in order on the caller's stream
  *   split        FP64 solves of long instances: grid points per workgroup when the Gram and
  *                the refinement/output passes of one instance are split over many
- *                workgroups (a multiple of 64, at least 512; instances with n >= 2 x split
- *                are split), 0 = never split, -1 = automatic (1024 when the plan has at most
- *                64 instances, for those with n >= 4096; else never)
+ *                workgroups (a multiple of 64, at least 512; every instance runs the chunked
+ *                kernels, with one chunk when n <= split), 0 = never split, -1 = automatic
+ *                (1024 when the plan has at most 64 instances, for those with n >= 4096;
+ *                else never)
  * Defaults: {0, 64, 0, 1, 1, -1}. */
 typedef struct nyls_tuning {
   int32_t eig_ql, ql_lanes, gram_valu, tail_layout, overlap, split;

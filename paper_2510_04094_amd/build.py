@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnyls.so")
 SOURCES = ["api.hip", "eig.hip", "gram64.hip", "gram32.hip", "kkt.hip", "points.hip",
-           "features.hip", "explicit.hip", "newton.hip", "newton_gen.hip", "adjoint.hip", "leverage.hip"]
+           "features.hip", "explicit.hip", "newton.hip", "newton_gen.hip", "adjoint.hip", "adjoint_split.hip",
+           "leverage.hip"]
 ARCH = "gfx950"
 
 

@@ -70,8 +70,8 @@ __global__ __launch_bounds__(64) void k_backward(
 
   const int inst = order ? order[blockIdx.x] : (int)blockIdx.x;
   const nyls_desc& d = desc[inst];
-  if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB)
-    return;  // another launch handles this instance
+  if (d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB || (d.flags & NYLS_DF_SPLIT))
+    return;  // another launch handles this instance (split instances: adjoint_split.hip)
   const int m = d.m, n = d.n;
   const int N = m + 1 + P;
   const nyls_wsl L = nyls_layout(m, P, 0);
@@ -537,6 +537,10 @@ void launch_nb(const nyls_plan_view& pv, double* ws, int refine, const double* t
 
 struct nyls_plan;
 nyls_plan_view nyls_plan_get_view(const nyls_plan* pl);
+hipError_t nyls_launch_backward_split(const nyls_plan_view& pv, double* ws, int refine,
+                                      const double* t_obs, const int64_t* obs_off, const double* g,
+                                      double* dl_df, double* dl_dr, double* dl_dv, double* dl_ds,
+                                      double* dl_dg, hipStream_t st);
 
 extern "C" int nyls_backward(const nyls_plan* pl, const double* t_obs, const int64_t* obs_off,
                              const double* dl_dyobs, double* dl_df, double* dl_dr, double* dl_dv,
@@ -553,6 +557,9 @@ extern "C" int nyls_backward(const nyls_plan* pl, const double* t_obs, const int
     launch_nb<4>(pv, w, refine, t_obs, obs_off, dl_dyobs, dl_df, dl_dr, dl_dv, dl_dsigma, dl_dgamma, stream);
   if (pv.nb_mask & 256)
     launch_nb<8>(pv, w, refine, t_obs, obs_off, dl_dyobs, dl_df, dl_dr, dl_dv, dl_dsigma, dl_dgamma, stream);
+  if (pv.n_split)
+    (void)nyls_launch_backward_split(pv, w, refine, t_obs, obs_off, dl_dyobs, dl_df, dl_dr, dl_dv,
+                                     dl_dsigma, dl_dgamma, stream);
   nyls_prof_end(NYLS_K_BACKWARD, stream);
   return hipGetLastError() == hipSuccess ? NYLS_OK : NYLS_E_HIP;
 }

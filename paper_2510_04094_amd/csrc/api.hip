@@ -197,7 +197,7 @@ void apply_tuning(nyls_plan* pl) {
   pl->split_off = pl->ws_doubles + pl->scratch_doubles;
   pl->split_doubles = 0;
   const int ch = split_chunk(pl);
-  const int min_n = pl->tune.split > 0 ? 2 * ch : 4096;
+  const int min_n = pl->tune.split > 0 ? 0 : 4096;
   for (nyls_desc& d : pl->h_desc) {
     int f = 0;
     d.chunk = d.nchunks = 0;

@@ -45,11 +45,10 @@ def test_long_first_order_instance_splits_at_the_fp64_bar(gpu_lib, m):
 
 def test_forced_split_on_higher_orders_and_boundary_conditions(gpu_lib):
     """split = 512 on second- to fourth-order problems with initial and two-point boundary
-    conditions (condition points inside the last chunk) at the FP64 bar of the unsplit test."""
+    conditions (condition points inside the last chunk; instances shorter than a chunk run
+    as one chunk) at the FP64 bar of the unsplit test."""
     insts = [higher_order_instance(name, tau) for name, tau in FP64_HIGHER_ORDER]
     insts += [workloads.linear_second_order(3, n=4000, m=50), workloads.linear_first_order(4, n=3000, m=33)]
-    split = [q for q in insts if q["n"] >= 1024]
-    assert len(split) >= 4, [q["n"] for q in insts]
     _, out, ys = _solve(gpu_lib, insts, tuning=dict(split=512))
     for i, q in enumerate(insts):
         ref = oracle.linear.solve(q)["yhat"]
@@ -109,3 +108,37 @@ def test_split_without_refinement(gpu_lib):
     assert np.all(np.isfinite(ys[0]))
     assert _rel(ys[0], yu[0]) <= 1e-4
     assert int(out_s["status"].cpu().numpy()[0]) & gpu_lib.S_REFINE_NOCONV == 0
+
+
+@pytest.mark.parametrize("split", [512, 2048])
+def test_split_adjoint_matches_oracle(gpu_lib, split):
+    """The adjoint of split instances (passes over chunks, chunk sums in chunk order) against
+    the oracle's gradients with the bars of the unsplit adjoint test: orders 1 and 2, bases of
+    20 to 62 landmarks (the m = 33 one with a last block of a single landmark)."""
+    from test_gpu_adjoint import loss_grad_obs, rel
+    insts = [workloads.linear_second_order(i, n=5000, m=m, obs=100, config=5) for i, m in enumerate((50, 62, 20))]
+    insts.append(workloads.linear_first_order(3, n=4000, m=33))
+    insts[-1]["t_obs"] = np.sort(np.random.default_rng(5).uniform(0.0, 1.0, 60))
+    insts[-1]["y_obs"] = np.interp(insts[-1]["t_obs"], insts[-1]["t"], insts[-1]["ystar"])
+    b = gpu_lib.Batch(insts, mode=gpu_lib.FP64, tuning=dict(split=split))
+    b.solve()
+    yo, off = b.predict([q["t_obs"] for q in insts], 0)
+    yo = yo.cpu().numpy()
+    g = [loss_grad_obs(yo[off[i]:off[i + 1]], q["y_obs"]) for i, q in enumerate(insts)]
+    out = b.backward([q["t_obs"] for q in insts], g)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    info = b.info().cpu().numpy()
+    for i, q in enumerate(insts):
+        ref = oracle.adjoint.grad(q, q["t_obs"], g[i])
+        o = slice(b.goff[i], b.goff[i + 1])
+        for k in range(q["p"]):
+            gf, rf = out["dl_df"][k, o], ref["dl_df"][k]
+            assert np.max(np.abs(gf - rf)) <= 1e-5 * np.max(np.abs(rf)), ("df", i, k)
+        assert np.max(np.abs(out["dl_dr"][o] - ref["dl_dr"])) <= 1e-5 * np.max(np.abs(ref["dl_dr"]))
+        for j in range(q["p"]):
+            assert rel(out["dl_dv"][i, j], ref["dl_dv"][j]) <= 1e-5, ("dv", i, j)
+        scale = 1e-5 * abs(ref["dl_dsigma"]) + 1e-8 * np.max(np.abs(ref["sigma_terms"]))
+        assert abs(out["dl_dsigma"][i] - ref["dl_dsigma"]) <= scale, ("dsigma", i)
+        assert rel(out["dl_dgamma"][i], ref["dl_dgamma"]) <= 1e-5, ("dgamma", i)
+        assert 1 <= info[i, 6] <= 3  # mu refinement passes
