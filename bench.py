@@ -34,8 +34,8 @@ TRAFFIC = {
     "backward": {
         "sources": ["paper_2510_04094_amd/csrc/adjoint.hip", "paper_2510_04094_amd/csrc/nyls_walk.h",
                     "paper_2510_04094_amd/csrc/nyls_dense.h", "paper_2510_04094_amd/csrc/nyls_internal.h"],
-        "sha1": "fbb06b0af5a55ee561369574fc3f691923534ebf",
-        "kib": {"mixed": (2191364.8, 1128808.3), "fp64": (2351165.4, 1129577.0)},
+        "sha1": "8a984ba4ab2bbbf484e313a075a1257e68c578cf",
+        "kib": {"mixed": (2166567.4, 1128657.0), "fp64": (2225698.7, 1129576.5)},
         "scale": (2.0, 1.0),
     },
 }
