@@ -337,6 +337,44 @@ def long_single_ms(nyls, steps=3):
     return res
 
 
+def long_time_wide_ms(nyls, steps=3):
+    """The long-time shape of the paper's large-scale table: one second-order instance with
+    n = 5e4 on [0, 100], m = 200 landmarks, sigma^2 = 1, gamma = 1e7 (FP64; a basis this wide
+    is always split, two wavefronts per chunk).  ms per nyls_solve and per nyls_backward (100
+    observations), and the solve's stages from the library's HIP-event timing.  Its parity
+    with the oracle is a GPU test."""
+    import torch
+    from paper_2510_04094_amd import workloads
+    q = workloads.linear_second_order(0, n=50000, m=200, t_end=100.0, sigma=1.0, tau=1e-8, obs=100)
+    b = nyls.Batch([q], mode=nyls.FP64)
+    tob = [q["t_obs"]]
+    g = torch.full((100,), 1e-3, dtype=torch.float64, device="cuda")
+    b.solve()
+    b.backward(tob, g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.solve()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        b.backward(tob, g)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    nyls.profile_reset()
+    nyls.profile_enable(True)
+    b.solve()
+    torch.cuda.synchronize()
+    nyls.profile_enable(False)
+    prof = nyls.profile_read()
+    info = b.info().cpu().numpy()
+    return {"solve_ms": (t1 - t0) * 1e3 / steps, "backward_ms": (t2 - t1) * 1e3 / steps,
+            "stage_ms": {k: v[0] for k, v in prof.items() if v[1]}, "rank": int(info[0, 0]),
+            "refinement_passes": float(info[0, 5]), "n": 50000, "m": 200,
+            "note": "second-order family on [0, 100], sigma = 1, FP64; solve, and adjoint for 100 "
+                    "observations; stages overlap (the Gram runs beside the eigensolver)"}
+
+
 def uneven_batch_rate(nyls, mode, count, steps, procs, check, tune):
     """Solves/s of the uneven batch (orders 1 and 2, n ~ U{500..1e4}, m in {20, 50, 100}),
     forward only, one nyls_solve captured in a HIP graph and replayed; every instance checked
@@ -435,7 +473,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle instances per timed run (0: 6 per process)")
     ap.add_argument("--cpu-runs", type=int, default=5, help="timed CPU runs (median reported)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--long", type=int, default=1, help="time one long single instance (n = 5e4, m = 100)")
+    ap.add_argument("--long", type=int, default=1,
+                    help="time long single instances (n = 5e4, m = 100; and m = 200 on [0, 100])")
     ap.add_argument("--uneven", type=int, default=4096, help="instances of the uneven-batch leg (0: skip)")
     ap.add_argument("--newton", type=int, default=64, help="instances of the Newton (Riccati) leg (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -559,9 +598,11 @@ def main():
         line["plain_fp64_per_instance"] = {"solves_per_s": plain_fp64_rate(nyls, insts[:args.plain]),
                                            "instances": args.plain, "note": "forward only"}
     if args.long:
+        log("long single instances")
         line["long_single_instance"] = dict(long_single_ms(nyls), n=50000, m=100,
                                             note="first-order family on [0, 20], FP64; solve, and adjoint "
                                                  "for 100 observations")
+        line["long_time_m200"] = long_time_wide_ms(nyls)
     if not args.no_cpu:
         log("CPU oracle baseline")
         count = args.cpu_sample or 6 * procs

@@ -39,7 +39,8 @@ extern "C" {
 #endif
 
 #define NYLS_MAX_P 4   /* highest ODE order */
-#define NYLS_MAX_M 128 /* most landmarks per instance */
+#define NYLS_MAX_M 256 /* most landmarks per instance (above 128: NYLS_FP64 solves, predictions
+                          and adjoints only, see nyls_problem) */
 #define NYLS_MAX_N (1 << 25) /* most grid points per instance */
 
 /* Arithmetic of the solve (nyls_plan_create `mode`). */
@@ -60,7 +61,8 @@ enum {
   NYLS_E_BATCH = -2,      /* batch < 1 */
   NYLS_E_MODE = -3,       /* unknown mode, or the call does not support the plan's mode */
   NYLS_E_ORDER = -4,      /* p outside 1..NYLS_MAX_P */
-  NYLS_E_SIZE = -5,       /* n < 2, n > NYLS_MAX_N, m < 2, m > n or m > NYLS_MAX_M (126 in mixed mode) */
+  NYLS_E_SIZE = -5,       /* n < 2, n > NYLS_MAX_N, m < 2, m > n or m > NYLS_MAX_M (126 in mixed
+                             mode, 128 in explicit mode and for the Newton and leverage calls) */
   NYLS_E_PARAM = -6,      /* sigma <= 0, gamma <= 0, tau outside [0, 1), or non-finite */
   NYLS_E_GRID = -7,       /* uniform grid with dt <= 0, or explicit grid missing */
   NYLS_E_LANDMARK = -8,   /* landmark indices not strictly ascending inside [0, n) */
@@ -91,7 +93,13 @@ enum {
  *   p          order, 1..4
  *   n          grid size; grid t_i = t0 + i*dt when uniform != 0, else t[i] (device,
  *              strictly ascending)
- *   m          number of landmarks (sub-sample size), 2 <= m <= min(n, 128)
+ *   m          number of landmarks (sub-sample size), 2 <= m <= min(n, NYLS_MAX_M).  Bases
+ *              of more than 128 landmarks (the long-time runs of Sec. 4 use up to 200) are
+ *              taken by NYLS_FP64 plans only, and by nyls_solve, nyls_predict,
+ *              nyls_features and nyls_backward: such an instance is always split over chunks
+ *              of grid points (nyls_tuning.split; 1024 points unless a size is set), its
+ *              eigensolver and KKT factors work in the workspace instead of on-chip memory,
+ *              and its passes run two wavefronts per chunk, one per half of the landmarks.
  *   lidx       HOST array of m strictly ascending grid indices, or NULL for the
  *              equidistant rule i_s = floor(s (n-1)/(m-1) + 1/2), s = 0..m-1 (Sec. 4.1)
  *   f          device [p][n]: f[(k-1)*n + i] = f_k(t_i); unused by the nonlinear path
@@ -159,7 +167,8 @@ int nyls_plan_set_params(nyls_plan* plan, const double* sigma, const double* gam
  *                workgroups (a multiple of 64, at least 512; every instance runs the chunked
  *                kernels, with one chunk when n <= split), 0 = never split, -1 = automatic
  *                (1024 when the plan has at most 64 instances, for those with n >= 4096;
- *                else never)
+ *                else never).  Instances with m > 128 are split whatever the setting (in
+ *                chunks of 1024 points unless a size is set)
  * Defaults: {0, 64, 0, 1, 1, -1}. */
 typedef struct nyls_tuning {
   int32_t eig_ql, ql_lanes, gram_valu, tail_layout, overlap, split;

@@ -7,7 +7,7 @@ defaults, keeps the fastest, and records it under the batch's key
 
     (GPU architecture, m bucket, ODE orders, mode)
 
-where the m bucket is the one-wave slot class of the largest basis (m <= 32, <= 64, <= 128).
+where the m bucket is the slot class of the largest basis (m <= 32, <= 64, <= 128, <= 256).
 A later plan with the same key can start from the cached choice (`Batch(..., tuning="cached")`).
 
 Cache file: $NYLS_TUNING_CACHE, else ~/.cache/nyls/tuning.json.  Timing uses HIP events on
@@ -39,7 +39,9 @@ def m_bucket(m):
         return "m<=32"
     if m <= 64:
         return "m<=64"
-    return "m<=128"
+    if m <= 128:
+        return "m<=128"
+    return "m<=256"
 
 
 def arch_name(device=None):

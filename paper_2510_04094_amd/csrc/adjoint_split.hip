@@ -26,13 +26,13 @@ __device__ inline bool takes(const nyls_desc& d) {
   return (d.flags & NYLS_DF_SPLIT) && d.p == P;
 }
 
-// beta = W mu for this lane's landmark slots
+// beta = W mu for this lane's landmark slots (s0 + 16 b + sl)
 template <int NB>
-__device__ inline void beta_slots(const double* W, const double* mu, int m, int r, int sl,
+__device__ inline void beta_slots(const double* W, const double* mu, int m, int r, int s0, int sl,
                                   const bool (&lv)[NB], double (&bev)[NB]) {
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int s = 16 * b + sl;
+    const int s = s0 + 16 * b + sl;
     double acc = 0.0;
     if (lv[b])
       for (int k = 0; k < r; ++k) acc += W[s * m + k] * mu[k];
@@ -115,23 +115,31 @@ __global__ __launch_bounds__(64) void k_bws_setup(const nyls_desc* __restrict__ 
   }
 }
 
-template <int NB, int P, bool EX>
-__global__ __launch_bounds__(64) void k_bws_mu_pass(const nyls_desc* __restrict__ desc,
-                                                    double* __restrict__ wsbase) {
-  __shared__ __align__(16) double tile[16 * NYLS_WALK_PAD];
-  __shared__ double bc[16];
+// G = 2: wide bases, two wavefronts per chunk (one per half of the landmark slots), the
+// per-point sums joined through LDS as in the forward passes.
+template <int NB, int P, bool EX, int G = 1>
+__global__ __launch_bounds__(64 * G) void k_bws_mu_pass(const nyls_desc* __restrict__ desc,
+                                                        double* __restrict__ wsbase) {
+  __shared__ __align__(16) double tiles[G][16 * NYLS_WALK_PAD];
+  __shared__ double bcs[G][16];
+  __shared__ double xw[G > 1 ? 2 * G * 16 : 1];
   const nyls_desc& d = desc[blockIdx.x];
-  if (!takes<P>(d) || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB) return;
+  if (!takes<P>(d) || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB * G) return;
   const int c = (int)blockIdx.y;
   if (c >= d.nchunks) return;
-  const int m = d.m, n = d.n, N = m + 1 + P, lane = threadIdx.x;
+  const int m = d.m, n = d.n, N = m + 1 + P;
+  const int lane = threadIdx.x & 63, grp = G > 1 ? (int)(threadIdx.x >> 6) : 0;
+  const int s0 = 16 * NB * grp;
+  double* const tile = tiles[grp];
+  double* const bc = bcs[grp];
+  int parity = 0;
   const nyls_wsl L = nyls_layout(m, P, 0);
   double* ws = wsbase + d.ws;
   if (ws[L.tmp + N + BS_DONE] != 0.0) return;
   const int r = (int)ws[L.info + 0];
   const int ibeg = c * d.chunk, iend = min(n, ibeg + d.chunk);
   nyls_walk<NB, EX> wk;
-  wk.init(d, lane);
+  wk.init(d, lane, s0);
   nyls_cpts cpt;
   cpt.init(d);
   const int ph = wk.ph;
@@ -141,7 +149,7 @@ __global__ __launch_bounds__(64) void k_bws_mu_pass(const nyls_desc* __restrict_
   const __amdgpu_buffer_rsrc_t fr = nyls_rsrc(d.f, P * n * 8);
   const double* mu = ws + L.mu;
   double bev[NB];
-  beta_slots<NB>(ws + L.W, mu, m, r, wk.sl, wk.lv, bev);
+  beta_slots<NB>(ws + L.W, mu, m, r, s0, wk.sl, wk.lv, bev);
   const double mub = mu[m];
   double zacc[NB], sacc = 0.0;
 #pragma unroll
@@ -181,6 +189,10 @@ __global__ __launch_bounds__(64) void k_bws_mu_pass(const nyls_desc* __restrict_
         });
     double tot[1];
     nyls_walk_sum<1>(tile, lane, tot);
+    if constexpr (G > 1) {
+      nyls_walk_join<G, 1>(tot, xw, lane, grp, parity);
+      parity ^= 1;
+    }
     const int ip = i0 + (lane & 15);
     const bool okp = ip < n && !cpt.has(ip);
     const double nu = okp ? tot[0] + st.c * mub : 0.0;
@@ -206,10 +218,10 @@ __global__ __launch_bounds__(64) void k_bws_mu_pass(const nyls_desc* __restrict_
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const double v = nyls_walk_fold(zacc[b]);
-    if (ph == 0 && wk.lv[b]) part[16 * b + wk.sl] = v;
+    if (ph == 0 && wk.lv[b]) part[s0 + 16 * b + wk.sl] = v;
   }
   const double csum = nyls_wave_sum(sacc);
-  if (lane == 0) part[m] = csum;
+  if (lane == 0 && grp == 0) part[m] = csum;
 }
 
 // One refinement step of mu (step `step` of at most `refine`), as in k_backward: the residual
@@ -290,26 +302,33 @@ __global__ __launch_bounds__(64) void k_bws_mu_combine(const nyls_desc* __restri
   }
 }
 
-template <int NB, int P, bool EX>
-__global__ __launch_bounds__(64) void k_bws_grad_pass(const nyls_desc* __restrict__ desc,
-                                                      double* __restrict__ wsbase,
-                                                      double* __restrict__ dl_df,
-                                                      double* __restrict__ dl_dr, int64_t total) {
+template <int NB, int P, bool EX, int G = 1>
+__global__ __launch_bounds__(64 * G) void k_bws_grad_pass(const nyls_desc* __restrict__ desc,
+                                                          double* __restrict__ wsbase,
+                                                          double* __restrict__ dl_df,
+                                                          double* __restrict__ dl_dr, int64_t total) {
   constexpr int Q = 4 + 2 * P;
-  __shared__ __align__(16) double tile[Q * 16 * NYLS_WALK_PAD];
-  __shared__ double bc[2 * 16];
+  __shared__ __align__(16) double tiles[G][Q * 16 * NYLS_WALK_PAD];
+  __shared__ double bcs[G][2 * 16];
+  __shared__ double xw[G > 1 ? 2 * G * Q * 16 : 1];
   const nyls_desc& d = desc[blockIdx.x];
-  if (!takes<P>(d) || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB) return;
+  if (!takes<P>(d) || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB * G) return;
   const int c = (int)blockIdx.y;
   if (c >= d.nchunks) return;
-  const int m = d.m, n = d.n, lane = threadIdx.x;
+  const int m = d.m, n = d.n;
+  const int lane = threadIdx.x & 63, grp = G > 1 ? (int)(threadIdx.x >> 6) : 0;
+  const int s0 = 16 * NB * grp;
+  const bool lead = grp == 0;  // writes dl/df, dl/dr and the scalar sum
+  double* const tile = tiles[grp];
+  double* const bc = bcs[grp];
+  int parity = 0;
   const nyls_wsl L = nyls_layout(m, P, 0);
   double* ws = wsbase + d.ws;
   const int r = (int)ws[L.info + 0];
   const int ibeg = c * d.chunk, iend = min(n, ibeg + d.chunk);
   const double gam = d.gamma;
   nyls_walk<NB, EX> wk;
-  wk.init(d, lane);
+  wk.init(d, lane, s0);
   nyls_cpts cpt;
   cpt.init(d);
   const int ph = wk.ph;
@@ -320,8 +339,8 @@ __global__ __launch_bounds__(64) void k_bws_grad_pass(const nyls_desc* __restric
   const double* mu = ws + L.mu;
   double alv[NB], bev[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) alv[b] = wk.lv[b] ? ws[L.alpha + 16 * b + wk.sl] : 0.0;
-  beta_slots<NB>(ws + L.W, mu, m, r, wk.sl, wk.lv, bev);
+  for (int b = 0; b < NB; ++b) alv[b] = wk.lv[b] ? ws[L.alpha + s0 + 16 * b + wk.sl] : 0.0;
+  beta_slots<NB>(ws + L.W, mu, m, r, s0, wk.sl, wk.lv, bev);
   const double bias = ws[L.x + m], mub = mu[m];
   double aeacc[NB], anacc[NB], t2 = 0.0;
 #pragma unroll
@@ -382,11 +401,15 @@ __global__ __launch_bounds__(64) void k_bws_grad_pass(const nyls_desc* __restric
         });
     double tot[Q];
     nyls_walk_sum<Q>(tile, lane, tot);
+    if constexpr (G > 1) {
+      nyls_walk_join<G, Q>(tot, xw, lane, grp, parity);
+      parity ^= 1;
+    }
     const int ip = i0 + (lane & 15);
     const bool okp = ip < n && !cpt.has(ip);
     const double ei = okp ? tot[0] + st.c * bias - st.r : 0.0;
     const double nui = okp ? tot[1] + st.c * mub : 0.0;
-    if (lane < 16 && ip < n) {
+    if (lane < 16 && ip < n && lead) {
       t2 += half_sigma * (ei * tot[3] + nui * tot[2]);
       if (dl_dr) dl_dr[d.goff + ip] = gam * nui;
       if (dl_df) {
@@ -424,12 +447,12 @@ __global__ __launch_bounds__(64) void k_bws_grad_pass(const nyls_desc* __restric
   for (int b = 0; b < NB; ++b) {
     const double va = nyls_walk_fold(aeacc[b]), vn = nyls_walk_fold(anacc[b]);
     if (ph == 0 && wk.lv[b]) {
-      part[16 * b + wk.sl] = va;
-      part[m + 16 * b + wk.sl] = vn;
+      part[s0 + 16 * b + wk.sl] = va;
+      part[m + s0 + 16 * b + wk.sl] = vn;
     }
   }
   t2 = nyls_wave_sum(t2);
-  if (lane == 0) part[2 * m] = t2;
+  if (lane == 0 && lead) part[2 * m] = t2;
 }
 
 // The sigma terms through the conditions and K_mm, dl/dgamma and dl/dv, as in k_backward;
@@ -558,14 +581,16 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_bws_final(const nyls_desc* __res
   if (dl_dv && tid < NYLS_MAX_P) dl_dv[inst * NYLS_MAX_P + tid] = tid < P ? mu[m + 1 + tid] : 0.0;
 }
 
+// NB: slot blocks of the instance class (16: wide bases, two wavefronts of eight blocks)
 template <int NB, int P, bool EX>
 void launch_passes_x(const nyls_plan_view& pv, double* ws, bool mu_pass, double* dl_df,
                      double* dl_dr, hipStream_t st) {
-  const dim3 grid(pv.batch, pv.max_chunks);
+  constexpr int G = NB > 8 ? NB / 8 : 1, NW = NB / G;
+  const dim3 grid(pv.batch, pv.max_chunks), block(64 * G);
   if (mu_pass)
-    hipLaunchKernelGGL((k_bws_mu_pass<NB, P, EX>), grid, dim3(64), 0, st, pv.d_desc, ws);
+    hipLaunchKernelGGL((k_bws_mu_pass<NW, P, EX, G>), grid, block, 0, st, pv.d_desc, ws);
   else
-    hipLaunchKernelGGL((k_bws_grad_pass<NB, P, EX>), grid, dim3(64), 0, st, pv.d_desc, ws, dl_df,
+    hipLaunchKernelGGL((k_bws_grad_pass<NW, P, EX, G>), grid, block, 0, st, pv.d_desc, ws, dl_df,
                        dl_dr, pv.total);
 }
 
@@ -622,11 +647,13 @@ hipError_t nyls_launch_backward_split(const nyls_plan_view& pv, double* ws, int 
     launch_passes_nb<2>(pv, ws, true, dl_df, dl_dr, st);
     launch_passes_nb<4>(pv, ws, true, dl_df, dl_dr, st);
     launch_passes_nb<8>(pv, ws, true, dl_df, dl_dr, st);
+    launch_passes_nb<16>(pv, ws, true, dl_df, dl_dr, st);
     launch_small_all(pv, ws, 1, step, refine, t_obs, obs_off, g, dl_dv, dl_ds, dl_dg, st);
   }
   launch_passes_nb<2>(pv, ws, false, dl_df, dl_dr, st);
   launch_passes_nb<4>(pv, ws, false, dl_df, dl_dr, st);
   launch_passes_nb<8>(pv, ws, false, dl_df, dl_dr, st);
+  launch_passes_nb<16>(pv, ws, false, dl_df, dl_dr, st);
   launch_small_all(pv, ws, 2, 0, refine, t_obs, obs_off, g, dl_dv, dl_ds, dl_dg, st);
   return hipGetLastError();
 }

@@ -12,6 +12,7 @@
 
 struct nyls_plan {
   int32_t batch = 0, mode = 0, maxm = 0, maxp = 0, maxn = 0;
+  int32_t maxm_narrow = 0;  // largest m <= NYLS_NARROW_MAX_M
   int64_t total = 0;        // sum of n
   int64_t ws_doubles = 0;   // per-instance blocks
   int64_t scratch_off = 0;  // explicit-mode scratch (doubles)
@@ -85,6 +86,7 @@ nyls_plan_view view(const nyls_plan* pl) {
   v.maxm = pl->maxm;
   v.maxp = pl->maxp;
   v.maxn = pl->maxn;
+  v.maxm_narrow = pl->maxm_narrow;
   v.d_desc = pl->d_desc;
   v.d_order = pl->d_order;
   v.total = pl->total;
@@ -183,7 +185,8 @@ __global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
 namespace {
 // Per-instance kernel choices (nyls_desc::flags) and the launch masks that follow from the
 // plan's tuning.
-// Grid points per workgroup of split instances for the plan's `split` setting (0: none).
+// Grid points per workgroup of split instances for the plan's `split` setting (0: none;
+// bases wider than NYLS_NARROW_MAX_M are split whatever it says).
 int split_chunk(const nyls_plan* pl) {
   if (pl->mode != NYLS_FP64) return 0;
   if (pl->tune.split > 0) return pl->tune.split;
@@ -198,13 +201,15 @@ void apply_tuning(nyls_plan* pl) {
   pl->split_doubles = 0;
   const int ch = split_chunk(pl);
   const int min_n = pl->tune.split > 0 ? 0 : 4096;
+  const int wide_ch = pl->tune.split > 0 ? pl->tune.split : 1024;
   for (nyls_desc& d : pl->h_desc) {
     int f = 0;
     d.chunk = d.nchunks = 0;
     d.part = 0;
-    if (ch > 0 && d.n >= min_n) {
+    const bool wide = d.m > NYLS_NARROW_MAX_M;
+    if (wide || (ch > 0 && d.n >= min_n)) {
       f |= NYLS_DF_SPLIT;
-      d.chunk = ch;
+      d.chunk = wide ? wide_ch : ch;
       d.nchunks = (d.n + ch - 1) / ch;
       d.part = pl->split_off + pl->split_doubles;
       pl->split_doubles += nyls_split_doubles(d.m, d.nchunks);
@@ -256,6 +261,7 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
     const nyls_problem& q = probs[i];
     int rc = validate(q, lid);
     if (rc == NYLS_OK && mode == NYLS_MIXED && q.m > 126) rc = NYLS_E_SIZE;
+    if (rc == NYLS_OK && mode != NYLS_FP64 && q.m > NYLS_NARROW_MAX_M) rc = NYLS_E_SIZE;
     if (rc != NYLS_OK) { delete pl; return rc; }
     if (!q.f || !q.r) pl->linear_ok = false;
     if (q.p != 1) pl->all_first_order = false;
@@ -285,6 +291,7 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
     pl->gnb_mask |= 1u << nyls_slot_blocks(q.m + 2);
     if (q.m > 64) ++pl->n_big;
     pl->maxm = std::max(pl->maxm, q.m);
+    if (q.m <= NYLS_NARROW_MAX_M) pl->maxm_narrow = std::max(pl->maxm_narrow, q.m);
     pl->maxp = std::max(pl->maxp, q.p);
     pl->maxn = std::max(pl->maxn, q.n);
   }
@@ -633,7 +640,9 @@ const char* nyls_error_string(int32_t code) {
     case NYLS_E_BATCH: return "batch must be >= 1";
     case NYLS_E_MODE: return "unknown or unsupported mode";
     case NYLS_E_ORDER: return "ODE order p outside 1..4";
-    case NYLS_E_SIZE: return "need 2 <= m <= n and m <= 128 (m <= 126 in NYLS_MIXED)";
+    case NYLS_E_SIZE:
+      return "need 2 <= m <= n and m <= 256 (m <= 126 in NYLS_MIXED; m <= 128 in NYLS_FP64_EXPLICIT and "
+             "for the Newton and leverage calls)";
     case NYLS_E_PARAM: return "need sigma > 0, gamma > 0, 0 <= tau < 1 (finite)";
     case NYLS_E_GRID: return "grid: dt <= 0 or explicit times missing / not ascending";
     case NYLS_E_LANDMARK: return "landmark indices not strictly ascending inside [0, n)";

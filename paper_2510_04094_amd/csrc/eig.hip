@@ -1,10 +1,10 @@
 // Nystrom basis: landmark kernel matrix K_mm, its eigendecomposition and the feature
 // transform W = U_r Lambda_r^{-1/2} (App. A.2, eq32), one wavefront per instance.
 //
-// K_mm (at most 128 x 128) is kept in LDS, reduced to tridiagonal form by Householder
+// K_mm (up to 128 x 128) is kept in LDS, reduced to tridiagonal form by Householder
 // reflections and diagonalised by implicit QL (k_eig_ql for m <= 64 with one row per lane,
 // staged with the lane-parallel QL of k_ql_lanes for batches; k_eig_ql2 for 64 < m <= 128
-// with two rows per lane).  Afterwards eigenvalues are sorted descending, each eigenvector is
+// with two rows per lane; k_eig_wide for wider bases, with the matrix in the workspace).  Afterwards eigenvalues are sorted descending, each eigenvector is
 // signed so its largest-magnitude entry (first on ties) is positive, and eigenpairs with
 // lambda_k <= tau * lambda_1 are dropped (the retained rank r goes to info[0]).
 #include "nyls_dense.h"
@@ -358,15 +358,16 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
 // those of step 3 of k_eig_ql; the plane rotations are logged to the instance's workspace
 // (its rotation-log region) for the replay on Q.  An instance whose log
 // would overflow is marked (info[7] = 2) and redone by k_eig_ql(QL_REDO).
-// MAXM = 64 takes the instances with m <= 64, MAXM = 128 those with 64 < m <= 128.
-template <int MAXM>
+// Takes the instances with LO < m <= MAXM, at most LN per wavefront (LN = 64 for m <= 128;
+// the wide bases, with their larger d and e, use LN = 16 to stay within the LDS).
+template <int MAXM, int LO = MAXM - kQlMaxM, int LN = 64>
 __global__ __launch_bounds__(64) void k_ql_lanes(const nyls_desc* __restrict__ desc,
                                                  double* __restrict__ wsbase, int batch, int ipw) {
-  __shared__ double dv[MAXM][64], ev[MAXM][64];  // [index][lane]: conflict-free
+  __shared__ double dv[MAXM][LN], ev[MAXM][LN];  // [index][lane]: conflict-free
   const int lane = threadIdx.x;
-  const int inst = blockIdx.x * ipw + lane;  // ipw <= 64 instances per wavefront
+  const int inst = blockIdx.x * ipw + lane;  // ipw <= LN instances per wavefront
   const int mi = desc[inst < batch ? inst : 0].m;
-  const bool act = lane < ipw && inst < batch && mi <= MAXM && mi > MAXM - kQlMaxM;
+  const bool act = lane < ipw && lane < LN && inst < batch && mi <= MAXM && mi > LO;
   const nyls_desc& d = desc[act ? inst : 0];
   const int m = act ? d.m : 0;
   const nyls_wsl L = nyls_layout(d.m, d.p, 0);
@@ -815,6 +816,193 @@ __global__ __launch_bounds__(64) void k_eig_ql2(const nyls_desc* __restrict__ de
   }
 }
 
+// ---- wide bases (NYLS_NARROW_MAX_M < m <= NYLS_MAX_M): 256 threads, K_mm in the workspace ----
+//
+// The matrix no longer fits in LDS, so the steps of k_eig_ql run on the instance's U block
+// (L2-resident), thread j owning column j: K_mm and every trailing block stay exactly
+// symmetric (the rank-2 update adds its two products in an order-independent way), so
+// column j is also row j, and every step reads and writes with coalesced accesses.
+//  1. Householder reduction as in step 1 of k_eig_ql, reflector k kept in row k;
+//  2. Q = H_0 ... H_{m-3} formed in place, then stored transposed in the T scratch
+//     (ZT[c m + i] = Z[i][c]), where each row of Z is a coalesced stripe;
+//  3. (k_ql_lanes) implicit QL on (d, e), one lane per instance, logging the rotations;
+//  4. replay: thread i applies the logged rotations to row i of Z (rows are independent,
+//     no synchronisation), then the ordering, signs, cut-off and W of step 4 of k_eig_ql.
+// A rotation log that overflowed (more than 2 m^2 rotations) leaves NYLS_S_EIG_NOCONV set.
+enum { WIDE_REDUCE = 0, WIDE_REPLAY = 1 };
+
+__global__ __launch_bounds__(NYLS_BLOCK) void k_eig_wide(const nyls_desc* __restrict__ desc,
+                                                         double* __restrict__ wsbase, int stage) {
+  __shared__ double vv[NYLS_MAX_M], ww[NYLS_MAX_M], tl[NYLS_MAX_M], bt[NYLS_MAX_M];
+  __shared__ double dd[NYLS_MAX_M], ee[NYLS_MAX_M], red[NYLS_BLOCK / 64];
+  __shared__ int pos[NYLS_MAX_M];
+  const nyls_desc& d = desc[blockIdx.x];
+  const int m = d.m;
+  if (m <= NYLS_NARROW_MAX_M) return;
+  const nyls_wsl L = nyls_layout(m, d.p, 0);
+  double* ws = wsbase + d.ws;
+  const int j = threadIdx.x;
+  const bool own = j < m;
+  double* A = ws + L.U;     // [m][m] K_mm, then Q
+  double* ZT = ws + L.tmp;  // [m][m] Z transposed
+  if (stage == WIDE_REDUCE) {
+    const double inv_sigma = 1.0 / d.sigma;
+    if (own) tl[j] = nyls_grid_t(d, d.lidx[j]);
+    __syncthreads();
+    if (own)
+      for (int c = 0; c < m; ++c) {
+        const double z = (tl[c] - tl[j]) * inv_sigma;
+        A[c * m + j] = exp(-z * z);
+      }
+    __syncthreads();
+    // 1. tridiagonalisation
+    for (int k = 0; k + 2 < m; ++k) {
+      const bool act = own && j > k;
+      const double x = act ? A[k * m + j] : 0.0;  // row k = column k below the diagonal
+      const double sig2 = nyls_block_sum(x * x, red);
+      const double xk1 = A[k * m + k + 1];
+      if (j == 0) dd[k] = A[k * m + k];
+      if (!(sig2 - xk1 * xk1 > 0.0)) {
+        if (j == 0) {
+          ee[k] = xk1;
+          bt[k] = 0.0;
+        }
+        continue;  // nothing below the subdiagonal: no reflector (the next block sum syncs)
+      }
+      const double alpha = xk1 >= 0.0 ? -sqrt(sig2) : sqrt(sig2);
+      const double beta = 1.0 / (sig2 - alpha * xk1);
+      const double v = act ? (j == k + 1 ? x - alpha : x) : 0.0;
+      if (j == 0) {
+        ee[k] = alpha;
+        bt[k] = beta;
+      }
+      if (own) vv[j] = v;
+      __syncthreads();
+      double pj = 0.0;  // p = beta B v (column j of B is row j)
+      if (act) {
+        for (int c = k + 1; c < m; ++c) pj += A[c * m + j] * vv[c];
+        pj *= beta;
+      }
+      const double K = 0.5 * beta * nyls_block_sum(v * pj, red);
+      const double w = pj - K * v;
+      if (own) ww[j] = w;
+      __syncthreads();
+      if (act) {
+        for (int c = k + 1; c < m; ++c)
+          A[c * m + j] -= __dadd_rn(__dmul_rn(vv[c], w), __dmul_rn(ww[c], v));
+        A[k * m + j] = v;  // reflector k
+      }
+      __syncthreads();
+    }
+    if (j == 0) {
+      dd[m - 2] = A[(m - 2) * m + m - 2];
+      ee[m - 2] = A[(m - 1) * m + m - 2];
+      dd[m - 1] = A[(m - 1) * m + m - 1];
+      ee[m - 1] = 0.0;
+    }
+    // 2. Q in place (the trailing 2 x 2 block starts as the identity)
+    if (own && j >= m - 2) {
+      A[(m - 2) * m + j] = j == m - 2 ? 1.0 : 0.0;
+      A[(m - 1) * m + j] = j == m - 1 ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int k = m - 3; k >= 0; --k) {
+      const bool act = own && j > k;
+      if (act) vv[j] = A[k * m + j];
+      __syncthreads();
+      const double beta = bt[k];
+      if (act && beta != 0.0) {
+        double t = 0.0;  // (v^T Q)_j over the trailing rows
+        for (int i = k + 1; i < m; ++i) t += vv[i] * A[i * m + j];
+        t *= beta;
+        for (int i = k + 1; i < m; ++i) A[i * m + j] -= vv[i] * t;
+      }
+      if (own && j >= k) A[k * m + j] = j == k ? 1.0 : 0.0;  // row k = e_k
+      if (j == k)
+        for (int i = k + 1; i < m; ++i) A[i * m + k] = 0.0;  // column k = e_k
+      __syncthreads();
+    }
+    if (own) {
+      ws[L.lam + j] = dd[j];
+      ws[L.W + j] = ee[j];
+      for (int i = 0; i < m; ++i) ZT[j * m + i] = A[i * m + j];
+    }
+    return;
+  }
+
+  // 4. replay of the logged sweeps (each: header (mm, k) and k rotations (c, s) for
+  //    columns mm - 1, mm - 2, ...), thread j carrying row j of Z
+  const int flag = (int)ws[L.info + 7];
+  if (flag != 2 && own) {
+    const double* lg = ws + L.log;
+    const int nsw = (int)ws[L.info + 6];
+    int hdr = 0;
+    for (int sw = 0; sw < nsw; ++sw) {
+      const int mm = (int)lg[2 * hdr], nrot = (int)lg[2 * hdr + 1];
+      double c0 = ZT[mm * m + j];
+      double z0 = nrot > 0 ? ZT[(mm - 1) * m + j] : 0.0;
+      for (int k = 0; k < nrot; ++k) {
+        const int i = mm - 1 - k;
+        const double cs = lg[2 * (hdr + 1 + k)], sn = lg[2 * (hdr + 1 + k) + 1];
+        const double zn = (k + 1 < nrot) ? ZT[(i - 1) * m + j] : 0.0;  // unchanged by this rotation
+        ZT[(i + 1) * m + j] = sn * z0 + cs * c0;
+        c0 = cs * z0 - sn * c0;
+        z0 = zn;
+      }
+      ZT[(mm - nrot) * m + j] = c0;
+      hdr += 1 + nrot;
+    }
+  }
+  const double dj = own ? ws[L.lam + j] : 0.0;
+  if (own) dd[j] = dj;
+  __syncthreads();
+  int ps = 0;
+  double sg = 1.0;
+  if (own) {
+    for (int q = 0; q < m; ++q) {
+      const double lq = dd[q];
+      ps += (lq > dj) || (lq == dj && q < j);
+    }
+    // eigenvector j is column j of Z = row j of ZT: largest |entry| positive, first on ties
+    int smax = 0;
+    double vmax = -1.0;
+    for (int s2 = 0; s2 < m; ++s2) {
+      const double a = fabs(ZT[j * m + s2]);
+      if (a > vmax) {
+        vmax = a;
+        smax = s2;
+      }
+    }
+    sg = ZT[j * m + smax] < 0.0 ? -1.0 : 1.0;
+    pos[j] = ps;
+    vv[j] = sg;
+    tl[ps] = dj;  // eigenvalues in descending order
+  }
+  __syncthreads();
+  const double lam1 = tl[0];
+  int rank = 0;
+  for (int q = 0; q < m; ++q) rank += (tl[q] > d.tau * lam1) ? 1 : 0;
+  if (own) {
+    for (int q = 0; q < m; ++q) {
+      const int pq = pos[q];
+      const double u = vv[q] * ZT[q * m + j];  // Z[j][q]
+      ws[L.U + j * m + pq] = u;
+      ws[L.W + j * m + pq] = pq < rank ? u / sqrt(tl[pq]) : 0.0;
+    }
+    ws[L.lam + j] = tl[j];
+  }
+  if (j == 0) {
+    int bits = 0;
+    if (rank < m) bits |= NYLS_S_TRUNCATED;
+    if (flag != 0) bits |= NYLS_S_EIG_NOCONV;
+    if (!(lam1 == lam1) || rank == 0) bits |= NYLS_S_NONFINITE;
+    ws[L.info + 0] = (double)rank;
+    ws[L.info + 1] = (double)bits;
+    ws[L.info + 6] = 0.0;
+    ws[L.info + 7] = 0.0;
+  }
+}
+
 }  // namespace
 
 hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hipStream_t st) {
@@ -841,12 +1029,19 @@ hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hip
                          (int)QL_REDO);
     }
   }
+  if (pv.nb_mask & (1u << 16)) {  // wide bases (never in single-instance launches)
+    constexpr int ipw = 8;
+    hipLaunchKernelGGL(k_eig_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, (int)WIDE_REDUCE);
+    hipLaunchKernelGGL((k_ql_lanes<NYLS_MAX_M, NYLS_NARROW_MAX_M, ipw>), dim3((pv.batch + ipw - 1) / ipw),
+                       dim3(64), 0, st, pv.d_desc, ws, pv.batch, ipw);
+    hipLaunchKernelGGL(k_eig_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, (int)WIDE_REPLAY);
+  }
   if (!(pv.nb_mask & 256)) return hipGetLastError();
   // 64 < m <= 128: one wavefront per instance, two rows per lane.  With many such instances
   // the QL is staged like the m <= 64 path (the lane-parallel QL takes up to 64 instances
   // per wavefront); a few run it inside their own wavefront, where all lanes share the
   // scalar chain instead of one lane carrying it.
-  const int lda = pv.maxm | 1;
+  const int lda = pv.maxm_narrow | 1;
   const size_t lds = (size_t)lda * lda * sizeof(double) + 3 * 128 * sizeof(double) + 128 * sizeof(int);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_ql2),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -8,7 +8,8 @@
 
 namespace {
 
-constexpr int TE = 16;  // evaluation points per workgroup
+// evaluation points per workgroup (8 for wide bases, whose kernel values would not fit)
+__host__ __device__ inline int tile_points(int maxm) { return maxm > NYLS_NARROW_MAX_M ? 8 : 16; }
 
 __global__ __launch_bounds__(NYLS_BLOCK) void k_features(
     const nyls_desc* __restrict__ desc, const double* __restrict__ wsbase,
@@ -31,6 +32,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_features(
     if (rank_out && tid == 0) rank_out[inst] = (int32_t)ws[L.info + 0];
   }
   const int nd = dmax + 1;
+  const int TE = tile_points(maxm);
   double* kd = sm;                 // [TE][nd][m]
   double* tl = kd + TE * nd * maxm;
   const double inv_sigma = 1.0 / d.sigma;
@@ -99,6 +101,7 @@ __global__ __launch_bounds__(64) void k_predict(
 hipError_t nyls_launch_features(const nyls_plan_view& pv, const double* ws, const double* t_eval,
                                 const int64_t* eval_off, int dmax, double* phi, double* eigval,
                                 int32_t* rank, int64_t max_eval, int single, hipStream_t st) {
+  const int TE = tile_points(pv.maxm);
   const size_t lds = ((size_t)TE * (dmax + 1) * pv.maxm + NYLS_MAX_M) * sizeof(double);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_features),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -31,9 +31,13 @@
 
 namespace {
 
-constexpr int TP = 64;      // points per tile
 constexpr int CH = 16;      // points per thread in the Gaussian recurrence
 constexpr int MAXB = 3;     // 4x4 blocks per thread (m <= 128 -> at most 561 blocks)
+// Wide bases (m > NYLS_NARROW_MAX_M, split instances only): 32-point tiles (two 260-column
+// tiles fit the LDS), and the up to 2145 blocks of the Gram are shared out over
+// ceil(nblk / (3 * 256)) workgroups per chunk (grid z), each writing its blocks straight
+// from registers; every one of them forms the chunk's rows.
+constexpr int kWideBlocks = MAXB * NYLS_BLOCK;
 
 __device__ inline int instance_of(const int32_t* order) {
   return order ? order[blockIdx.x] : (int)blockIdx.x;
@@ -50,13 +54,17 @@ __device__ inline void block_coords(int blk, int nb, int& bi, int& bj) {
 // smode 1 / 2: split instances, chunk blockIdx.y of the grid, into its partial sum, in
 // kernel space (1, needs nothing from the eigensolver) or, for instances that need the
 // eigenbasis, rotated (2, after the eigensolver).
+// TP = 64: bases up to NYLS_NARROW_MAX_M; TP = 32: wide bases (see kWideBlocks).
+template <int TP>
 __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restrict__ desc,
                                                        const int32_t* __restrict__ order,
                                                        double* __restrict__ wsbase, int maxm,
                                                        int only, int smode) {
+  constexpr bool WIDE = TP == 32;
   extern __shared__ double sm[];
   const nyls_desc& d = desc[instance_of(order)];
   if (((d.flags & NYLS_DF_SPLIT) != 0) != (smode != 0)) return;
+  if ((d.m > NYLS_NARROW_MAX_M) != WIDE) return;
   const int chunk = (int)blockIdx.y;
   if (smode && chunk >= d.nchunks) return;
   if (only && !((int)wsbase[d.ws + nyls_layout(d.m, d.p, 0).info + 1] & only)) return;
@@ -65,7 +73,9 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
   const int gp = (g + 3) & ~3;
   const int nb = gp >> 2;
   const int nblk = nb * (nb + 1) / 2;
-  const int ngrp = nblk >= NYLS_BLOCK ? 1 : NYLS_BLOCK / nblk;
+  const int ngrp = (WIDE || nblk >= NYLS_BLOCK) ? 1 : NYLS_BLOCK / nblk;
+  const int blk0 = WIDE ? (int)blockIdx.z * kWideBlocks : 0;  // first block of this workgroup
+  if (blk0 >= nblk) return;
   const nyls_wsl L = nyls_layout(m, p, 0);
   double* ws = wsbase + d.ws;
   const int tid = threadIdx.x;
@@ -107,8 +117,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
   } else {
 #pragma unroll
     for (int k = 0; k < MAXB; ++k) {
-      const int b = tid + k * NYLS_BLOCK;
-      if (b < nblk) { myblk[k] = b; nmine = k + 1; }
+      const int b = blk0 + tid + k * NYLS_BLOCK;
+      if (b < nblk && (WIDE || b < kWideBlocks)) { myblk[k] = b; nmine = k + 1; }
     }
   }
 #pragma unroll
@@ -177,6 +187,23 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
       }
     }
   }
+  double* out = smode ? wsbase + d.part + nyls_split_gram(m, chunk) : ws + L.gram;
+  if constexpr (WIDE) {
+    // one thread per block: its entries and their mirror images, straight from registers
+#pragma unroll
+    for (int k = 0; k < MAXB; ++k) {
+      if (k >= nmine) break;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int a = 4 * bi[k] + (e >> 2), b = 4 * bj[k] + (e & 3);
+        if (a < g && b < g) {
+          out[a * g + b] = acc[k][e];
+          out[b * g + a] = acc[k][e];
+        }
+      }
+    }
+    return;
+  }
   __syncthreads();
   // Fixed-order reduction of the groups into Q[blk][16].
   for (int gi = 0; gi < ngrp; ++gi) {
@@ -193,7 +220,6 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
     }
     __syncthreads();
   }
-  double* out = smode ? wsbase + d.part + nyls_split_gram(m, chunk) : ws + L.gram;
   for (int e = tid; e < g * g; e += NYLS_BLOCK) {
     int a = e / g, b = e - a * g;
     if (a > b) { const int t = a; a = b; b = t; }
@@ -572,10 +598,11 @@ void launch_ks_all(const nyls_plan_view& pv, double* ws, hipStream_t st, int onl
 
 }  // namespace
 
-size_t nyls_gram64_lds_bytes(int maxm) {
+namespace {
+size_t gram64_lds_bytes(int maxm, int TP, bool wide) {
   const int gp = (maxm + 2 + 3) & ~3;
   const int nb = gp >> 2;
-  const size_t tile = (size_t)TP * gp, red = (size_t)nb * (nb + 1) / 2 * 16;
+  const size_t tile = (size_t)TP * gp, red = wide ? 0 : (size_t)nb * (nb + 1) / 2 * 16;
   // the rotated-row tile Q2 sits after the point flags at an offset that is independent of
   // the instance's own tile width; the reduction buffer may run into fr / tl / okp only
   const size_t base = tile * sizeof(double) + TP * (NYLS_MAX_P + 1) * sizeof(double) +
@@ -585,36 +612,45 @@ size_t nyls_gram64_lds_bytes(int maxm) {
   return total;
 }
 
-namespace {
+// The LDS-tile Gram: TP = 64 for the bases up to NYLS_NARROW_MAX_M (smode 0: unsplit
+// instances, one workgroup each; 1 / 2: split instances, one per chunk), TP = 32 for the wide
+// bases (always split; grid z shares out the Gram's blocks).
+template <int TP>
+void launch_vg(const nyls_plan_view& pv, double* ws, hipStream_t st, int smode, int only) {
+  constexpr bool wide = TP == 32;
+  const int maxm = wide ? pv.maxm : pv.maxm_narrow;
+  if (wide ? (!smode || !(pv.nb_mask & (1u << 16))) : maxm == 0) return;
+  if (smode && !pv.n_split) return;
+  const size_t lds = gram64_lds_bytes(maxm, TP, wide);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64<TP>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int gz = 1;
+  if (wide) {
+    const int nb = ((maxm + 2 + 3) & ~3) >> 2;
+    gz = (nb * (nb + 1) / 2 + kWideBlocks - 1) / kWideBlocks;
+  }
+  const dim3 grid(pv.batch, smode ? pv.max_chunks : 1, gz);
+  hipLaunchKernelGGL(k_gram64<TP>, grid, dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws, maxm,
+                     only, smode);
+}
+
 // Chunk partials of the split instances (smode 1: kernel space, 2: eigenbasis where needed).
 void launch_split_parts(const nyls_plan_view& pv, double* ws, hipStream_t st, int smode) {
-  if (!pv.n_split) return;
-  const size_t lds = nyls_gram64_lds_bytes(pv.maxm);
-  hipLaunchKernelGGL(k_gram64, dim3(pv.batch, pv.max_chunks), dim3(NYLS_BLOCK), lds, st, pv.d_desc,
-                     pv.d_order, ws, pv.maxm, 0, smode);
+  launch_vg<64>(pv, ws, st, smode, 0);
+  launch_vg<32>(pv, ws, st, smode, 0);
 }
 }  // namespace
 
 hipError_t nyls_launch_gram64_kspace(const nyls_plan_view& pv, double* ws, hipStream_t st) {
   launch_ks_all(pv, ws, st, -1);
-  if (pv.n_split) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)nyls_gram64_lds_bytes(pv.maxm));
-    launch_split_parts(pv, ws, st, 1);
-  }
+  launch_split_parts(pv, ws, st, 1);
   return hipGetLastError();
 }
 
 hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t st) {
   if (!pv.only) {
     launch_ks_all(pv, ws, st, 0);
-    if (pv.n_split) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)nyls_gram64_lds_bytes(pv.maxm));
-      launch_split_parts(pv, ws, st, 1);
-    }
+    launch_split_parts(pv, ws, st, 1);
   }
   return nyls_launch_gram64_rest(pv, ws, st);
 }
@@ -622,11 +658,7 @@ hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t 
 hipError_t nyls_launch_gram64_rest(const nyls_plan_view& pv, double* ws, hipStream_t st) {
   if (pv.gnb_mask & 4) launch_mfma_nb<2>(pv, ws, st);
   if (pv.gnb_mask & 16) launch_mfma_nb<4>(pv, ws, st);
-  const size_t lds = nyls_gram64_lds_bytes(pv.maxm);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_gram64, dim3(pv.batch), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws,
-                     pv.maxm, pv.only, 0);
+  launch_vg<64>(pv, ws, st, 0, pv.only);
   if (pv.n_split && !pv.only) {
     launch_split_parts(pv, ws, st, 2);
     hipLaunchKernelGGL(k_gram_split_sum, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws);

@@ -80,10 +80,10 @@ __device__ inline int instance_of(const int32_t* order) {
   return order ? order[blockIdx.x] : (int)blockIdx.x;
 }
 
-// gamma K~ (+ identity) of the kernel-space instances with m + 2 > 64 (nine column blocks
-// cover m <= 128), into the instance's T scratch as rows a <= m, columns b <= m + 1 (row
-// stride m + 2), for k_kkt.  A kernel of its own: its nine accumulator tiles per wavefront
-// would cost k_kkt's other instances their occupancy.
+// gamma K~ (+ identity) of the kernel-space instances with 64 < m + 2 <= 130 (nine column
+// blocks cover m <= 128), into the instance's T scratch as rows a <= m, columns b <= m + 1
+// (row stride m + 2), for k_kkt.  A kernel of its own: its nine accumulator tiles per
+// wavefront would cost k_kkt's other instances their occupancy.
 __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt_mfma_wide(const nyls_desc* __restrict__ desc,
                                                          const int32_t* __restrict__ order,
                                                          double* __restrict__ wsbase, int single,
@@ -91,17 +91,61 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt_mfma_wide(const nyls_desc* _
   const int inst = single >= 0 ? single : instance_of(order);
   const nyls_desc& d = desc[inst];
   const int m = d.m, g = m + 2;
-  if (g <= 64) return;
+  if (g <= 64 || m > NYLS_NARROW_MAX_M) return;
   const nyls_wsl L = nyls_layout(m, d.p, 0);
   double* ws = wsbase + d.ws;
   if (only && !((int)ws[L.info + 1] & only)) return;
   if (eigbasis || ws[L.info + 4] != 0.0) return;
   const int r = (int)ws[L.info + 0];
   double* T = ws + L.tmp;
-  kkt_transform_mfma<(NYLS_MAX_M + 2 + 15) / 16>(ws + L.gram, ws + L.W, m, r, d.gamma,
+  kkt_transform_mfma<(NYLS_NARROW_MAX_M + 2 + 15) / 16>(ws + L.gram, ws + L.W, m, r, d.gamma,
                         [&](int a, int b, double v) { T[a * g + b] = v; });
 }
 
+// The same product for the wide bases (kernel-space Gram), in two element-parallel steps
+// over the instance's workspace: step 0 forms P = S~ W~ (g x g, in the rotation-log region,
+// free after the eigensolver), step 1 gamma W~^T P (+ identity) into T.  Grid (instance,
+// element tiles of 256).
+__global__ __launch_bounds__(NYLS_BLOCK) void k_kkt_wide_transform(const nyls_desc* __restrict__ desc,
+                                                              double* __restrict__ wsbase, int step) {
+  const nyls_desc& d = desc[blockIdx.x];
+  const int m = d.m, g = m + 2;
+  if (m <= NYLS_NARROW_MAX_M) return;
+  const nyls_wsl L = nyls_layout(m, d.p, 0);
+  double* ws = wsbase + d.ws;
+  if (ws[L.info + 4] != 0.0) return;  // eigenbasis Gram: k_kkt scales it directly
+  const int e = (int)blockIdx.y * NYLS_BLOCK + (int)threadIdx.x;
+  const int r = (int)ws[L.info + 0];
+  const double* W = ws + L.W;
+  double* P = ws + L.log;
+  if (step == 0) {
+    if (e >= g * g) return;
+    const int a = e / g, k = e - a * g;
+    const double* S = ws + L.gram;
+    double v = 0.0;
+    if (k >= m) {
+      v = S[a * g + k];
+    } else if (k < r) {
+      for (int s = 0; s < m; ++s) v += S[a * g + s] * W[s * m + k];
+    }
+    P[e] = v;
+  } else {
+    if (e >= (m + 1) * g) return;
+    const int a = e / g, b = e - a * g;
+    double v = 0.0;
+    if (a == m) {
+      v = P[m * g + b];
+    } else if (a < r) {
+      for (int s = 0; s < m; ++s) v += W[s * m + a] * P[s * g + b];
+    }
+    ws[L.tmp + e] = d.gamma * v + ((a == b && a < m) ? 1.0 : 0.0);
+  }
+}
+
+// WIDE = false: bases up to NYLS_NARROW_MAX_M, the matrix in LDS; WIDE = true: the wide
+// bases, the matrix assembled and factored in place in the workspace (it would not fit the
+// LDS).  Each instantiation skips the other's instances.
+template <bool WIDE>
 __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict__ desc,
                                                     const int32_t* __restrict__ order,
                                                     double* __restrict__ wsbase,
@@ -112,9 +156,13 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
   extern __shared__ double sm[];
   const int inst = single >= 0 ? single : instance_of(order);
   const nyls_desc& d = desc[inst];
+  if ((d.m > NYLS_NARROW_MAX_M) != WIDE) return;
   if (only && !((int)wsbase[d.ws + nyls_layout(d.m, d.p, 0).info + 1] & only)) return;
   const int m = d.m, p = d.p;
-  const int g = m + 2, N = m + 1 + p, lda = N | 1;  // odd row stride: row-per-lane access is conflict-free
+  // in LDS with an odd row stride (row-per-lane access is conflict-free), the factors copied
+  // out afterwards; wide bases in place
+  constexpr bool wide = WIDE;
+  const int g = m + 2, N = m + 1 + p, lda = wide ? N : (N | 1);
   const nyls_wsl L = nyls_layout(m, p, 0);
   double* ws = wsbase + d.ws;
   const double* W = ws + L.W;
@@ -124,8 +172,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
   const int r = (int)ws[L.info + 0];
   const double gam = d.gamma;
 
-  double* K = sm;                       // [N][lda]
-  double* rhs = K + N * lda;            // [N]
+  double* K = wide ? ws + L.lu : sm;     // [N][lda]
+  double* rhs = wide ? sm : K + N * lda;  // [N]
   double* kc = rhs + (N + 1);           // [p][m] kernel-derivative vectors of the conditions
   double* red = kc + NYLS_MAX_P * NYLS_MAX_M;
   int* piv = reinterpret_cast<int*>(red + 16);  // [N + 1]
@@ -158,27 +206,18 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
     kc[j * NYLS_MAX_M + s] = nyls_pick(kd, d.cond_d[j]);
   }
   __syncthreads();
-  // feature-space condition rows h_j = W^T k^(d_j)(t_{i_j}), each entry formed once (p m <=
-  // 2 per thread), then kept in kc in place of the kernel vectors and in the workspace for
-  // the later passes
-  double hv[2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int e = tid + u * NYLS_BLOCK;
-    hv[u] = 0.0;
-    if (e < p * m) {
-      const int j = e / m, k = e - j * m;
-      if (k < r)
-        for (int s = 0; s < m; ++s) hv[u] += W[s * m + k] * kc[j * NYLS_MAX_M + s];
-      ws[L.H + e] = hv[u];
-    }
+  // feature-space condition rows h_j = W^T k^(d_j)(t_{i_j}), each entry formed once and
+  // written to the workspace for the later passes, then read back into kc in place of the
+  // kernel vectors (once every thread has finished reading those)
+  for (int e = tid; e < p * m; e += NYLS_BLOCK) {
+    const int j = e / m, k = e - j * m;
+    double hv = 0.0;
+    if (k < r)
+      for (int s = 0; s < m; ++s) hv += W[s * m + k] * kc[j * NYLS_MAX_M + s];
+    ws[L.H + e] = hv;
   }
   __syncthreads();
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int e = tid + u * NYLS_BLOCK;
-    if (e < p * m) kc[(e / m) * NYLS_MAX_M + e % m] = hv[u];
-  }
+  for (int e = tid; e < p * m; e += NYLS_BLOCK) kc[(e / m) * NYLS_MAX_M + e % m] = ws[L.H + e];
   __syncthreads();
   for (int e = tid; e < N * N; e += NYLS_BLOCK) {
     const int a = e / N, b = e - a * N;
@@ -241,7 +280,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
   } else {
     sing = nyls_lu(K, lda, N, piv, red);
     nyls_lu_solve(K, lda, N, piv, rhs);
-    for (int e = tid; e < N * N; e += NYLS_BLOCK) ws[L.lu + e] = K[(e / N) * lda + e % N];
+    if (!wide)
+      for (int e = tid; e < N * N; e += NYLS_BLOCK) ws[L.lu + e] = K[(e / N) * lda + e % N];
   }
   for (int a = tid; a < N; a += NYLS_BLOCK) {
     ws[L.piv + a] = (double)piv[a];
@@ -263,23 +303,38 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
 
 }  // namespace
 
-size_t nyls_kkt_lds_bytes(int maxm, int maxp) {
-  const int N = maxm + 1 + maxp;
-  return ((size_t)N * (N + 1) + (N + 1) + NYLS_MAX_P * NYLS_MAX_M + 16) * sizeof(double) +
-         (size_t)2 * (N + 1) * sizeof(int);
+// LDS of k_kkt: the matrix of the largest on-chip system (bases up to NYLS_NARROW_MAX_M),
+// or the vectors of a wide one, whichever is larger.
+size_t nyls_kkt_lds_bytes(int maxm_narrow, int maxm, int maxp) {
+  const int Nn = maxm_narrow + 1 + maxp, Nw = maxm + 1 + maxp;
+  const size_t narrow = maxm_narrow > 0 ? (size_t)Nn * (Nn + 1) + (Nn + 1) : 0;
+  const size_t wide = maxm > NYLS_NARROW_MAX_M ? (size_t)(Nw + 1) : 0;
+  const int Nmax = Nn > Nw ? Nn : Nw;
+  return ((narrow > wide ? narrow : wide) + NYLS_MAX_P * NYLS_MAX_M + 16) * sizeof(double) +
+         (size_t)2 * (Nmax + 1) * sizeof(int);
 }
 
 hipError_t nyls_launch_kkt(const nyls_plan_view& pv, double* ws, double* kkt_out, double* rhs_out,
                            int factor, hipStream_t st) {
-  const size_t lds = nyls_kkt_lds_bytes(pv.maxm, pv.maxp);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_kkt),
+  const size_t lds = nyls_kkt_lds_bytes(pv.maxm_narrow, pv.maxm, pv.maxp);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_kkt<false>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const int kn = pv.maxm + 1 + NYLS_MAX_P;
   const int eb = (pv.mode == NYLS_MIXED && !pv.only) ? 1 : 0;
-  if (pv.maxm + 2 > 64 && !eb)
+  if (pv.maxm_narrow + 2 > 64 && !eb)
     hipLaunchKernelGGL(k_kkt_mfma_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, pv.d_order, ws,
                        -1, eb, pv.only);
-  hipLaunchKernelGGL(k_kkt, dim3(pv.batch), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws,
-                     kkt_out, rhs_out, kn, factor, -1, eb, pv.only);
+  if (pv.maxm > NYLS_NARROW_MAX_M && !eb) {
+    const int g = pv.maxm + 2;
+    for (int step = 0; step < 2; ++step)
+      hipLaunchKernelGGL(k_kkt_wide_transform, dim3(pv.batch, (g * g + NYLS_BLOCK - 1) / NYLS_BLOCK),
+                         dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, step);
+  }
+  if (pv.maxm_narrow > 0)
+    hipLaunchKernelGGL(k_kkt<false>, dim3(pv.batch), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws,
+                       kkt_out, rhs_out, kn, factor, -1, eb, pv.only);
+  if (pv.maxm > NYLS_NARROW_MAX_M)
+    hipLaunchKernelGGL(k_kkt<true>, dim3(pv.batch), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws,
+                       kkt_out, rhs_out, kn, factor, -1, eb, pv.only);
   return hipGetLastError();
 }

@@ -42,11 +42,11 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_lev_prepare(const nyls_desc* __r
   const double ridge = ridge_in > 0.0 ? ridge_in : 1.0 / d.gamma;
   const double inv_sigma = 1.0 / d.sigma;
   double* tl = sm;                  // [128]
-  double* red = tl + NYLS_MAX_M;    // [16]
+  double* red = tl + NYLS_NARROW_MAX_M;    // [16]
   int* piv = reinterpret_cast<int*>(red + 16);  // [128]
-  double* big = reinterpret_cast<double*>(piv + NYLS_MAX_M);
+  double* big = reinterpret_cast<double*>(piv + NYLS_NARROW_MAX_M);
   double* K = big;                  // [TP][maxm] kernel values of a tile
-  double* Q = K + TP * NYLS_MAX_M;  // [TP][gp] features of a tile (also the reduction buffer)
+  double* Q = K + TP * NYLS_NARROW_MAX_M;  // [TP][gp] features of a tile (also the reduction buffer)
   for (int s = tid; s < m; s += NYLS_BLOCK) tl[s] = nyls_grid_t(d, d.lidx[s]);
   __syncthreads();
   // G = Phi^T Phi accumulated in feature space: a kernel-space sum mapped through W twice
@@ -56,13 +56,13 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_lev_prepare(const nyls_desc* __r
   for (int i0 = 0; i0 < n; i0 += TP) {
     __syncthreads();
     nyls_gauss_tile<TP, CH>(d, i0, tl, inv_sigma,
-                            [&](int pt, int s, double, double ev) { K[pt * NYLS_MAX_M + s] = ev; });
+                            [&](int pt, int s, double, double ev) { K[pt * NYLS_NARROW_MAX_M + s] = ev; });
     __syncthreads();
     for (int e = tid; e < TP * gp; e += NYLS_BLOCK) {
       const int pt = e / gp, k = e - pt * gp;
       double acc = 0.0;
       if (k < r)
-        for (int s = 0; s < m; ++s) acc += K[pt * NYLS_MAX_M + s] * W[s * m + k];
+        for (int s = 0; s < m; ++s) acc += K[pt * NYLS_NARROW_MAX_M + s] * W[s * m + k];
       Q[e] = acc;
     }
     __syncthreads();
@@ -94,10 +94,10 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_lev_prepare(const nyls_desc* __r
 __global__ __launch_bounds__(NYLS_BLOCK) void k_lev_scores(const nyls_desc* __restrict__ desc,
                                                            const double* __restrict__ wsbase,
                                                            double* __restrict__ scores) {
-  __shared__ double kt[SP][NYLS_MAX_M + 1];  // k_i, then phi_i = W^T k_i
-  __shared__ double ph[SP][NYLS_MAX_M + 1];
+  __shared__ double kt[SP][NYLS_NARROW_MAX_M + 1];  // k_i, then phi_i = W^T k_i
+  __shared__ double ph[SP][NYLS_NARROW_MAX_M + 1];
   __shared__ double part[NYLS_BLOCK];
-  __shared__ double tl[NYLS_MAX_M];
+  __shared__ double tl[NYLS_NARROW_MAX_M];
   const nyls_desc& d = desc[blockIdx.y];
   const int m = d.m, n = d.n;
   const int i0 = blockIdx.x * SP;
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_lev_select(const nyls_desc* __re
                                                            int32_t* __restrict__ lidx, int maxm) {
   __shared__ double bk[NYLS_BLOCK / 64];
   __shared__ int bi[NYLS_BLOCK / 64];
-  __shared__ int chosen[NYLS_MAX_M];
+  __shared__ int chosen[NYLS_NARROW_MAX_M];
   const int inst = blockIdx.x;
   const nyls_desc& d = desc[inst];
   const int m = d.m, n = d.n;
@@ -227,10 +227,10 @@ size_t prepare_lds_bytes(int maxm) {
   size_t q = (size_t)TP * gp;
   const size_t redd = nyls_gram::red_doubles(gp);
   if (redd > q) q = redd;
-  size_t tile = (size_t)TP * NYLS_MAX_M + q;
+  size_t tile = (size_t)TP * NYLS_NARROW_MAX_M + q;
   const size_t g = (size_t)maxm * (maxm + 1) + maxm;
   if (g > tile) tile = g;
-  return (NYLS_MAX_M + 16) * sizeof(double) + NYLS_MAX_M * sizeof(int) + tile * sizeof(double);
+  return (NYLS_NARROW_MAX_M + 16) * sizeof(double) + NYLS_NARROW_MAX_M * sizeof(int) + tile * sizeof(double);
 }
 
 }  // namespace
@@ -243,6 +243,7 @@ extern "C" int nyls_leverage_scores(const nyls_plan* pl, double ridge, double* s
   if (!pl || !scores || !ws) return NYLS_E_NULL;
   if (!(ridge >= 0.0) || !(ridge < HUGE_VAL)) return NYLS_E_ARG;
   const nyls_plan_view pv = nyls_plan_get_view(pl);
+  if (pv.maxm > NYLS_NARROW_MAX_M) return NYLS_E_SIZE;
   double* w = static_cast<double*>(ws);
   hipError_t e = nyls_launch_eig(pv, w, -1, stream);
   if (e != hipSuccess) return NYLS_E_HIP;
@@ -261,6 +262,7 @@ extern "C" int nyls_leverage_sample(const nyls_plan* pl, const double* scores, c
   if (!pl || !scores || !u || !lidx) return NYLS_E_NULL;
   // with `ends` the other m - 2 landmarks come from the n - 2 interior points (m <= n)
   const nyls_plan_view pv = nyls_plan_get_view(pl);
+  if (pv.maxm > NYLS_NARROW_MAX_M) return NYLS_E_SIZE;
   hipLaunchKernelGGL(k_lev_select, dim3(pv.batch), dim3(NYLS_BLOCK), 0, stream, pv.d_desc, scores, u,
                      ends ? 1 : 0, lidx, pv.maxm);
   return hipGetLastError() == hipSuccess ? NYLS_OK : NYLS_E_HIP;

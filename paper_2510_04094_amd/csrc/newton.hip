@@ -56,8 +56,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_init(const nyls_desc* __r
   const int r = (int)ws[L.info + 0];
   const double inv_sigma = 1.0 / d.sigma;
   double* tl = sm;                          // [128]
-  double* kc = tl + NYLS_MAX_M;             // [128]
-  double* okf = kc + NYLS_MAX_M;            // [TP]
+  double* kc = tl + NYLS_NARROW_MAX_M;             // [128]
+  double* okf = kc + NYLS_NARROW_MAX_M;            // [TP]
   double* Q = okf + TP;                     // [2*TP][gp], later the reduction buffer
   for (int s = tid; s < m; s += NYLS_BLOCK) tl[s] = nyls_grid_t(d, d.lidx[s]);
   __syncthreads();
@@ -131,10 +131,10 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_step(
 
   // common LDS
   double* tl = sm;                       // [128] landmark times
-  double* al = tl + NYLS_MAX_M;          // [128] alpha
-  double* dal = al + NYLS_MAX_M;         // [128] W domega
-  double* lin = dal + NYLS_MAX_M;        // [128] sum rho k' - eta k
-  double* part = lin + NYLS_MAX_M;       // [256] partial sums
+  double* al = tl + NYLS_NARROW_MAX_M;          // [128] alpha
+  double* dal = al + NYLS_NARROW_MAX_M;         // [128] W domega
+  double* lin = dal + NYLS_NARROW_MAX_M;        // [128] sum rho k' - eta k
+  double* part = lin + NYLS_NARROW_MAX_M;       // [256] partial sums
   double* red = part + NYLS_BLOCK;       // [16]
   double* rhs = red + 16;                // [136]
   double* pd = rhs + 136;                // [TP][8] per-point data
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_step(
 }
 
 size_t step_lds_bytes(int maxm) {
-  const size_t common = (4 * NYLS_MAX_M + NYLS_BLOCK + 16 + 136 + TP * 8) * sizeof(double) + 136 * sizeof(int);
+  const size_t common = (4 * NYLS_NARROW_MAX_M + NYLS_BLOCK + 16 + 136 + TP * 8) * sizeof(double) + 136 * sizeof(int);
   const int gp = round4(maxm + 2);
   size_t pass = (2 * (size_t)TP * maxm + (size_t)TP * gp + TP) * sizeof(double);
   const size_t redb = (size_t)nyls_gram::red_doubles(gp) * sizeof(double);
@@ -372,7 +372,7 @@ size_t init_lds_bytes(int maxm) {
   size_t q = 2 * (size_t)TP * gp;
   const size_t redd = nyls_gram::red_doubles(gp);
   if (redd > q) q = redd;
-  return (2 * NYLS_MAX_M + TP + q) * sizeof(double);
+  return (2 * NYLS_NARROW_MAX_M + TP + q) * sizeof(double);
 }
 
 __global__ __launch_bounds__(NYLS_BLOCK) void k_riccati_eval(
@@ -397,6 +397,7 @@ extern "C" int nyls_riccati_eval(const nyls_plan* pl, const double* q, const dou
   if (!pl || !q || !x || !F || !Fy || !Fyy) return NYLS_E_NULL;
   if (!nyls_plan_first_order(pl)) return NYLS_E_NONLINEAR;
   const nyls_plan_view pv = nyls_plan_get_view(pl);
+  if (pv.maxm > NYLS_NARROW_MAX_M) return NYLS_E_SIZE;
   int gx = (pv.maxn + NYLS_BLOCK - 1) / NYLS_BLOCK;
   gx = gx > 64 ? 64 : gx;
   hipLaunchKernelGGL(k_riccati_eval, dim3(gx, pv.batch), dim3(NYLS_BLOCK), 0, stream, pv.d_desc, q, x,
@@ -411,6 +412,7 @@ extern "C" int nyls_newton_init(const nyls_plan* pl, double* x, void* ws, hipStr
   const int order = nyls_plan_common_order(pl);
   if (order != 1 && order != 2) return NYLS_E_NONLINEAR;
   const nyls_plan_view pv = nyls_plan_get_view(pl);
+  if (pv.maxm > NYLS_NARROW_MAX_M) return NYLS_E_SIZE;
   double* w = static_cast<double*>(ws);
   hipError_t e = nyls_launch_eig(pv, w, -1, stream);
   if (e != hipSuccess) return NYLS_E_HIP;
@@ -431,6 +433,7 @@ extern "C" int nyls_newton_state(const nyls_plan* pl, const double* x, double* u
   if (!pl || !x || !u || !ws) return NYLS_E_NULL;
   const int order = nyls_plan_common_order(pl);
   if (order != 1 && order != 2) return NYLS_E_NONLINEAR;
+  if (nyls_plan_get_view(pl).maxm > NYLS_NARROW_MAX_M) return NYLS_E_SIZE;
   const hipError_t e = nyls_launch_newton_state(nyls_plan_get_view(pl), static_cast<const double*>(ws),
                                                 x, (int64_t)nyls_plan_newton_stride(pl), u, stream);
   return e == hipSuccess ? NYLS_OK : NYLS_E_HIP;
@@ -443,6 +446,7 @@ extern "C" int nyls_newton_step(const nyls_plan* pl, const double* F, const doub
   const int order = nyls_plan_common_order(pl);
   if (order != 1 && order != 2) return NYLS_E_NONLINEAR;
   const nyls_plan_view pv = nyls_plan_get_view(pl);
+  if (pv.maxm > NYLS_NARROW_MAX_M) return NYLS_E_SIZE;
   if (order == 2) {
     nyls_prof_begin(NYLS_K_NEWTON, stream);
     const hipError_t e = nyls_launch_newton2_step(pv, static_cast<double*>(ws), F, Fy, Fyy, x,

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton2_init(const nyls_desc* __
                                                              double* __restrict__ wsbase,
                                                              double* __restrict__ x, int64_t xs,
                                                              int maxm, int maxp) {
-  __shared__ double kc[NYLS_MAX_P][NYLS_MAX_M];
+  __shared__ double kc[NYLS_MAX_P][NYLS_NARROW_MAX_M];
   const int inst = blockIdx.x;
   const nyls_desc& d = desc[inst];
   const int m = d.m, n = d.n;
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_state(const nyls_desc* __
                                                              const double* __restrict__ x,
                                                              int64_t xs, int maxm, int maxp,
                                                              double* __restrict__ u, int64_t total) {
-  __shared__ double al[NYLS_MAX_M], tl[NYLS_MAX_M];
+  __shared__ double al[NYLS_NARROW_MAX_M], tl[NYLS_NARROW_MAX_M];
   const nyls_desc& d = desc[blockIdx.y];
   const int m = d.m, n = d.n;
   const nyls_wsl L = nyls_layout(m, d.p, 0);
@@ -134,10 +134,10 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton2_step(
 
   // common LDS
   double* tl = sm;                        // [128] landmark times
-  double* al = tl + NYLS_MAX_M;           // [128] alpha
-  double* dal = al + NYLS_MAX_M;          // [128] W d omega
-  double* lin = dal + NYLS_MAX_M;         // [128] sum rho q - eta phi (feature space)
-  double* part = lin + NYLS_MAX_M;        // [256] partial sums
+  double* al = tl + NYLS_NARROW_MAX_M;           // [128] alpha
+  double* dal = al + NYLS_NARROW_MAX_M;          // [128] W d omega
+  double* lin = dal + NYLS_NARROW_MAX_M;         // [128] sum rho q - eta phi (feature space)
+  double* part = lin + NYLS_NARROW_MAX_M;        // [256] partial sums
   double* red = part + NYLS_BLOCK;        // [16]
   double* rhs = red + 16;                 // [136]
   double* pd = rhs + 136;                 // [TP][8] per-point data
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton2_step(
 }  // namespace
 
 size_t nyls_newton2_lds_bytes(int maxm) {
-  const size_t common = (4 * NYLS_MAX_M + NYLS_BLOCK + 16 + 136 + TP * 8) * sizeof(double) +
+  const size_t common = (4 * NYLS_NARROW_MAX_M + NYLS_BLOCK + 16 + 136 + TP * 8) * sizeof(double) +
                         136 * sizeof(int);
   const int gp = round4(maxm + 2);
   const size_t qrows = (size_t)NR * TP;

@@ -7,6 +7,12 @@
 
 #define NYLS_BLOCK 256
 
+// Bases up to this size run the one-wavefront passes (up to eight 16-slot landmark blocks
+// per lane) and keep K_mm and the KKT matrix on chip; wider ones (up to NYLS_MAX_M) are
+// always split over point chunks, with two wavefronts per chunk, one per half of the
+// landmark slots, and factor K_mm and the KKT matrix in the workspace.
+#define NYLS_NARROW_MAX_M 128
+
 // One instance as the kernels see it (device-resident table, one entry per instance).
 struct nyls_desc {
   int32_t p, n, m, uniform;
@@ -313,8 +319,11 @@ void nyls_prof_end(int kernel, hipStream_t st);
 enum { NYLS_K_EIG = 0, NYLS_K_GRAM64, NYLS_K_GRAM32, NYLS_K_KKT, NYLS_K_POINTS, NYLS_K_FEATURES,
        NYLS_K_PREDICT, NYLS_K_EXPLICIT, NYLS_K_NEWTON, NYLS_K_BACKWARD, NYLS_K_COUNT };
 
-// 16-landmark slot blocks per lane of the one-wave passes for an instance with m landmarks.
-__host__ __device__ inline int nyls_slot_blocks(int m) { return m <= 32 ? 2 : (m <= 64 ? 4 : 8); }
+// 16-landmark slot blocks per lane of the one-wave passes for an instance with m landmarks
+// (16 for the wide bases: eight per lane in each of two wavefronts).
+__host__ __device__ inline int nyls_slot_blocks(int m) {
+  return m <= 32 ? 2 : (m <= 64 ? 4 : (m <= NYLS_NARROW_MAX_M ? 8 : 16));
+}
 
 // Column blocks of the kernel-space MFMA Gram (m + 2 <= 64): nbu = ceil((m + 2) / 16) blocks
 // carry data, and the last of them goes to the VALU when it holds at most four columns;
@@ -342,6 +351,7 @@ __host__ __device__ inline int nyls_walk_tail(int m) {
 // Host launchers (defined in the .hip files; all enqueue on `stream`).
 struct nyls_plan_view {
   int32_t batch, mode, maxm, maxp, maxn;
+  int32_t maxm_narrow;      // largest m <= NYLS_NARROW_MAX_M (0 if none): sizes on-chip buffers
   unsigned p_mask;          // bit p set when some instance has ODE order p
   unsigned rec_mask;        // bit 1: some instance has rec == 1, bit 0: some has rec == 0
   unsigned nb_mask;         // bit b set when some instance has nyls_slot_blocks(m) == b

@@ -124,7 +124,9 @@ struct nyls_walk {
   bool tlv;
   double te, tr16, tg, q16, q16m1, g16;
 
-  __device__ void init(const nyls_desc& d, int lane) {
+  // s0: first landmark of the lane's slots (0, or 16 NB for the second wavefront of a wide
+  // basis); slot b of the lane is landmark s0 + 16 b + sl.
+  __device__ void init(const nyls_desc& d, int lane, int s0 = 0) {
     sl = lane & 15;
     ph = lane >> 4;
     n = d.n;
@@ -138,7 +140,7 @@ struct nyls_walk {
     tr = nyls_rsrc(EX && !d.uniform ? d.t : nullptr, EX && !d.uniform ? n * 8 : 0);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int s = 16 * b + sl;
+      const int s = s0 + 16 * b + sl;
       lv[b] = s < d.m;
       ls[b] = lv[b] ? d.lidx[s] : 0;
       ev[b] = rv[b] = gc[b] = 0.0;
@@ -291,6 +293,30 @@ __device__ inline void nyls_walk_sum_tail(const double* tile, const double* ttil
     out[q] = nyls_add_xor32(nyls_add_xor16(s));
   }
   nyls_wave_lds_sync();
+}
+
+// Wide bases, G wavefronts per workgroup (wavefront grp walks landmark slots
+// grp * 16 NB ..): every wavefront holds in tot[q] the totals of chunk point lane & 15 over its
+// own slots; afterwards every lane holds the sums over all G wavefronts, added in wavefront
+// order, so all wavefronts see bitwise the same values.  xw: LDS, 2 * G * Q * 16 doubles;
+// `parity` alternates between consecutive calls, so one workgroup barrier per call suffices
+// (a buffer is written again only after every wavefront has passed the next call's barrier,
+// i.e. finished reading it).  Every wavefront of the workgroup must make the same calls.
+template <int G, int Q>
+__device__ inline void nyls_walk_join(double (&tot)[Q], double* xw, int lane, int grp, int parity) {
+  double* buf = xw + parity * (G * Q * 16);
+  if (lane < 16)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) buf[(grp * Q + q) * 16 + lane] = tot[q];
+  __syncthreads();
+  const int pt = lane & 15;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double v = buf[q * 16 + pt];
+#pragma unroll
+    for (int g = 1; g < G; ++g) v += buf[(g * Q + q) * 16 + pt];
+    tot[q] = v;
+  }
 }
 
 // Per-point values w[q] held by lanes 0..15 (for chunk point lane) are returned in every lane

@@ -25,7 +25,8 @@
 
 namespace {
 
-constexpr int NK = NYLS_MAX_M + 1 + NYLS_MAX_P;
+constexpr int NK = NYLS_MAX_M + 1 + NYLS_MAX_P;          // split instances (any basis)
+constexpr int NKN = NYLS_NARROW_MAX_M + 1 + NYLS_MAX_P;  // one-wave instances
 
 __device__ inline int instance_of(const int32_t* order, int single) {
   return single >= 0 ? single : (order ? order[blockIdx.x] : (int)blockIdx.x);
@@ -41,8 +42,8 @@ __global__ __launch_bounds__(64) void k_points(
   __shared__ __align__(16) double tile[2 * 16 * NYLS_WALK_PAD];
   __shared__ double ttile[TL ? 2 * 64 : 1];
   __shared__ double bc[16];
-  __shared__ double Rv[NK], xv[NK], zs[NYLS_MAX_M];
-  __shared__ int piv[NK];
+  __shared__ double Rv[NKN], xv[NKN], zs[NYLS_NARROW_MAX_M];
+  __shared__ int piv[NKN];
 
   const int inst = instance_of(order, single);
   const nyls_desc& d = desc[inst];
@@ -334,14 +335,21 @@ __global__ void k_split_init(const nyls_desc* __restrict__ desc, double* __restr
   st[SS_CORR] = st[SS_DPREV] = st[SS_BPREV] = st[SS_PASSES] = st[SS_YMAX] = 0.0;
 }
 
-template <int NB, int P, bool EX, bool REF>
-__global__ __launch_bounds__(64) void k_pass_split(const nyls_desc* __restrict__ desc,
-                                                   double* __restrict__ wsbase,
-                                                   double* __restrict__ yhat, int track) {
-  __shared__ __align__(16) double tile[2 * 16 * NYLS_WALK_PAD];
-  __shared__ double bc[16];
+// G = 2: wide bases (m > NYLS_NARROW_MAX_M), two wavefronts per chunk, wavefront w walking
+// the landmark slots 16 NB w .. 16 NB (w + 1) - 1; the per-point sums over the landmarks are
+// joined through LDS (nyls_walk_join), after which both wavefronts hold the same residuals
+// and each accumulates the landmark sums of its own slots.
+template <int NB, int P, bool EX, bool REF, int G = 1>
+__global__ __launch_bounds__(64 * G) void k_pass_split(const nyls_desc* __restrict__ desc,
+                                                       double* __restrict__ wsbase,
+                                                       double* __restrict__ yhat, int track) {
+  constexpr int Q = REF ? 2 : 1;
+  __shared__ __align__(16) double tiles[G][2 * 16 * NYLS_WALK_PAD];
+  __shared__ double bcs[G][16];
+  __shared__ double xw[G > 1 ? 2 * G * Q * 16 : 1];
   const nyls_desc& d = desc[blockIdx.x];
-  if (!(d.flags & NYLS_DF_SPLIT) || d.p != P || d.rec != (EX ? 0 : 1) || nyls_slot_blocks(d.m) != NB)
+  if (!(d.flags & NYLS_DF_SPLIT) || d.p != P || d.rec != (EX ? 0 : 1) ||
+      nyls_slot_blocks(d.m) != NB * G)
     return;
   const int c = (int)blockIdx.y;
   if (c >= d.nchunks) return;
@@ -350,12 +358,16 @@ __global__ __launch_bounds__(64) void k_pass_split(const nyls_desc* __restrict__
   double* ws = wsbase + d.ws;
   const double* sst = ws + L.acc;
   if (REF ? sst[SS_DONE] != 0.0 : sst[SS_NEEDOUT] == 0.0) return;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, grp = G > 1 ? (int)(threadIdx.x >> 6) : 0;
+  const int s0 = 16 * NB * grp;  // first landmark slot of this wavefront
+  double* const tile = tiles[grp];
+  double* const bc = bcs[grp];
+  const bool lead = grp == 0;  // writes the per-point outputs and scalar sums
   const int ibeg = c * d.chunk, iend = min(n, ibeg + d.chunk);
   double* yo = yhat + d.goff;
 
   nyls_walk<NB, EX> wk;
-  wk.init(d, lane);
+  wk.init(d, lane, s0);
   nyls_cpts cpt;
   cpt.init(d);
   const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
@@ -363,14 +375,14 @@ __global__ __launch_bounds__(64) void k_pass_split(const nyls_desc* __restrict__
   const __amdgpu_buffer_rsrc_t yr = nyls_rsrc(yhat + d.goff, n * 8);
   double alv[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) alv[b] = wk.lv[b] ? ws[L.alpha + 16 * b + wk.sl] : 0.0;
+  for (int b = 0; b < NB; ++b) alv[b] = wk.lv[b] ? ws[L.alpha + s0 + 16 * b + wk.sl] : 0.0;
   const double bias = ws[L.x + m];
   nyls_oppoly<P> op;
   op.init(inv_s2);
-  constexpr int Q = REF ? 2 : 1;
   double zacc[NB], sacc = 0.0, ymax = 0.0, dmax = 0.0;
 #pragma unroll
   for (int b = 0; b < NB; ++b) zacc[b] = 0.0;
+  int parity = 0;
   struct stage {
     double f[P][4];
     double r, c, y;
@@ -417,10 +429,14 @@ __global__ __launch_bounds__(64) void k_pass_split(const nyls_desc* __restrict__
         });
     double tot[Q];
     nyls_walk_sum<Q>(tile, lane, tot);
+    if constexpr (G > 1) {
+      nyls_walk_join<G, Q>(tot, xw, lane, grp, parity);
+      parity ^= 1;
+    }
     const int ip = i0 + (lane & 15);
     const double yv = tot[0] + bias;
     if (ip < n) {
-      if (lane < 16) {
+      if (lane < 16 && lead) {
         if (track) dmax = fmax(dmax, fabs(yv - st.y));
         yo[ip] = yv;
       }
@@ -455,11 +471,11 @@ __global__ __launch_bounds__(64) void k_pass_split(const nyls_desc* __restrict__
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb) {
       const double zb = nyls_walk_fold(zacc[bb]);
-      if (wk.ph == 0 && wk.lv[bb]) part[16 * bb + wk.sl] = zb;
+      if (wk.ph == 0 && wk.lv[bb]) part[s0 + 16 * bb + wk.sl] = zb;
     }
   }
   const double ssum = nyls_wave_sum(sacc);
-  if (lane == 0) {
+  if (lane == 0 && lead) {
     part[m] = ssum;
     part[m + 1] = ymax;
     part[m + 2] = dmax;
@@ -642,12 +658,14 @@ hipError_t launch_nb(const nyls_plan_view& pv, double* ws, int refine, double* y
 }  // namespace
 
 namespace {
+// NB: slot blocks of the instance class (16: wide bases, two wavefronts of eight blocks)
 template <int NB, int P, bool EX>
 void launch_pass_split(const nyls_plan_view& pv, double* ws, double* yhat, bool ref, int track,
                        hipStream_t st) {
-  const dim3 grid(pv.batch, pv.max_chunks);
-  if (ref) hipLaunchKernelGGL((k_pass_split<NB, P, EX, true>), grid, dim3(64), 0, st, pv.d_desc, ws, yhat, track);
-  else hipLaunchKernelGGL((k_pass_split<NB, P, EX, false>), grid, dim3(64), 0, st, pv.d_desc, ws, yhat, track);
+  constexpr int G = NB > 8 ? NB / 8 : 1, NW = NB / G;
+  const dim3 grid(pv.batch, pv.max_chunks), block(64 * G);
+  if (ref) hipLaunchKernelGGL((k_pass_split<NW, P, EX, true, G>), grid, block, 0, st, pv.d_desc, ws, yhat, track);
+  else hipLaunchKernelGGL((k_pass_split<NW, P, EX, false, G>), grid, block, 0, st, pv.d_desc, ws, yhat, track);
 }
 
 template <int NB, int P>
@@ -688,6 +706,7 @@ void launch_split_points(const nyls_plan_view& pv, double* ws, int refine, doubl
     launch_pass_split_nb<2>(pv, ws, yhat, ref, track, st);
     launch_pass_split_nb<4>(pv, ws, yhat, ref, track, st);
     launch_pass_split_nb<8>(pv, ws, yhat, ref, track, st);
+    launch_pass_split_nb<16>(pv, ws, yhat, ref, track, st);
   };
   for (int step = 0; step < refine; ++step) {
     pass(true, step > 0);

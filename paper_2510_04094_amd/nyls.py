@@ -13,7 +13,7 @@ import torch
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnyls.so")
 MAX_P = 4
-MAX_M = 128
+MAX_M = 256
 MAX_N = 1 << 25
 
 FP64, MIXED, FP64_EXPLICIT = 0, 1, 2

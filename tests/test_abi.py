@@ -61,7 +61,7 @@ def create(pr, batch=1, mode=0):
 
 @pytest.mark.parametrize("kw,code", [
     (dict(p=0), -4), (dict(p=5), -4),
-    (dict(n=1), -5), (dict(m=1), -5), (dict(m=101), -5), (dict(n=200, m=129), -5),
+    (dict(n=1), -5), (dict(m=1), -5), (dict(m=101), -5), (dict(n=300, m=257), -5),
     (dict(sigma=0.0), -6), (dict(gamma=-1.0), -6), (dict(tau=1.0), -6), (dict(sigma=float("nan")), -6),
     (dict(dt=0.0), -7), (dict(uniform=0), -7),
     (dict(v=None), -1),
@@ -70,6 +70,13 @@ def create(pr, batch=1, mode=0):
 ])
 def test_invalid_problems_are_rejected_on_the_host(kw, code):
     assert create(problem(**kw)) == code
+
+
+def test_wide_bases_only_in_fp64_mode():
+    """Bases above 128 landmarks are taken by NYLS_FP64 plans only (mixed mode stops at 126)."""
+    assert create(problem(n=300, m=127), mode=1) == -5
+    assert create(problem(n=300, m=129), mode=1) == -5
+    assert create(problem(n=300, m=129), mode=2) == -5
 
 
 def test_invalid_landmarks_are_rejected():

@@ -7,8 +7,8 @@ from paper_2510_04094_amd import autotune, nyls
 
 
 def test_m_bucket_follows_the_slot_classes():
-    assert [autotune.m_bucket(m) for m in (2, 32, 33, 64, 65, 128)] == \
-        ["m<=32", "m<=32", "m<=64", "m<=64", "m<=128", "m<=128"]
+    assert [autotune.m_bucket(m) for m in (2, 32, 33, 64, 65, 128, 129, 256)] == \
+        ["m<=32", "m<=32", "m<=64", "m<=64", "m<=128", "m<=128", "m<=256", "m<=256"]
 
 
 def test_key_names_arch_bucket_orders_and_mode():

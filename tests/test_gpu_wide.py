@@ -1,0 +1,154 @@
+"""Bases wider than 128 landmarks (up to 256): the long-time runs of Sec. 4 use m = 200 on
+[0, 100] with n = 5e4.  Such instances are always split over point chunks; their passes run
+two wavefronts per chunk (one per half of the landmark slots), and K_mm and the KKT matrix
+are factored in the workspace.  GPU against the oracle for the solve, the feature map, the
+prediction and the adjoint, alone and in batches with narrow instances."""
+import numpy as np
+import pytest
+import torch
+
+import fp64_floor
+import oracle
+from paper_2510_04094_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _bad(gpu_lib):
+    return gpu_lib.S_SINGULAR | gpu_lib.S_NONFINITE | gpu_lib.S_REFINE_NOCONV | gpu_lib.S_EIG_NOCONV
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _solve(gpu_lib, insts, **kw):
+    b = gpu_lib.Batch(insts, mode=gpu_lib.FP64, **kw)
+    out = b.solve()
+    torch.cuda.synchronize()
+    y = out["yhat"].cpu().numpy()
+    return b, out, [y[b.goff[i]:b.goff[i + 1]] for i in range(len(insts))]
+
+
+WIDE = [
+    # (family, seed, n, m, t_end, sigma, tau): the paper's long-time shape (n = 5e4, m = 200
+    # on [0, 100], sigma^2 = 1), the largest basis, an uneven second wavefront, the smallest
+    # wide basis
+    ("second", 0, 50000, 200, 100.0, 1.0, 1e-8),
+    ("first", 1, 50000, 200, 100.0, 1.0, 1e-10),
+    ("second", 2, 20000, 256, 50.0, 0.5, 1e-8),
+    ("first", 3, 10000, 150, 20.0, 0.3, 1e-10),
+    ("second", 4, 3000, 129, 10.0, 0.4, 1e-8),
+]
+
+
+def wide_instance(family, seed, n, m, t_end, sigma, tau, obs=0):
+    if family == "first":
+        return workloads.linear_first_order(seed, n=n, m=m, t_end=t_end, sigma=sigma, tau=tau)
+    return workloads.linear_second_order(seed, n=n, m=m, t_end=t_end, sigma=sigma, tau=tau, obs=obs)
+
+
+@pytest.mark.parametrize("case", WIDE, ids=["%s-n%d-m%d" % (c[0], c[2], c[3]) for c in WIDE])
+def test_wide_basis_solve_at_the_fp64_bar(gpu_lib, case):
+    q = wide_instance(*case)
+    ref = oracle.linear.solve(q)
+    b, out, ys = _solve(gpu_lib, [q])
+    err, bar = _rel(ys[0], ref["yhat"]), fp64_floor.bar(q, ref["yhat"])
+    assert err <= bar, (err, bar)
+    assert int(out["status"].cpu().numpy()[0]) & _bad(gpu_lib) == 0
+    info = b.info().cpu().numpy()
+    assert int(info[0, 0]) == ref["r"]
+    assert 1 <= info[0, 5] <= 4
+
+
+@pytest.mark.parametrize("split", [512, 2048])
+def test_wide_basis_with_explicit_chunk_sizes(gpu_lib, split):
+    q = wide_instance("second", 5, 12000, 180, 30.0, 0.6, 1e-8)
+    ref = oracle.linear.solve(q)["yhat"]
+    _, _, ys = _solve(gpu_lib, [q], tuning=dict(split=split))
+    assert _rel(ys[0], ref) <= fp64_floor.bar(q, ref)
+
+
+def test_wide_basis_on_an_explicit_grid(gpu_lib):
+    """Explicit grids take the exact-exponential passes of both wavefronts."""
+    q = wide_instance("first", 6, 6000, 160, 10.0, 0.25, 1e-10)
+    ref = oracle.linear.solve(q)["yhat"]
+    _, _, ys = _solve(gpu_lib, [q], explicit_grid=True)
+    assert _rel(ys[0], ref) <= fp64_floor.bar(q, ref)
+
+
+def test_batch_of_wide_and_narrow_bases(gpu_lib):
+    """Wide instances beside one-wave ones (split and unsplit) in one plan, orders 1 to 3."""
+    insts = [wide_instance("second", 7, 20000, 200, 40.0, 0.7, 1e-8),
+             workloads.linear_second_order(8, n=9000, m=50),
+             wide_instance("first", 9, 8000, 140, 10.0, 0.2, 1e-10),
+             workloads.linear_first_order(10, n=3000, m=20),
+             workloads.linear_order_p(11, 3, n=6000, m=100, sigma=0.2, tau=1e-8)]
+    _, out, ys = _solve(gpu_lib, insts)
+    st = out["status"].cpu().numpy()
+    for i, q in enumerate(insts):
+        ref = oracle.linear.solve(q)["yhat"]
+        bar = fp64_floor.bar(q, ref)
+        assert _rel(ys[i], ref) <= bar, (i, _rel(ys[i], ref), bar)
+        assert int(st[i]) & _bad(gpu_lib) == 0, i
+
+
+def test_wide_basis_features_and_eigenvalues(gpu_lib):
+    """Eigenvalues at 1e-13 lambda_1 and the sign-free feature Gram phi(s)^T phi(t) (the
+    Nystrom kernel) against the oracle's basis."""
+    q = wide_instance("second", 12, 8000, 220, 20.0, 0.5, 1e-10)
+    b = gpu_lib.Batch([q], mode=gpu_lib.FP64)
+    times = [np.sort(np.random.default_rng(1).uniform(q["t"][0], q["t"][-1], 41))]
+    phi, eig, rank, off = b.features(times, dmax=2)
+    torch.cuda.synchronize()
+    phi, eig, rank = phi.cpu().numpy(), eig.cpu().numpy(), rank.cpu().numpy()
+    tl = q["t"][oracle.nystrom.landmark_indices(q)]
+    lam, u, r, w = oracle.nystrom.basis(tl, q["sigma"], q["tau"])
+    assert rank[0] == r
+    np.testing.assert_allclose(eig[0, :q["m"]], lam, rtol=0, atol=1e-13 * lam[0])
+    for d in range(3):
+        ref = oracle.nystrom.features(d, times[0], tl, q["sigma"], w)
+        got = phi[:, d, :r]
+        gk, rk = got @ got.T, ref @ ref.T
+        assert np.max(np.abs(gk - rk)) <= 1e-9 * np.max(np.abs(rk)), d
+        assert np.all(phi[:, d, r:] == 0)
+
+
+def test_wide_basis_predict_and_adjoint_match_oracle(gpu_lib):
+    """y_hat at the observation times and the adjoint gradients of a wide instance (its
+    passes over chunks with two wavefronts) with the bars of the split adjoint test."""
+    from test_gpu_adjoint import loss_grad_obs, rel
+    q = workloads.linear_second_order(13, n=20000, m=200, t_end=40.0, sigma=0.7, tau=1e-8, obs=100, config=5)
+    b = gpu_lib.Batch([q], mode=gpu_lib.FP64)
+    b.solve()
+    yo, _ = b.predict([q["t_obs"]], 0)
+    yo = yo.cpu().numpy()
+    ref_sol = oracle.linear.solve(q)
+    ref_y = oracle.linear.predict(ref_sol, q["t_obs"], q["sigma"], 0)
+    assert _rel(yo, ref_y) <= fp64_floor.bar(q, ref_sol["yhat"])
+    g = [loss_grad_obs(yo, q["y_obs"])]
+    out = b.backward([q["t_obs"]], g)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    ref = oracle.adjoint.grad(q, q["t_obs"], g[0])
+    for k in range(q["p"]):
+        gf, rf = out["dl_df"][k], ref["dl_df"][k]
+        assert np.max(np.abs(gf - rf)) <= 1e-5 * np.max(np.abs(rf)), ("df", k)
+    assert np.max(np.abs(out["dl_dr"] - ref["dl_dr"])) <= 1e-5 * np.max(np.abs(ref["dl_dr"]))
+    for j in range(q["p"]):
+        assert rel(out["dl_dv"][0, j], ref["dl_dv"][j]) <= 1e-5, ("dv", j)
+    scale = 1e-5 * abs(ref["dl_dsigma"]) + 1e-8 * np.max(np.abs(ref["sigma_terms"]))
+    assert abs(out["dl_dsigma"][0] - ref["dl_dsigma"]) <= scale
+    assert rel(out["dl_dgamma"][0], ref["dl_dgamma"]) <= 1e-5
+
+
+def test_wide_bases_are_refused_where_not_supported(gpu_lib):
+    """Mixed mode and the Newton and leverage calls stop at 128 landmarks (size error)."""
+    q = wide_instance("first", 14, 3000, 140, 5.0, 0.2, 1e-10)
+    with pytest.raises(gpu_lib.NylsError):
+        gpu_lib.Batch([q], mode=gpu_lib.MIXED)
+    b = gpu_lib.Batch([q], mode=gpu_lib.FP64)
+    with pytest.raises(gpu_lib.NylsError):
+        b.leverage_scores()
+    with pytest.raises(gpu_lib.NylsError):
+        b.newton_init()
