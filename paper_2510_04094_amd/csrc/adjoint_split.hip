@@ -455,8 +455,60 @@ __global__ __launch_bounds__(64 * G) void k_bws_grad_pass(const nyls_desc* __res
   if (lane == 0 && lead) part[2 * m] = t2;
 }
 
+// C(i, j) = sum_k A(i, k) B(k, j), i < M, j < N, for the 256 threads of a workgroup: 64 x 64
+// output tiles (4 x 4 per thread) over k-chunks of 16, both operands staged through LDS
+// (ab: 2 * 16 * 65 doubles).  a(i, k) and b(k, j) read the operands; A_KFAST says that
+// consecutive k of a row of A are adjacent in memory (else consecutive i are), which decides
+// the order the tile is loaded in (B is read with consecutive j adjacent).  out(i, j, v)
+// receives each result once.
+template <bool A_KFAST, class FA, class FB, class FO>
+__device__ inline void block_gemm(int M, int N, int K, FA a, FB b, FO out, double* ab) {
+  constexpr int TS = 65;  // LDS row stride
+  double* As = ab;           // [16][TS]: As[k][i]
+  double* Bs = ab + 16 * TS;  // [16][TS]: Bs[k][j]
+  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  for (int i0 = 0; i0 < M; i0 += 64)
+    for (int j0 = 0; j0 < N; j0 += 64) {
+      double acc[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+      for (int k0 = 0; k0 < K; k0 += 16) {
+        __syncthreads();
+        for (int e = tid; e < 16 * 64; e += NYLS_BLOCK) {
+          const int ia = A_KFAST ? e >> 4 : e & 63, ka = A_KFAST ? e & 15 : e >> 6;
+          As[ka * TS + ia] = (i0 + ia < M && k0 + ka < K) ? a(i0 + ia, k0 + ka) : 0.0;
+          const int jb = e & 63, kb = e >> 6;
+          Bs[kb * TS + jb] = (j0 + jb < N && k0 + kb < K) ? b(k0 + kb, j0 + jb) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            av[u] = As[kk * TS + 4 * ti + u];
+            bv[u] = Bs[kk * TS + 4 * tj + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + 4 * ti + u, j = j0 + 4 * tj + v;
+          if (i < M && j < N) out(i, j, acc[u][v]);
+        }
+    }
+}
+
 // The sigma terms through the conditions and K_mm, dl/dgamma and dl/dv, as in k_backward;
-// 256 threads, for the m^3 products of the K_mm term.
+// 256 threads, the m^3 products of the K_mm term as LDS-tiled products.
 template <int P>
 __global__ __launch_bounds__(NYLS_BLOCK) void k_bws_final(const nyls_desc* __restrict__ desc,
                                                   double* __restrict__ wsbase,
@@ -465,6 +517,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_bws_final(const nyls_desc* __res
                                                   double* __restrict__ dl_dgamma) {
   __shared__ double tl[NYLS_MAX_M], kb[NYLS_MAX_M], ae[NYLS_MAX_M], an[NYLS_MAX_M];
   __shared__ double ug1[NYLS_MAX_M], ug2[NYLS_MAX_M], xv[NK], mu[NK], red[16];
+  __shared__ double ab[2 * 16 * 65];
   const int inst = (int)blockIdx.x;
   const nyls_desc& d = desc[inst];
   if (!takes<P>(d)) return;
@@ -551,24 +604,20 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_bws_final(const nyls_desc* __res
     const double z = (tl[a] - tl[s]) * inv_sigma;
     dK[e] = (2.0 * z * z * inv_sigma) * exp(-z * z);
   }
+  block_gemm<true>(
+      m, r, m, [&](int a, int s) { return dK[a * m + s]; }, [&](int s, int l) { return U[s * m + l]; },
+      [&](int a, int l, double v) { E[a * m + l] = v; }, ab);
   __syncthreads();
-  for (int e = tid; e < m * r; e += NT) {
-    const int a = e / r, l = e - a * r;
-    double acc = 0.0;
-    for (int s = 0; s < m; ++s) acc += dK[a * m + s] * U[s * m + l];
-    E[a * m + l] = acc;
-  }
-  __syncthreads();
-  double tk = 0.0;
-  for (int e = tid; e < m * r; e += NT) {
-    const int k = e / r, l = e - k * r;
-    double dkl = 0.0;
-    for (int a = 0; a < m; ++a) dkl += U[a * m + k] * E[a * m + l];
-    const double ll = lamv[l], lk = lamv[k];
-    const double qb = 0.5 * sqrt(ll) * (ug1[k] * xv[l] - ug2[k] * mu[l]);
-    const double fkl = (k < r) ? -1.0 / (lk * ll) : 1.0 / (ll * (ll - lk));
-    tk += (k < r ? 1.0 : 2.0) * fkl * qb * dkl;
-  }
+  double tk = 0.0;  // sum over (k, l) of the weight times (U^T dK U)[k][l]
+  block_gemm<false>(
+      m, r, m, [&](int k, int a) { return U[a * m + k]; }, [&](int a, int l) { return E[a * m + l]; },
+      [&](int k, int l, double dkl) {
+        const double ll = lamv[l], lk = lamv[k];
+        const double qb = 0.5 * sqrt(ll) * (ug1[k] * xv[l] - ug2[k] * mu[l]);
+        const double fkl = (k < r) ? -1.0 / (lk * ll) : 1.0 / (ll * (ll - lk));
+        tk += (k < r ? 1.0 : 2.0) * fkl * qb * dkl;
+      },
+      ab);
   tk = nyls_block_sum(tk, red);
   double mw = 0.0;
   for (int k = tid; k < r; k += NT) mw += mu[k] * xv[k];

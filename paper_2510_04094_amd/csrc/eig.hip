@@ -358,8 +358,7 @@ __global__ __launch_bounds__(64) void k_eig_ql(const nyls_desc* __restrict__ des
 // those of step 3 of k_eig_ql; the plane rotations are logged to the instance's workspace
 // (its rotation-log region) for the replay on Q.  An instance whose log
 // would overflow is marked (info[7] = 2) and redone by k_eig_ql(QL_REDO).
-// Takes the instances with LO < m <= MAXM, at most LN per wavefront (LN = 64 for m <= 128;
-// the wide bases, with their larger d and e, use LN = 16 to stay within the LDS).
+// Takes the instances with LO < m <= MAXM, at most LN per wavefront.
 template <int MAXM, int LO = MAXM - kQlMaxM, int LN = 64>
 __global__ __launch_bounds__(64) void k_ql_lanes(const nyls_desc* __restrict__ desc,
                                                  double* __restrict__ wsbase, int batch, int ipw) {
@@ -816,20 +815,56 @@ __global__ __launch_bounds__(64) void k_eig_ql2(const nyls_desc* __restrict__ de
   }
 }
 
-// ---- wide bases (NYLS_NARROW_MAX_M < m <= NYLS_MAX_M): 256 threads, K_mm in the workspace ----
+// ---- wide bases (NYLS_NARROW_MAX_M < m <= NYLS_MAX_M): K_mm in the workspace ----
 //
 // The matrix no longer fits in LDS, so the steps of k_eig_ql run on the instance's U block
 // (L2-resident), thread j owning column j: K_mm and every trailing block stay exactly
 // symmetric (the rank-2 update adds its two products in an order-independent way), so
-// column j is also row j, and every step reads and writes with coalesced accesses.
-//  1. Householder reduction as in step 1 of k_eig_ql, reflector k kept in row k;
+// column j is also row j, and every step reads and writes with coalesced accesses.  The
+// column loops load eight entries before they store any (the loads of one thread would
+// otherwise wait behind its own stores, one L2 round trip per entry).
+//  1. (k_eig_wide, WIDE_REDUCE) Householder reduction as in step 1 of k_eig_ql, reflector k
+//     kept in row k;
 //  2. Q = H_0 ... H_{m-3} formed in place, then stored transposed in the T scratch
-//     (ZT[c m + i] = Z[i][c]), where each row of Z is a coalesced stripe;
-//  3. (k_ql_lanes) implicit QL on (d, e), one lane per instance, logging the rotations;
-//  4. replay: thread i applies the logged rotations to row i of Z (rows are independent,
-//     no synchronisation), then the ordering, signs, cut-off and W of step 4 of k_eig_ql.
+//     (ZT[c m + i] = Z[i][c]);
+//  3. (k_ql_wide) implicit QL on (d, e), one wavefront per instance carrying the chain,
+//     logging the rotations;
+//  4. (k_eig_wide_replay) the logged rotations applied to the rows of Z: rows are
+//     independent, so four workgroups per instance each hold 64 rows in LDS (one per lane);
+//  5. (k_eig_wide, WIDE_FINISH) the ordering, signs, cut-off and W of step 4 of k_eig_ql.
 // A rotation log that overflowed (more than 2 m^2 rotations) leaves NYLS_S_EIG_NOCONV set.
-enum { WIDE_REDUCE = 0, WIDE_REPLAY = 1 };
+enum { WIDE_REDUCE = 0, WIDE_FINISH = 1 };
+constexpr int kWideRows = 64;  // rows of Z per replay workgroup
+
+// A[c m + j] -= u[c] * a + w[c] * b for c in [c0, m) (thread-owned column j), eight loads
+// issued before the stores.
+template <class F>
+__device__ inline void wide_col_update(double* A, int m, int j, int c0, F delta) {
+  int c = c0;
+  for (; c + 8 <= m; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = A[(c + u) * m + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) A[(c + u) * m + j] = v[u] - delta(c + u);
+  }
+  for (; c < m; ++c) A[c * m + j] -= delta(c);
+}
+
+// sum over c in [c0, m) of A[c m + j] * x[c] (x in LDS)
+__device__ inline double wide_col_dot(const double* A, int m, int j, int c0, const double* x) {
+  double acc = 0.0;
+  int c = c0;
+  for (; c + 8 <= m; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = A[(c + u) * m + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u] * x[c + u];
+  }
+  for (; c < m; ++c) acc += A[c * m + j] * x[c];
+  return acc;
+}
 
 __global__ __launch_bounds__(NYLS_BLOCK) void k_eig_wide(const nyls_desc* __restrict__ desc,
                                                          double* __restrict__ wsbase, int stage) {
@@ -878,18 +913,15 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig_wide(const nyls_desc* __rest
       }
       if (own) vv[j] = v;
       __syncthreads();
-      double pj = 0.0;  // p = beta B v (column j of B is row j)
-      if (act) {
-        for (int c = k + 1; c < m; ++c) pj += A[c * m + j] * vv[c];
-        pj *= beta;
-      }
+      // p = beta B v (column j of B is row j)
+      const double pj = act ? beta * wide_col_dot(A, m, j, k + 1, vv) : 0.0;
       const double K = 0.5 * beta * nyls_block_sum(v * pj, red);
       const double w = pj - K * v;
       if (own) ww[j] = w;
       __syncthreads();
       if (act) {
-        for (int c = k + 1; c < m; ++c)
-          A[c * m + j] -= __dadd_rn(__dmul_rn(vv[c], w), __dmul_rn(ww[c], v));
+        wide_col_update(A, m, j, k + 1,
+                        [&](int c) { return __dadd_rn(__dmul_rn(vv[c], w), __dmul_rn(ww[c], v)); });
         A[k * m + j] = v;  // reflector k
       }
       __syncthreads();
@@ -912,10 +944,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig_wide(const nyls_desc* __rest
       __syncthreads();
       const double beta = bt[k];
       if (act && beta != 0.0) {
-        double t = 0.0;  // (v^T Q)_j over the trailing rows
-        for (int i = k + 1; i < m; ++i) t += vv[i] * A[i * m + j];
-        t *= beta;
-        for (int i = k + 1; i < m; ++i) A[i * m + j] -= vv[i] * t;
+        const double t = beta * wide_col_dot(A, m, j, k + 1, vv);  // (v^T Q)_j
+        wide_col_update(A, m, j, k + 1, [&](int i) { return vv[i] * t; });
       }
       if (own && j >= k) A[k * m + j] = j == k ? 1.0 : 0.0;  // row k = e_k
       if (j == k)
@@ -930,29 +960,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig_wide(const nyls_desc* __rest
     return;
   }
 
-  // 4. replay of the logged sweeps (each: header (mm, k) and k rotations (c, s) for
-  //    columns mm - 1, mm - 2, ...), thread j carrying row j of Z
+  // 5. ordering, signs, cut-off, W and U
   const int flag = (int)ws[L.info + 7];
-  if (flag != 2 && own) {
-    const double* lg = ws + L.log;
-    const int nsw = (int)ws[L.info + 6];
-    int hdr = 0;
-    for (int sw = 0; sw < nsw; ++sw) {
-      const int mm = (int)lg[2 * hdr], nrot = (int)lg[2 * hdr + 1];
-      double c0 = ZT[mm * m + j];
-      double z0 = nrot > 0 ? ZT[(mm - 1) * m + j] : 0.0;
-      for (int k = 0; k < nrot; ++k) {
-        const int i = mm - 1 - k;
-        const double cs = lg[2 * (hdr + 1 + k)], sn = lg[2 * (hdr + 1 + k) + 1];
-        const double zn = (k + 1 < nrot) ? ZT[(i - 1) * m + j] : 0.0;  // unchanged by this rotation
-        ZT[(i + 1) * m + j] = sn * z0 + cs * c0;
-        c0 = cs * z0 - sn * c0;
-        z0 = zn;
-      }
-      ZT[(mm - nrot) * m + j] = c0;
-      hdr += 1 + nrot;
-    }
-  }
   const double dj = own ? ws[L.lam + j] : 0.0;
   if (own) dd[j] = dj;
   __syncthreads();
@@ -1003,6 +1012,203 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig_wide(const nyls_desc* __rest
   }
 }
 
+// 3. implicit QL on (d, e) of a wide basis, logging the rotations as k_ql_lanes does (same
+// shift, chase, split test and log format), one wavefront per instance with every lane
+// carrying the (wave-uniform) scalar chain: d and e sit in LDS, lane 0 writes the updated
+// entries and the log, and the first negligible off-diagonal of a new sweep is found with
+// one ballot per 64 entries.  Uniform control flow keeps the chain free of the exec-mask
+// bookkeeping of the lane-per-instance kernel, whose single active lane would carry it here.
+__global__ __launch_bounds__(64) void k_ql_wide(const nyls_desc* __restrict__ desc,
+                                                double* __restrict__ wsbase) {
+  __shared__ double dv[NYLS_MAX_M], ev[NYLS_MAX_M];
+  const nyls_desc& d = desc[blockIdx.x];
+  const int m = d.m;
+  if (m <= NYLS_NARROW_MAX_M) return;
+  const nyls_wsl L = nyls_layout(m, d.p, 0);
+  double* ws = wsbase + d.ws;
+  const int lane = threadIdx.x;
+  for (int k = lane; k < m; k += 64) {
+    dv[k] = ws[L.lam + k];
+    ev[k] = ws[L.W + k];
+  }
+  nyls_wave_lds_sync();
+  double* lg = ws + L.log;
+  const int cap = (int)((L.aux - L.log) / 2);
+  const double eps = 2.220446049250313e-16;
+  int iters = 0, pos = 0, nsw = 0;
+  bool converged = true, overflow = false;
+  for (int l = 0; l < m && !overflow; ++l) {
+    int it = 0;
+    for (;;) {
+      // first index mm >= l with a negligible e_mm (m - 1 counts as one)
+      int mm = m - 1;
+      for (int b0 = l; b0 < m - 1; b0 += 64) {
+        const int ix = b0 + lane;
+        const bool t = ix < m - 1 && fabs(ev[ix]) <= eps * (fabs(dv[ix]) + fabs(dv[ix + 1]));
+        const unsigned long long mk = __ballot(t);
+        if (mk) {
+          mm = b0 + __ffsll((long long)mk) - 1;
+          break;
+        }
+      }
+      if (mm == l) break;
+      if (++it > kQlMaxIter) { converged = false; break; }
+      if (pos + 1 + (mm - l) > cap) { overflow = true; break; }
+      ++iters;
+      const double dL = dv[l], eL = ev[l];
+      double g = (dv[l + 1] - dL) / (2.0 * eL);
+      double r = sqrt(g * g + 1.0);
+      g = dv[mm] - dL + eL / (g + (g >= 0.0 ? r : -r));
+      double sn = 1.0, cs = 1.0, pp = 0.0;
+      const int hdr = pos++;
+      int nrot = 0;
+      bool split = false;
+      double ei = ev[mm - 1], di = dv[mm - 1], di1 = dv[mm];
+      // the rotations in blocks of eight, the block's entries i - 1 .. i - 8 (not rewritten
+      // by this sweep before their rotation) read together
+      for (int i = mm - 1; i >= l && !split;) {
+        double eb[8], db[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int ix = max(i - 1 - q, 0);  // (unused below index 0)
+          eb[q] = ev[ix];
+          db[q] = dv[ix];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q, --i) {
+          if (i < l) break;
+          const double f = sn * ei, b = cs * ei;
+          const double x = f * f + g * g;
+          if (x == 0.0) {  // exact deflation: the chase stops here
+            if (lane == 0) {
+              ev[i + 1] = 0.0;
+              dv[i + 1] = di1 - pp;
+              ev[mm] = 0.0;
+            }
+            split = true;
+            break;
+          }
+          const double y = nyls_rsqrt(x);
+          sn = f * y;
+          cs = g * y;
+          g = di1 - pp;
+          r = (di - g) * sn + 2.0 * cs * b;
+          pp = sn * r;
+          if (lane == 0) {
+            ev[i + 1] = x * y;
+            dv[i + 1] = g + pp;
+            lg[2 * pos] = cs;
+            lg[2 * pos + 1] = sn;
+          }
+          g = cs * r - b;
+          ++pos;
+          ++nrot;
+          di1 = di;
+          di = db[q];
+          ei = eb[q];
+        }
+      }
+      if (lane == 0) {
+        lg[2 * hdr] = (double)mm;
+        lg[2 * hdr + 1] = (double)nrot;
+        if (!split) {
+          dv[l] -= pp;
+          ev[l] = g;
+          ev[mm] = 0.0;
+        }
+      }
+      ++nsw;
+      nyls_wave_lds_sync();
+    }
+  }
+  for (int k = lane; k < m; k += 64) ws[L.lam + k] = dv[k];
+  if (lane == 0) {
+    ws[L.info + 2] = (double)iters;
+    ws[L.info + 6] = (double)nsw;
+    ws[L.info + 7] = overflow ? 2.0 : (converged ? 0.0 : 1.0);
+  }
+}
+
+// 4. replay: workgroup (instance, y) carries rows 64 y .. 64 y + 63 of Z, lane l row 64 y + l,
+// in LDS (Zs[c * 64 + l] = Z[64 y + l][c]).  The log (each sweep: header (mm, k) and k
+// rotations (c, s) for columns mm - 1, mm - 2, ...) is read in windows of 64 entries, one per
+// lane, the next window loaded while the current one is used; an entry comes to every lane
+// with a lane read.  Rotation i writes column i + 1 and reads column i, which no earlier
+// rotation of the sweep has rewritten, so the reads of eight rotations are issued together.
+// One wavefront per workgroup: no barriers.
+__global__ __launch_bounds__(64) void k_eig_wide_replay(const nyls_desc* __restrict__ desc,
+                                                        double* __restrict__ wsbase) {
+  extern __shared__ double sm[];
+  const nyls_desc& d = desc[blockIdx.x];
+  const int m = d.m;
+  if (m <= NYLS_NARROW_MAX_M) return;
+  const int r0 = (int)blockIdx.y * kWideRows;
+  if (r0 >= m) return;
+  const nyls_wsl L = nyls_layout(m, d.p, 0);
+  double* ws = wsbase + d.ws;
+  if ((int)ws[L.info + 7] == 2) return;  // log overflow: flagged in WIDE_FINISH
+  const int lane = threadIdx.x;
+  const int row = r0 + lane;
+  const bool own = row < m;
+  double* Zs = sm;  // [m][64]
+  double* ZT = ws + L.tmp;
+  for (int c = 0; c < m; ++c) Zs[c * kWideRows + lane] = own ? ZT[c * m + row] : 0.0;
+  const double* lg = ws + L.log;
+  const int cap = (int)((L.aux - L.log) / 2);
+  const int nsw = (int)ws[L.info + 6];
+  auto ld = [&](int e, double& a, double& b) {
+    a = e < cap ? lg[2 * e] : 0.0;
+    b = e < cap ? lg[2 * e + 1] : 0.0;
+  };
+  int wb = 0;  // first entry of the current window
+  double ca, cb, na, nb;
+  ld(lane, ca, cb);
+  ld(64 + lane, na, nb);
+  auto get = [&](int e, double& a, double& b) {  // e wave-uniform, never decreasing
+    while (e >= wb + 64) {
+      ca = na;
+      cb = nb;
+      wb += 64;
+      ld(wb + 64 + lane, na, nb);
+    }
+    a = nyls_rdlane(ca, e - wb);
+    b = nyls_rdlane(cb, e - wb);
+  };
+  int hdr = 0;
+  for (int sw = 0; sw < nsw; ++sw) {
+    double hm, hn;
+    get(hdr, hm, hn);
+    const int mm = (int)hm, nrot = (int)hn;
+    double c0 = Zs[mm * kWideRows + lane];
+    int k = 0;
+    // blocks of eight rotations: their eight Z entries (columns mm - 1 - k .. mm - 8 - k, not
+    // yet rewritten in this sweep) are loaded together before the block's stores
+    for (; k + 8 <= nrot; k += 8) {
+      double zb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) zb[u] = Zs[(mm - 1 - k - u) * kWideRows + lane];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        double cs, sn;
+        get(hdr + 1 + k + u, cs, sn);
+        Zs[(mm - k - u) * kWideRows + lane] = sn * zb[u] + cs * c0;
+        c0 = cs * zb[u] - sn * c0;
+      }
+    }
+    for (; k < nrot; ++k) {
+      double cs, sn;
+      get(hdr + 1 + k, cs, sn);
+      const double z0 = Zs[(mm - 1 - k) * kWideRows + lane];
+      Zs[(mm - k) * kWideRows + lane] = sn * z0 + cs * c0;
+      c0 = cs * z0 - sn * c0;
+    }
+    Zs[(mm - nrot) * kWideRows + lane] = c0;
+    hdr += 1 + nrot;
+  }
+  if (own)
+    for (int c = 0; c < m; ++c) ZT[c * m + row] = Zs[c * kWideRows + lane];
+}
+
 }  // namespace
 
 hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hipStream_t st) {
@@ -1030,11 +1236,14 @@ hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hip
     }
   }
   if (pv.nb_mask & (1u << 16)) {  // wide bases (never in single-instance launches)
-    constexpr int ipw = 8;
     hipLaunchKernelGGL(k_eig_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, (int)WIDE_REDUCE);
-    hipLaunchKernelGGL((k_ql_lanes<NYLS_MAX_M, NYLS_NARROW_MAX_M, ipw>), dim3((pv.batch + ipw - 1) / ipw),
-                       dim3(64), 0, st, pv.d_desc, ws, pv.batch, ipw);
-    hipLaunchKernelGGL(k_eig_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, (int)WIDE_REPLAY);
+    hipLaunchKernelGGL(k_ql_wide, dim3(pv.batch), dim3(64), 0, st, pv.d_desc, ws);
+    const size_t lds = (size_t)pv.maxm * kWideRows * sizeof(double);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_wide_replay),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_eig_wide_replay, dim3(pv.batch, (pv.maxm + kWideRows - 1) / kWideRows), dim3(64),
+                       lds, st, pv.d_desc, ws);
+    hipLaunchKernelGGL(k_eig_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, (int)WIDE_FINISH);
   }
   if (!(pv.nb_mask & 256)) return hipGetLastError();
   // 64 < m <= 128: one wavefront per instance, two rows per lane.  With many such instances

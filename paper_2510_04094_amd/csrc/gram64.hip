@@ -232,22 +232,27 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
 
 // Gram of a split instance: the sum of its chunk partials in chunk order (a fixed order,
 // so the result does not depend on which workgroup finished first), and the basis it is in.
+// Grid (instance, tiles of 256 Gram entries), one entry per thread.
 __global__ __launch_bounds__(NYLS_BLOCK) void k_gram_split_sum(const nyls_desc* __restrict__ desc,
                                                                double* __restrict__ wsbase) {
   const nyls_desc& d = desc[blockIdx.x];
   if (!(d.flags & NYLS_DF_SPLIT)) return;
   const int m = d.m, g = m + 2;
+  const int e = (int)blockIdx.y * NYLS_BLOCK + (int)threadIdx.x;
+  if ((int)blockIdx.y * NYLS_BLOCK >= g * g) return;
   const nyls_wsl L = nyls_layout(m, d.p, 0);
   double* ws = wsbase + d.ws;
   const double* part = wsbase + d.part;
-  const int rank = (int)ws[L.info + 0];
-  const bool rotate = rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam];
-  for (int e = threadIdx.x; e < g * g; e += NYLS_BLOCK) {
+  if (e < g * g) {
     double acc = 0.0;
     for (int c = 0; c < d.nchunks; ++c) acc += part[nyls_split_gram(m, c) + e];
     ws[L.gram + e] = acc;
   }
-  if (threadIdx.x == 0) ws[L.info + 4] = rotate ? 1.0 : 0.0;
+  if (e == 0) {
+    const int rank = (int)ws[L.info + 0];
+    const bool rotate = rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam];
+    ws[L.info + 4] = rotate ? 1.0 : 0.0;
+  }
 }
 
 
@@ -661,7 +666,9 @@ hipError_t nyls_launch_gram64_rest(const nyls_plan_view& pv, double* ws, hipStre
   launch_vg<64>(pv, ws, st, 0, pv.only);
   if (pv.n_split && !pv.only) {
     launch_split_parts(pv, ws, st, 2);
-    hipLaunchKernelGGL(k_gram_split_sum, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws);
+    const int g = pv.maxm + 2;
+    hipLaunchKernelGGL(k_gram_split_sum, dim3(pv.batch, (g * g + NYLS_BLOCK - 1) / NYLS_BLOCK),
+                       dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws);
   }
   return hipGetLastError();
 }

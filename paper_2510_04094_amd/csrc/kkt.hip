@@ -76,6 +76,77 @@ __device__ inline void kkt_transform_mfma(const double* __restrict__ S, const do
   }
 }
 
+// LU with partial pivoting of the N x N row-major matrix A in global memory (lda = N) by the
+// 256 threads of a workgroup, for the wide bases: thread j updates columns j, j + 256, ...
+// (coalesced across the threads), and each column loop issues eight loads before its stores.
+// The pivot is the first largest |entry| of the column, the multipliers are kept in LDS
+// (lcol, N doubles); pivots and arithmetic are those of nyls_lu.  redv / redi: four doubles
+// and four ints of LDS.
+__device__ inline int lu_global(double* A, int N, int* piv, double* lcol, double* redv, int* redi) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int singular = 0;
+  for (int k = 0; k < N; ++k) {
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < N; i += NYLS_BLOCK) {
+      const double a = fabs(A[i * N + k]);
+      if (a > best) { best = a; bi = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) {
+      redv[wave] = best;
+      redi[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double b = redv[0];
+      int ix = redi[0];
+      for (int w = 1; w < NYLS_BLOCK / 64; ++w)
+        if (redv[w] > b || (redv[w] == b && redi[w] < ix)) { b = redv[w]; ix = redi[w]; }
+      piv[k] = ix;
+    }
+    __syncthreads();
+    const int pr = piv[k];
+    if (pr != k)
+      for (int j = tid; j < N; j += NYLS_BLOCK) {
+        const double t = A[k * N + j];
+        A[k * N + j] = A[pr * N + j];
+        A[pr * N + j] = t;
+      }
+    __syncthreads();
+    const double pv = A[k * N + k];
+    if (pv == 0.0 || !(pv == pv)) {
+      singular = 1;
+      continue;
+    }
+    const double inv = 1.0 / pv;
+    for (int i = k + 1 + tid; i < N; i += NYLS_BLOCK) {
+      const double l = A[i * N + k] * inv;
+      A[i * N + k] = l;
+      lcol[i] = l;
+    }
+    __syncthreads();
+    for (int j = k + 1 + tid; j < N; j += NYLS_BLOCK) {
+      const double u = A[k * N + j];
+      int i = k + 1;
+      for (; i + 8 <= N; i += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = A[(i + q) * N + j];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) A[(i + q) * N + j] = v[q] - lcol[i + q] * u;
+      }
+      for (; i < N; ++i) A[i * N + j] -= lcol[i] * u;
+    }
+    __syncthreads();
+  }
+  return singular;
+}
+
 __device__ inline int instance_of(const int32_t* order) {
   return order ? order[blockIdx.x] : (int)blockIdx.x;
 }
@@ -277,11 +348,13 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
     __syncthreads();
     sing = (int)red[0];
     for (int e = tid; e < N * N; e += NYLS_BLOCK) ws[L.lu + e] = K[perm[e / N] * lda + e % N];
+  } else if (wide) {
+    sing = lu_global(K, N, piv, kc, red, perm);
+    nyls_lu_solve(K, lda, N, piv, rhs);
   } else {
     sing = nyls_lu(K, lda, N, piv, red);
     nyls_lu_solve(K, lda, N, piv, rhs);
-    if (!wide)
-      for (int e = tid; e < N * N; e += NYLS_BLOCK) ws[L.lu + e] = K[(e / N) * lda + e % N];
+    for (int e = tid; e < N * N; e += NYLS_BLOCK) ws[L.lu + e] = K[(e / N) * lda + e % N];
   }
   for (int a = tid; a < N; a += NYLS_BLOCK) {
     ws[L.piv + a] = (double)piv[a];
