@@ -126,7 +126,7 @@ struct nyls_walk {
 
   // s0: first landmark of the lane's slots (0, or 16 NB for the second wavefront of a wide
   // basis); slot b of the lane is landmark s0 + 16 b + sl.
-  __device__ void init(const nyls_desc& d, int lane, int s0 = 0) {
+  __device__ __attribute__((always_inline)) void init(const nyls_desc& d, int lane, int s0 = 0) {
     sl = lane & 15;
     ph = lane >> 4;
     n = d.n;
@@ -158,7 +158,7 @@ struct nyls_walk {
   // Must be called before chunk(i0) for every chunk, in increasing order from i0 = 0:
   // starts a new run of the recurrence every 64 points (and decides, wave-uniformly,
   // whether that run needs one exponential per value instead).
-  __device__ void advance(const nyls_desc& d, int i0) {
+  __device__ __attribute__((always_inline)) void advance(const nyls_desc& d, int i0) {
     if ((!EX || d.uniform) && (i0 & 63) == 0) {
       bool any = false;
       if (TL) {
@@ -200,7 +200,7 @@ struct nyls_walk {
   // With TL, blocks b < NB - 1 are emitted this way and tail(g, e) is called once for the
   // lane's tail pair (point i0 + tpt, landmark 16 (NB - 1) + tts).
   template <class Emit, class Done, class Tail>
-  __device__ void chunk(const nyls_desc& d, int i0, Emit emit, Done done, Tail tail) {
+  __device__ __attribute__((always_inline)) void chunk(const nyls_desc& d, int i0, Emit emit, Done done, Tail tail) {
     if (!EX || !exact) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -234,7 +234,7 @@ struct nyls_walk {
   }
 
   template <class Emit, class Done>
-  __device__ void chunk(const nyls_desc& d, int i0, Emit emit, Done done) {
+  __device__ __attribute__((always_inline)) void chunk(const nyls_desc& d, int i0, Emit emit, Done done) {
     static_assert(!TL, "the tail layout needs a tail callback");
     chunk(d, i0, emit, done, [](double, double) {});
   }
