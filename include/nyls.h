@@ -80,12 +80,16 @@ enum {
   NYLS_S_SINGULAR = 2,        /* a zero pivot in the KKT / Schur factorisation */
   NYLS_S_NONFINITE = 4,       /* a NaN or Inf appeared in the solution */
   NYLS_S_EIG_NOCONV = 8,      /* the eigensolver hit its iteration limit */
-  NYLS_S_SMALL_PIVOT = 16,    /* Newton: a diagonal y-block entry |d_i| < 1e-10 gamma */
+  NYLS_S_SMALL_PIVOT = 16,    /* Newton: a diagonal y-block entry |d_i| < 1e-10 gamma was met
+                                 (up to 32 such points per step stay in the dense system:
+                                 the step is exact; see NYLS_S_PIVOT_OVERFLOW) */
   NYLS_S_REFINE_NOCONV = 32,  /* refinement ended with its last change of y_hat above
                                  1e-8 max|y_hat| */
   NYLS_S_FP64_RESOLVED = 64,  /* NYLS_MIXED: refinement on the FP32 Gram did not converge, the
                                  instance was solved again with the FP64 Gram */
-  NYLS_S_PARAM_KEPT = 128     /* nyls_plan_set_params: the new sigma or gamma was not taken */
+  NYLS_S_PARAM_KEPT = 128,    /* nyls_plan_set_params: the new sigma or gamma was not taken */
+  NYLS_S_PIVOT_OVERFLOW = 256 /* Newton: more than 32 small pivots (or a non-finite one); the
+                                 others were divided out as usual */
 };
 
 /*
@@ -307,8 +311,10 @@ int nyls_newton_state(const nyls_plan* plan, const double* x, double* u, const v
  * The diagonal y-block d_i = gamma (1 + F_y^2 - rho_i F_yy) is eliminated first (Schur
  * complement on (omega, b, lambda)), so a step costs O(n m^2 + m^3); for p = 2 the whole
  * weighted Gram is formed again each step (the y' dependence makes every block depend on
- * the iterate).  |d_i| < 1e-10 gamma sets NYLS_S_SMALL_PIVOT.  Afterwards nyls_predict
- * evaluates the current y_hat. */
+ * the iterate).  |d_i| < 1e-10 gamma sets NYLS_S_SMALL_PIVOT; for p = 1 up to 32 such
+ * points per instance are not divided out but stay unknowns of the dense system, which is
+ * then solved by LU in the workspace (the step is the exact Newton step; more than 32 set
+ * NYLS_S_PIVOT_OVERFLOW).  Afterwards nyls_predict evaluates the current y_hat. */
 int nyls_newton_step(const nyls_plan* plan, const double* F, const double* dF,
                      const double* d2F, double* x, double* step_inf, int32_t* status,
                      void* ws, hipStream_t stream);

@@ -654,7 +654,8 @@ const char* nyls_error_string(int32_t code) {
     case NYLS_S_SINGULAR: return "zero pivot in the factorisation";
     case NYLS_S_NONFINITE: return "non-finite value in the solution";
     case NYLS_S_EIG_NOCONV: return "eigensolver hit its iteration limit";
-    case NYLS_S_SMALL_PIVOT: return "Newton diagonal block entry below 1e-10 gamma";
+    case NYLS_S_SMALL_PIVOT: return "Newton diagonal block entry below 1e-10 gamma (kept in the dense system)";
+    case NYLS_S_PIVOT_OVERFLOW: return "more than 32 small Newton pivots, or a non-finite one";
     case NYLS_S_REFINE_NOCONV: return "iterative refinement did not reach rounding level";
     case NYLS_S_FP64_RESOLVED: return "solved again with the FP64 Gram";
     case NYLS_S_PARAM_KEPT: return "new sigma or gamma not taken";

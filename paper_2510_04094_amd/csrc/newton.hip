@@ -15,6 +15,11 @@
 // Y_z - sum q_i Y4_i / d_i, then dy_i = (Y4_i - q_i^T dz) / d_i, and x <- x - dx.
 // The weighted sum over points is accumulated in kernel space as the Gram of
 // (kappa_i, 1, Y4_i / gamma) with weights gamma^2 / d_i, then mapped through W.
+// Points whose pivot is tiny (|d_i| < 1e-10 gamma; d_i can pass through zero at early
+// iterates) are not divided out: up to kKeep of them stay in the system as unknowns,
+//   [[J_zz - sum_good q q^T / d, Q_B], [Q_B^T, D_B]] [dz; dy_B] = [Y_z - sum_good q Y4 / d; Y4_B],
+// which is the same Newton step without the division, solved by dense LU in the
+// workspace.  More such points than kKeep set NYLS_S_PIVOT_OVERFLOW and are divided out.
 #include "nyls_dense.h"
 #include "nyls_gramacc.h"
 
@@ -36,6 +41,8 @@ namespace {
 
 constexpr int TP = 32;
 constexpr int CH = 8;  // points per thread in the Gaussian recurrence
+constexpr int kKeep = 32;  // small-pivot points kept in the dense system per step
+constexpr int kNz = NYLS_NARROW_MAX_M + 2 + kKeep;  // largest dense system
 
 __host__ __device__ inline int round4(int x) { return (x + 3) & ~3; }
 
@@ -136,10 +143,11 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_step(
   double* lin = dal + NYLS_NARROW_MAX_M;        // [128] sum rho k' - eta k
   double* part = lin + NYLS_NARROW_MAX_M;       // [256] partial sums
   double* red = part + NYLS_BLOCK;       // [16]
-  double* rhs = red + 16;                // [136]
-  double* pd = rhs + 136;                // [TP][8] per-point data
-  int* piv = reinterpret_cast<int*>(pd + TP * 8);  // [136]
-  double* big = reinterpret_cast<double*>(piv + 136);
+  double* rhs = red + 16;                // [kNz]
+  double* pd = rhs + kNz;                // [TP][8] per-point data
+  int* piv = reinterpret_cast<int*>(pd + TP * 8);  // [kNz]
+  int* keep = piv + kNz;                 // [kKeep + 1] kept points, then their count
+  double* big = reinterpret_cast<double*>(keep + kKeep + 2);
   // pass region
   double* K0 = big;                      // [TP][m]
   double* K1 = K0 + TP * maxm;           // [TP][m]
@@ -152,6 +160,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_step(
     for (int k = 0; k < r; ++k) acc += W[s * m + k] * xi[k];
     al[s] = acc;
   }
+  if (tid == 0) keep[kKeep] = 0;
   __syncthreads();
   const double b = xi[maxm], lam = xi[maxm + 1];
 
@@ -189,8 +198,17 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_step(
           eta = xi[maxm + 2 + i] - d0 - b;
           y4 = gam * (-rho * fy + eta);
           dd = gam * (1.0 + fy * fy - rho * Fyy[i]);
-          if (!(fabs(dd) >= 1e-10 * gam)) bad |= (dd == 0.0 || !(dd == dd)) ? 2 : 1;
           w = (dd != 0.0 && dd == dd) ? gam * gam / dd : 0.0;
+          if (!(fabs(dd) >= 1e-10 * gam)) {
+            bad |= 1;
+            const int slot = dd == dd ? atomicAdd(&keep[kKeep], 1) : kKeep;
+            if (slot < kKeep) {
+              keep[slot] = i;  // stays in the dense system (out of the weighted Gram)
+              w = 0.0;
+            } else {
+              bad |= 2;
+            }
+          }
           etasum += eta;
         }
         pd[pt * 8 + 0] = rho;
@@ -224,7 +242,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_step(
   nyls_gram::finish(A, Q, Sw, g, g);
   part[tid] = (cg < ngc) ? linacc : 0.0;
   const double esum = nyls_block_sum(etasum, red);
-  const double badf = nyls_block_sum((double)bad, red);
+  const double badf = nyls_block_sum((bad & 1) ? 1.0 : 0.0, red);  // small pivots met
+  const double ovff = nyls_block_sum((bad & 2) ? 1.0 : 0.0, red);  // ... beyond kKeep
   __syncthreads();
   for (int s = tid; s < m; s += NYLS_BLOCK) {
     double acc = 0.0;
@@ -297,8 +316,70 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_step(
     rhs[a] = val;
   }
   __syncthreads();
-  const int sing = nyls_lu(Z, lz, N2, piv, red);
-  nyls_lu_solve(Z, lz, N2, piv, rhs);   // rhs <- dz
+  const int nkeep = min(keep[kKeep], kKeep);
+  int sing;
+  if (nkeep == 0) {
+    sing = nyls_lu(Z, lz, N2, piv, red);
+    nyls_lu_solve(Z, lz, N2, piv, rhs);   // rhs <- dz
+  } else {
+    // the kept points in index order (their slots were taken in arbitrary order)
+    if (tid == 0)
+      for (int a = 1; a < nkeep; ++a) {
+        const int v = keep[a];
+        int c = a - 1;
+        for (; c >= 0 && keep[c] > v; --c) keep[c + 1] = keep[c];
+        keep[c + 1] = v;
+      }
+    __syncthreads();
+    // [[Z, Q_B], [Q_B^T, D_B]] in the workspace, Q_B = -gamma (W^T kappa_i, 1, 0) per kept
+    // point, D_B = diag(d_i); right-hand side (rhs, Y4_B)
+    const int Ne = N2 + nkeep;
+    double* Ze = ws + L.aux + 2 * (int64_t)g * g;  // [Ne][Ne]
+    for (int e = tid; e < Ne * Ne; e += NYLS_BLOCK) {
+      const int a = e / Ne, c = e - a * Ne;
+      double val = 0.0;
+      if (a < N2 && c < N2) val = Z[a * lz + c];
+      else if (a >= N2 && c >= N2) val = 0.0;  // diagonal entries below
+      Ze[e] = val;
+    }
+    __syncthreads();
+    for (int e = tid; e < nkeep * N2; e += NYLS_BLOCK) {
+      const int j = e / N2, a = e - j * N2;
+      const int i = keep[j];
+      const double ti = nyls_grid_t(d, i), fy = Fy[i];
+      double v = 0.0;
+      if (a < r) {
+        for (int s = 0; s < m; ++s) {
+          const double z = (ti - tl[s]) * inv_sigma;
+          const double e0 = exp(-z * z);
+          v += W[s * m + a] * (fy * (-2.0 * z * inv_sigma * e0) + e0);
+        }
+        v *= -gam;
+      } else if (a == m) {
+        v = -gam;
+      }
+      Ze[a * Ne + N2 + j] = v;
+      Ze[(N2 + j) * Ne + a] = v;
+    }
+    for (int j = tid; j < nkeep; j += NYLS_BLOCK) {
+      const int i = keep[j];
+      const double ti = nyls_grid_t(d, i), fy = Fy[i];
+      double d0 = 0.0, d1 = 0.0;
+      for (int s = 0; s < m; ++s) {
+        const double z = (ti - tl[s]) * inv_sigma;
+        const double e0 = exp(-z * z);
+        d0 += e0 * al[s];
+        d1 += -2.0 * z * inv_sigma * e0 * al[s];
+      }
+      const double rho = d1 - F[i];
+      const double eta = xi[maxm + 2 + i] - d0 - b;
+      Ze[(N2 + j) * Ne + N2 + j] = gam * (1.0 + fy * fy - rho * Fyy[i]);
+      rhs[N2 + j] = gam * (-rho * fy + eta);
+    }
+    __syncthreads();
+    sing = nyls_lu(Ze, Ne, Ne, piv, red);
+    nyls_lu_solve(Ze, Ne, Ne, piv, rhs);  // rhs <- (dz, dy_B)
+  }
   for (int s = tid; s < m; s += NYLS_BLOCK) {
     double acc = 0.0;
     for (int k = 0; k < r; ++k) acc += W[s * m + k] * rhs[k];
@@ -310,6 +391,9 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_step(
   double dmax = 0.0;
   for (int i = tid; i < n; i += NYLS_BLOCK) {
     if (nyls_is_condition_point(d, i)) continue;
+    bool kept = false;
+    for (int j = 0; j < nkeep; ++j) kept |= keep[j] == i;
+    if (kept) continue;  // dy_i came from the dense system
     const double ti = nyls_grid_t(d, i);
     const double fy = Fy[i];
     double d0 = 0.0, d1 = 0.0, dk = 0.0;
@@ -327,6 +411,11 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_step(
     const double dd = gam * (1.0 + fy * fy - rho * Fyy[i]);
     const double dy = (dd != 0.0 && dd == dd) ? (y4 + gam * (dk + db)) / dd : 0.0;
     xi[maxm + 2 + i] -= dy;
+    dmax = fmax(dmax, fabs(dy));
+  }
+  for (int j = tid; j < nkeep; j += NYLS_BLOCK) {
+    const double dy = rhs[N2 + j];
+    xi[maxm + 2 + keep[j]] -= dy;
     dmax = fmax(dmax, fabs(dy));
   }
   for (int a = tid; a < N2; a += NYLS_BLOCK) dmax = fmax(dmax, fabs(rhs[a]));
@@ -350,6 +439,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_step(
     ws[L.x + m] = b - db;
     int bits = (int)ws[L.info + 1];
     if (badf > 0) bits |= NYLS_S_SMALL_PIVOT;
+    if (ovff > 0) bits |= NYLS_S_PIVOT_OVERFLOW;
     if (sing) bits |= NYLS_S_SINGULAR;
     if (!(fabs(b - db) <= 1.7976931348623157e308)) bits |= NYLS_S_NONFINITE;
     if (status) status[inst] = bits;
@@ -357,7 +447,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_newton_step(
 }
 
 size_t step_lds_bytes(int maxm) {
-  const size_t common = (4 * NYLS_NARROW_MAX_M + NYLS_BLOCK + 16 + 136 + TP * 8) * sizeof(double) + 136 * sizeof(int);
+  const size_t common = (4 * NYLS_NARROW_MAX_M + NYLS_BLOCK + 16 + kNz + TP * 8) * sizeof(double) +
+                        (kNz + kKeep + 2) * sizeof(int);
   const int gp = round4(maxm + 2);
   size_t pass = (2 * (size_t)TP * maxm + (size_t)TP * gp + TP) * sizeof(double);
   const size_t redb = (size_t)nyls_gram::red_doubles(gp) * sizeof(double);

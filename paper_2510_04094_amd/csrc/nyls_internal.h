@@ -83,7 +83,8 @@ __host__ __device__ inline nyls_wsl nyls_layout(int m, int p, int n_newton) {
   L.log = L.U + (int64_t)m * m;  // plane-rotation log of the lane-parallel QL: 2 m^2 (c, s)
                                  // entries
   L.aux = L.log + 4 * (int64_t)m * m;  // Newton: constant block (m+2)^2 + weighted Gram (m+2)^2
-  L.end = L.aux + (n_newton > 0 ? 2 * g * g : 0);
+                                       // + the system with small-pivot points kept (m+34)^2
+  L.end = L.aux + (n_newton > 0 ? 2 * g * g + (g + 32) * (g + 32) : 0);
   L.end = (L.end + 7) & ~int64_t(7);
   return L;
 }

@@ -20,6 +20,7 @@ FP64, MIXED, FP64_EXPLICIT = 0, 1, 2
 S_TRUNCATED, S_SINGULAR, S_NONFINITE, S_EIG_NOCONV, S_SMALL_PIVOT, S_REFINE_NOCONV = 1, 2, 4, 8, 16, 32
 S_FP64_RESOLVED = 64
 S_PARAM_KEPT = 128
+S_PIVOT_OVERFLOW = 256
 
 _lib = None
 

@@ -75,3 +75,58 @@ def test_riccati_evaluator_requires_first_order(gpu_lib):
     q = torch.zeros(b.total, dtype=torch.float64, device="cuda")
     with pytest.raises(gpu_lib.NylsError):
         b.riccati_eval(q, x, True)
+
+
+def test_small_pivots_stay_in_the_dense_system(gpu_lib):
+    """A Newton step where the caller's F_yy drives d_i = gamma (1 + F_y^2 - rho_i F_yy) to
+    (about) zero at three points: those points are not divided out but stay unknowns of the
+    dense system, so the step is the exact Newton step; compared with the oracle's dense
+    step (the paper's full system) on the gauge-free parts (the slack values y_i and b)."""
+    p = workloads.riccati(0, n=300)
+    b = gpu_lib.Batch([p], mode=gpu_lib.FP64)
+    q = torch.tensor(p["q"], dtype=torch.float64, device="cuda")
+    x = b.newton_init()
+    F, Fy, Fyy = b.riccati_eval(q, x, True)
+    b.newton_step(x, F, Fy, Fyy)  # leave the starting point
+    F, Fy, Fyy = b.riccati_eval(q, x, False)
+    yd, _ = b.predict([p["t"]], 1)
+    y0, _ = b.predict([p["t"]], 0)
+    torch.cuda.synchronize()
+    Fh, Fyh, Fyyh = F.cpu().numpy(), Fy.cpu().numpy(), Fyy.cpu().numpy()
+    rho = yd.cpu().numpy() - Fh
+    st = oracle.newton.setup(p)
+    idx, r = st["idx"], st["r"]
+    cand = [i for i in idx[5:-5] if abs(rho[i]) > 1e-2]
+    pts = np.array(cand[::max(1, len(cand) // 3)][:3])
+    assert pts.size == 3
+    fyy = Fyyh.copy()
+    fyy[pts] = (1.0 + Fyh[pts] ** 2) / rho[pts]
+    x1 = x.clone()
+    b.newton_step(x, F, Fy, torch.tensor(fyy, device="cuda"))
+    torch.cuda.synchronize()
+    status = int(b._status.cpu().numpy()[0])
+    assert status & gpu_lib.S_SMALL_PIVOT
+    assert not status & (gpu_lib.S_PIVOT_OVERFLOW | gpu_lib.S_SINGULAR | gpu_lib.S_NONFINITE)
+    x1h, x2h = x1.cpu().numpy()[0], x.cpu().numpy()[0]
+    m = b.maxm
+    # omega in the oracle's eigenbasis (the eigenvector signs of the two sides may differ):
+    # the least-squares fit of the GPU's y_hat - b on the oracle's features
+    phi_all = oracle.nystrom.features(0, st["t"], st["t_land"], p["sigma"], st["W"])
+    om = np.linalg.lstsq(phi_all, y0.cpu().numpy() - x1h[m], rcond=None)[0]
+    xo = np.concatenate([om, [x1h[m], x1h[m + 1]], x1h[m + 2 + idx]])
+
+    def fun(ix, y):
+        return Fh[ix], Fyh[ix], fyy[ix]
+
+    jac = oracle.newton.jacobian(xo, st, p, fun)
+    dg = np.diag(jac)[r + 2:]
+    assert np.max(np.abs(dg[np.searchsorted(idx, pts)])) <= 1e-9 * p["gamma"]  # the forced pivots
+    _, dx = oracle.newton.step_dense(xo, st, p, fun)
+    _, dx_div = oracle.newton.step_schur(xo, st, p, fun)  # dividing by the tiny pivots
+    dy_gpu = x1h[m + 2 + idx] - x2h[m + 2 + idx]
+    dy_ref = dx[r + 2:]
+    scale = max(abs(dx[r]), np.max(np.abs(dy_ref)))
+    # an early iterate, ill-conditioned as in the step-by-step test (there 1e-4)
+    assert np.max(np.abs(dy_gpu - dy_ref)) <= 1e-5 * scale
+    assert abs((x1h[m] - x2h[m]) - dx[r]) <= 1e-5 * scale
+    assert np.max(np.abs(dx_div[r + 2:] - dy_ref)) > 1e-2 * scale  # the case is not benign
