@@ -29,6 +29,7 @@ struct nyls_plan {
   unsigned ntl_mask = 0;
   int32_t n_big = 0;        // instances with m > 64
   int32_t n_split = 0, max_chunks = 0;
+  int32_t n_vgram = 0;      // unsplit instances on the LDS-tile FP64 Gram
   int64_t split_off = 0;       // partial sums of split instances (doubles from ws)
   int64_t split_doubles = 0;
   nyls_tuning tune = {0, 64, 0, 1, 1, -1};
@@ -100,6 +101,7 @@ nyls_plan_view view(const nyls_plan* pl) {
   v.ntl_mask = pl->ntl_mask;
   v.n_big = pl->n_big;
   v.n_split = pl->n_split;
+  v.n_vgram = pl->n_vgram;
   v.max_chunks = pl->max_chunks;
   v.eig_ql = pl->tune.eig_ql;
   v.ql_lanes = pl->tune.ql_lanes;
@@ -196,7 +198,7 @@ int split_chunk(const nyls_plan* pl) {
 
 void apply_tuning(nyls_plan* pl) {
   pl->gcls_mask = pl->tl_mask = pl->ntl_mask = 0;
-  pl->n_split = pl->max_chunks = 0;
+  pl->n_split = pl->max_chunks = pl->n_vgram = 0;
   pl->split_off = pl->ws_doubles + pl->scratch_doubles;
   pl->split_doubles = 0;
   const int ch = split_chunk(pl);
@@ -221,6 +223,7 @@ void apply_tuning(nyls_plan* pl) {
     if (pl->tune.tail_layout && (nyls_gram_class(d.m) & 1)) f |= NYLS_DF_GRAM_TAIL;
     if (pl->tune.gram_valu && d.m + 2 <= 64) f |= NYLS_DF_GRAM_VALU;
     d.flags = f;
+    if (!(f & NYLS_DF_SPLIT) && (d.m + 2 > 64 || (f & NYLS_DF_GRAM_VALU))) ++pl->n_vgram;
     if (d.m + 2 <= 64 && !(f & NYLS_DF_GRAM_VALU)) pl->gcls_mask |= 1u << nyls_gram_class_of(d);
     if (f & NYLS_DF_TAIL) pl->tl_mask |= 1u << nyls_slot_blocks(d.m);
     else pl->ntl_mask |= 1u << nyls_slot_blocks(d.m);
@@ -530,7 +533,7 @@ int solve_impl(const nyls_plan* pl, int32_t refine_steps, double* omega, double*
     // joined whatever happened above, so no work is left running on the side stream
     if (ej == hipSuccess) ej = hipStreamWaitEvent(stream, pl->ev_join, 0);
     if (e == hipSuccess) e = ej;
-    if (e == hipSuccess) e = nyls_launch_gram64_rest(pv, w, stream);
+    if (e == hipSuccess) e = nyls_launch_gram64_rest(pv, w, stream, true);
   } else {
     nyls_prof_begin(NYLS_K_EIG, stream);
     e = nyls_launch_eig(pv, w, -1, stream);

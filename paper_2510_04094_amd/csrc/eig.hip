@@ -866,14 +866,18 @@ __device__ inline double wide_col_dot(const double* A, int m, int j, int c0, con
   return acc;
 }
 
+// Instances with lo < m <= hi (the wide bases, or batches of 64 < m <= 128, where the
+// one-wave kernel's K_mm fills half a CU's LDS); redo: leave instances whose rotation log
+// overflowed to k_eig_ql2(QL_REDO).
 __global__ __launch_bounds__(NYLS_BLOCK) void k_eig_wide(const nyls_desc* __restrict__ desc,
-                                                         double* __restrict__ wsbase, int stage) {
+                                                         double* __restrict__ wsbase, int stage,
+                                                         int lo, int hi, int redo) {
   __shared__ double vv[NYLS_MAX_M], ww[NYLS_MAX_M], tl[NYLS_MAX_M], bt[NYLS_MAX_M];
   __shared__ double dd[NYLS_MAX_M], ee[NYLS_MAX_M], red[NYLS_BLOCK / 64];
   __shared__ int pos[NYLS_MAX_M];
   const nyls_desc& d = desc[blockIdx.x];
   const int m = d.m;
-  if (m <= NYLS_NARROW_MAX_M) return;
+  if (m <= lo || m > hi) return;
   const nyls_wsl L = nyls_layout(m, d.p, 0);
   double* ws = wsbase + d.ws;
   const int j = threadIdx.x;
@@ -962,6 +966,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig_wide(const nyls_desc* __rest
 
   // 5. ordering, signs, cut-off, W and U
   const int flag = (int)ws[L.info + 7];
+  if (redo && flag == 2) return;  // recomputed by k_eig_ql2(QL_REDO)
   const double dj = own ? ws[L.lam + j] : 0.0;
   if (own) dd[j] = dj;
   __syncthreads();
@@ -1137,11 +1142,11 @@ __global__ __launch_bounds__(64) void k_ql_wide(const nyls_desc* __restrict__ de
 // rotation of the sweep has rewritten, so the reads of eight rotations are issued together.
 // One wavefront per workgroup: no barriers.
 __global__ __launch_bounds__(64) void k_eig_wide_replay(const nyls_desc* __restrict__ desc,
-                                                        double* __restrict__ wsbase) {
+                                                        double* __restrict__ wsbase, int lo, int hi) {
   extern __shared__ double sm[];
   const nyls_desc& d = desc[blockIdx.x];
   const int m = d.m;
-  if (m <= NYLS_NARROW_MAX_M) return;
+  if (m <= lo || m > hi) return;  // (the LDS holds hi columns)
   const int r0 = (int)blockIdx.y * kWideRows;
   if (r0 >= m) return;
   const nyls_wsl L = nyls_layout(m, d.p, 0);
@@ -1236,14 +1241,16 @@ hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hip
     }
   }
   if (pv.nb_mask & (1u << 16)) {  // wide bases (never in single-instance launches)
-    hipLaunchKernelGGL(k_eig_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, (int)WIDE_REDUCE);
+    const int lo = NYLS_NARROW_MAX_M;
+    hipLaunchKernelGGL(k_eig_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, (int)WIDE_REDUCE, lo, NYLS_MAX_M, 0);
     hipLaunchKernelGGL(k_ql_wide, dim3(pv.batch), dim3(64), 0, st, pv.d_desc, ws);
     const size_t lds = (size_t)pv.maxm * kWideRows * sizeof(double);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_wide_replay),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_eig_wide_replay, dim3(pv.batch, (pv.maxm + kWideRows - 1) / kWideRows), dim3(64),
-                       lds, st, pv.d_desc, ws);
-    hipLaunchKernelGGL(k_eig_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, (int)WIDE_FINISH);
+                       lds, st, pv.d_desc, ws, lo, NYLS_MAX_M);
+    hipLaunchKernelGGL(k_eig_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, (int)WIDE_FINISH, lo,
+                       NYLS_MAX_M, 0);
   }
   if (!(pv.nb_mask & 256)) return hipGetLastError();
   // 64 < m <= 128: one wavefront per instance, two rows per lane.  With many such instances
@@ -1259,13 +1266,23 @@ hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hip
     hipLaunchKernelGGL(k_eig_ql2, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
                        (int)QL_FULL);
   } else {
+    // staged through the workspace: the reduction by 256 threads per instance (K_mm in the
+    // workspace, many instances per CU), the lane-parallel QL, the replay on rows of Z held in
+    // LDS by two workgroups per instance and the ordering; instances whose rotation log
+    // overflowed are redone by the one-wave kernel
     const int ipw = pv.ql_lanes >= 1 && pv.ql_lanes <= kQlLaneInst ? pv.ql_lanes : kQlLaneInst;
-    hipLaunchKernelGGL(k_eig_ql2, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
-                       (int)QL_REDUCE);
+    const int lo = kQlMaxM;
+    hipLaunchKernelGGL(k_eig_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, (int)WIDE_REDUCE, lo, 2 * kQlMaxM, 1);
     hipLaunchKernelGGL(k_ql_lanes<2 * kQlMaxM>, dim3((pv.batch + ipw - 1) / ipw), dim3(64), 0, st,
                        pv.d_desc, ws, pv.batch, ipw);
-    hipLaunchKernelGGL(k_eig_ql2, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
-                       (int)QL_REPLAY);
+    const int mr = pv.maxm_narrow;
+    const size_t rl = (size_t)mr * kWideRows * sizeof(double);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_wide_replay),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)rl);
+    hipLaunchKernelGGL(k_eig_wide_replay, dim3(pv.batch, (mr + kWideRows - 1) / kWideRows), dim3(64), rl, st,
+                       pv.d_desc, ws, lo, 2 * kQlMaxM);
+    hipLaunchKernelGGL(k_eig_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, (int)WIDE_FINISH, lo,
+                       2 * kQlMaxM, 1);
     hipLaunchKernelGGL(k_eig_ql2, grid, dim3(64), lds, st, pv.d_desc, pv.d_order, ws, single, lda,
                        (int)QL_REDO);
   }

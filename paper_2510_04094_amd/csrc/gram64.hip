@@ -50,10 +50,12 @@ __device__ inline void block_coords(int blk, int nb, int& bi, int& bj) {
   bj = row + b;
 }
 
-// smode 0: instances without NYLS_DF_SPLIT, the whole grid, into the instance's Gram;
+// smode 0: instances without NYLS_DF_SPLIT, the whole grid, into the instance's Gram, in the
+// basis the eigensolver's result calls for; smode 3 / 4: the same in two halves, kernel space
+// for every instance (3, needs nothing from the eigensolver, so it can run beside it) and,
+// after the eigensolver, rotated for the instances that need the eigenbasis (4);
 // smode 1 / 2: split instances, chunk blockIdx.y of the grid, into its partial sum, in
-// kernel space (1, needs nothing from the eigensolver) or, for instances that need the
-// eigenbasis, rotated (2, after the eigensolver).
+// kernel space (1) or, for instances that need the eigenbasis, rotated (2).
 // TP = 64: bases up to NYLS_NARROW_MAX_M; TP = 32: wide bases (see kWideBlocks).
 template <int TP>
 __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restrict__ desc,
@@ -63,10 +65,11 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
   constexpr bool WIDE = TP == 32;
   extern __shared__ double sm[];
   const nyls_desc& d = desc[instance_of(order)];
-  if (((d.flags & NYLS_DF_SPLIT) != 0) != (smode != 0)) return;
+  const bool split = smode == 1 || smode == 2;
+  if (((d.flags & NYLS_DF_SPLIT) != 0) != split) return;
   if ((d.m > NYLS_NARROW_MAX_M) != WIDE) return;
   const int chunk = (int)blockIdx.y;
-  if (smode && chunk >= d.nchunks) return;
+  if (split && chunk >= d.nchunks) return;
   if (only && !((int)wsbase[d.ws + nyls_layout(d.m, d.p, 0).info + 1] & only)) return;
   const int m = d.m, p = d.p, n = d.n;
   const int g = m + 2;
@@ -91,14 +94,14 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
   // Ill-conditioned K_mm (retained eigenvalues below 1e-9 lambda_1): the kernel-space Gram
   // would lose most digits in W^T S W, so the rows are rotated by U^T first and the Gram is
   // accumulated in the eigenbasis (the KKT kernel then scales by Lambda^{-1/2}).
-  const int rank = smode == 1 ? 0 : (int)ws[L.info + 0];
+  const int rank = (smode == 1 || smode == 3) ? 0 : (int)ws[L.info + 0];
   const bool rotate = only || (rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam]);
-  if (smode == 2 && !rotate) return;  // the kernel-space partials stand
+  if ((smode == 2 || smode == 4) && !rotate) return;  // the kernel-space Gram stands
   // m + 2 <= 64: the one-wave MFMA kernels take the instance unless its tuning asks for this
   // one (split instances always come here)
-  if (!smode && nyls_slot_blocks(m + 2) <= 4 && !(d.flags & NYLS_DF_GRAM_VALU)) return;
-  const int ibeg = smode ? chunk * d.chunk : 0;
-  const int iend = smode ? min(n, ibeg + d.chunk) : n;
+  if (!split && nyls_slot_blocks(m + 2) <= 4 && !(d.flags & NYLS_DF_GRAM_VALU)) return;
+  const int ibeg = split ? chunk * d.chunk : 0;
+  const int iend = split ? min(n, ibeg + d.chunk) : n;
   const double* Ug = ws + L.U;
   const bool ulds = maxm <= 64;
   if (rotate && ulds)
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
       }
     }
   }
-  double* out = smode ? wsbase + d.part + nyls_split_gram(m, chunk) : ws + L.gram;
+  double* out = split ? wsbase + d.part + nyls_split_gram(m, chunk) : ws + L.gram;
   if constexpr (WIDE) {
     // one thread per block: its entries and their mirror images, straight from registers
 #pragma unroll
@@ -227,7 +230,7 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
     const int blk = ia * nb - ia * (ia - 1) / 2 + (ib - ia);
     out[e] = Q[blk * 16 + (a & 3) * 4 + (b & 3)];
   }
-  if (tid == 0 && !smode) ws[L.info + 4] = rotate ? 1.0 : 0.0;
+  if (tid == 0 && !split) ws[L.info + 4] = rotate ? 1.0 : 0.0;
 }
 
 // Gram of a split instance: the sum of its chunk partials in chunk order (a fixed order,
@@ -624,8 +627,9 @@ template <int TP>
 void launch_vg(const nyls_plan_view& pv, double* ws, hipStream_t st, int smode, int only) {
   constexpr bool wide = TP == 32;
   const int maxm = wide ? pv.maxm : pv.maxm_narrow;
-  if (wide ? (!smode || !(pv.nb_mask & (1u << 16))) : maxm == 0) return;
-  if (smode && !pv.n_split) return;
+  const bool split = smode == 1 || smode == 2;
+  if (wide ? (!split || !(pv.nb_mask & (1u << 16))) : maxm == 0) return;
+  if (split ? !pv.n_split : (!pv.n_vgram && !pv.only)) return;
   const size_t lds = gram64_lds_bytes(maxm, TP, wide);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64<TP>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -634,7 +638,7 @@ void launch_vg(const nyls_plan_view& pv, double* ws, hipStream_t st, int smode, 
     const int nb = ((maxm + 2 + 3) & ~3) >> 2;
     gz = (nb * (nb + 1) / 2 + kWideBlocks - 1) / kWideBlocks;
   }
-  const dim3 grid(pv.batch, smode ? pv.max_chunks : 1, gz);
+  const dim3 grid(pv.batch, split ? pv.max_chunks : 1, gz);
   hipLaunchKernelGGL(k_gram64<TP>, grid, dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws, maxm,
                      only, smode);
 }
@@ -648,6 +652,7 @@ void launch_split_parts(const nyls_plan_view& pv, double* ws, hipStream_t st, in
 
 hipError_t nyls_launch_gram64_kspace(const nyls_plan_view& pv, double* ws, hipStream_t st) {
   launch_ks_all(pv, ws, st, -1);
+  launch_vg<64>(pv, ws, st, 3, 0);  // LDS-tile kernel-space Grams (m + 2 > 64, or by tuning)
   launch_split_parts(pv, ws, st, 1);
   return hipGetLastError();
 }
@@ -657,13 +662,15 @@ hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t 
     launch_ks_all(pv, ws, st, 0);
     launch_split_parts(pv, ws, st, 1);
   }
-  return nyls_launch_gram64_rest(pv, ws, st);
+  return nyls_launch_gram64_rest(pv, ws, st, false);
 }
 
-hipError_t nyls_launch_gram64_rest(const nyls_plan_view& pv, double* ws, hipStream_t st) {
+hipError_t nyls_launch_gram64_rest(const nyls_plan_view& pv, double* ws, hipStream_t st, bool ks_done) {
   if (pv.gnb_mask & 4) launch_mfma_nb<2>(pv, ws, st);
   if (pv.gnb_mask & 16) launch_mfma_nb<4>(pv, ws, st);
-  launch_vg<64>(pv, ws, st, 0, pv.only);
+  // after nyls_launch_gram64_kspace the LDS-tile kernel-space Grams exist: only the
+  // instances that need the eigenbasis are done again
+  launch_vg<64>(pv, ws, st, (ks_done && !pv.only) ? 4 : 0, pv.only);
   if (pv.n_split && !pv.only) {
     launch_split_parts(pv, ws, st, 2);
     const int g = pv.maxm + 2;

@@ -369,6 +369,8 @@ struct nyls_plan_view {
   unsigned ntl_mask;        // bit b: some instance of slot class b does not
   int32_t n_big;            // instances with m > 64
   int32_t n_split;          // instances with NYLS_DF_SPLIT
+  int32_t n_vgram;          // unsplit instances whose FP64 Gram takes the LDS-tile kernel
+                            // (m + 2 > 64, or NYLS_DF_GRAM_VALU)
   int32_t max_chunks;       // largest nchunks of a split instance
   int32_t eig_ql;           // tuning: 1 QL inside one wavefront per instance
   int32_t ql_lanes;         // tuning: instances per wavefront of the lane-parallel QL
@@ -380,10 +382,10 @@ hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hip
 hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t st);
 // The two halves of nyls_launch_gram64 for a solve that overlaps the Gram with the
 // eigensolver: the kernel-space Grams of every instance (they read nothing the eigensolver
-// writes), then, once the eigensolver is done, the eigenbasis Grams that replace them where
-// K_mm is ill-conditioned and the Grams of bases too wide for the one-wave kernels.
+// writes), then, once the eigensolver is done (ks_done = true), the eigenbasis Grams that
+// replace them where K_mm is ill-conditioned.
 hipError_t nyls_launch_gram64_kspace(const nyls_plan_view& pv, double* ws, hipStream_t st);
-hipError_t nyls_launch_gram64_rest(const nyls_plan_view& pv, double* ws, hipStream_t st);
+hipError_t nyls_launch_gram64_rest(const nyls_plan_view& pv, double* ws, hipStream_t st, bool ks_done);
 hipError_t nyls_launch_gram32(const nyls_plan_view& pv, double* ws, hipStream_t st);
 hipError_t nyls_launch_kkt(const nyls_plan_view& pv, double* ws, double* kkt_out, double* rhs_out,
                            int factor, hipStream_t st);
