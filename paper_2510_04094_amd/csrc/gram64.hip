@@ -38,6 +38,7 @@ constexpr int MAXB = 3;     // 4x4 blocks per thread (m <= 128 -> at most 561 bl
 // ceil(nblk / (3 * 256)) workgroups per chunk (grid z), each writing its blocks straight
 // from registers; every one of them forms the chunk's rows.
 constexpr int kWideBlocks = MAXB * NYLS_BLOCK;
+constexpr int kG4Blocks = 8;  // column blocks of the four-wave MFMA Gram (m + 2 <= 128)
 
 __device__ inline int instance_of(const int32_t* order) {
   return order ? order[blockIdx.x] : (int)blockIdx.x;
@@ -98,8 +99,9 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
   const bool rotate = only || (rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam]);
   if ((smode == 2 || smode == 4) && !rotate) return;  // the kernel-space Gram stands
   // m + 2 <= 64: the one-wave MFMA kernels take the instance unless its tuning asks for this
-  // one (split instances always come here)
+  // one, m + 2 <= 128 in kernel space the four-wave one (split instances always come here)
   if (!split && nyls_slot_blocks(m + 2) <= 4 && !(d.flags & NYLS_DF_GRAM_VALU)) return;
+  if (!split && !rotate && m + 2 <= 16 * kG4Blocks && !(d.flags & NYLS_DF_GRAM_VALU)) return;
   const int ibeg = split ? chunk * d.chunk : 0;
   const int iend = split ? min(n, ibeg + d.chunk) : n;
   const double* Ug = ws + L.U;
@@ -423,6 +425,135 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   if (lane == 0) ws[L.info + 4] = 0.0;
 }
 
+// Kernel-space FP64 Gram for 64 < m + 2 <= 128 on the matrix cores, four wavefronts per
+// instance.  The one-wave kernel's 36 accumulator tiles would not fit one wavefront's
+// registers, so the work is shared out: wavefront w forms the rows q_i for the column blocks
+// 2w and 2w + 1 (the one-wave lane layout with two slot blocks, landmarks from 32 w on) and
+// stores them to LDS in that same operand layout, Qt[j][b][lane] = q_(4j+ph)[16 b + sl]; after
+// one workgroup barrier every wavefront reads the operands of all blocks back from its own
+// lane positions and accumulates the tile pairs t = I (I + 1) / 2 + ... with t = w (mod 4)
+// (at most nine, 36 accumulator doubles).  The LDS rows are double-buffered by chunk, so one
+// barrier per 16-point chunk suffices.
+template <int P, bool EX>
+__global__ __launch_bounds__(NYLS_BLOCK) void k_gram64_mfma4(const nyls_desc* __restrict__ desc,
+                                                             const int32_t* __restrict__ order,
+                                                             double* __restrict__ wsbase, int only) {
+  constexpr int NBW = kG4Blocks / 4;                      // slot blocks formed per wavefront
+  constexpr int TMAX = kG4Blocks * (kG4Blocks + 1) / 2;   // tile pairs
+  constexpr int TW = (TMAX + 3) / 4;                      // per wavefront
+  __shared__ __align__(16) double Qt[2][4][kG4Blocks][64];
+  const nyls_desc& d = desc[instance_of(order)];
+  if (d.p != P || d.rec != (EX ? 0 : 1) || d.m + 2 <= 64 || d.m + 2 > 16 * kG4Blocks ||
+      (d.flags & (NYLS_DF_GRAM_VALU | NYLS_DF_SPLIT)))
+    return;
+  const int m = d.m, n = d.n, g = m + 2;
+  const int nbt = (g + 15) >> 4;  // blocks with data
+  const nyls_wsl L = nyls_layout(m, P, 0);
+  double* ws = wsbase + d.ws;
+  // only < 0: every instance, before the eigensolver has chosen the basis (instances that
+  // turn out to need the eigenbasis are redone by k_gram64)
+  if (only >= 0 && use_eigenbasis(ws, L, only)) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int s0 = 16 * NBW * w;
+
+  nyls_walk<NBW, EX> wk;
+  wk.init(d, lane, s0);
+  nyls_cpts cpt;
+  cpt.init(d);
+  const double inv_sigma = wk.inv_sigma, inv_s2 = inv_sigma * inv_sigma;
+  const __amdgpu_buffer_rsrc_t fr = nyls_rsrc(d.f, P * n * 8), rr = nyls_rsrc(d.r, n * 8);
+  int kind[NBW];  // 0 landmark, 1 c_i, 2 r_i, 3 nothing
+#pragma unroll
+  for (int b = 0; b < NBW; ++b) {
+    const int sidx = s0 + 16 * b + wk.sl;
+    kind[b] = sidx < m ? 0 : (sidx == m ? 1 : (sidx == m + 1 ? 2 : 3));
+  }
+  nyls_d4 acc[TW];
+#pragma unroll
+  for (int t = 0; t < TW; ++t) acc[t] = nyls_d4{0.0, 0.0, 0.0, 0.0};
+  nyls_oppoly<P> op;
+  op.init(inv_s2);
+  struct stage {
+    double f[P][4], r[4];
+  };
+  auto load = [&](int i0, stage& st) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = i0 + 4 * j + wk.ph;
+#pragma unroll
+      for (int k = 0; k < P; ++k) st.f[k][j] = nyls_bload(fr, (k * n + i) * 8);
+      st.r[j] = nyls_bload(rr, i * 8);
+    }
+  };
+  int buf = 0;
+  auto body = [&](int i0, const stage& st) {
+    wk.advance(d, i0);
+    double cj[4][P];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double f[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) f[k] = st.f[k][j];
+      op.coef(f, cj[j]);
+    }
+    double q[NBW];
+    wk.chunk(
+        d, i0,
+        [&](int b, int j, double gg, double e) {
+          q[b] = kind[b] == 0 ? e * nyls_horner<P>(gg, cj[j])
+                              : (kind[b] == 1 ? -st.f[P - 1][j] : (kind[b] == 2 ? st.r[j] : 0.0));
+        },
+        [&](int j) {
+          const int i = i0 + 4 * j + wk.ph;
+          const bool ok = i < n && !cpt.has(i);
+#pragma unroll
+          for (int b = 0; b < NBW; ++b) Qt[buf][j][NBW * w + b][lane] = ok ? q[b] : 0.0;
+        });
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double qa[kG4Blocks];
+#pragma unroll
+      for (int I = 0; I < kG4Blocks; ++I) qa[I] = I < nbt ? Qt[buf][j][I][lane] : 0.0;
+      int t = 0;
+#pragma unroll
+      for (int I = 0; I < kG4Blocks; ++I)
+#pragma unroll
+        for (int J = I; J < kG4Blocks; ++J, ++t)
+          if ((t & 3) == w && J < nbt)
+            acc[t >> 2] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[I], qa[J], acc[t >> 2], 0, 0, 0);
+    }
+    buf ^= 1;
+  };
+  stage sa, sb;
+  load(0, sa);
+  for (int i0 = 0; i0 < n; i0 += 32) {
+    load(i0 + 16, sb);
+    body(i0, sa);
+    if (i0 + 16 >= n) break;
+    load(i0 + 32, sa);
+    body(i0 + 16, sb);
+  }
+  // tile (I, J): register v of lane l holds row 16 I + 4 v + l / 16, column 16 J + l % 16
+  double* out = ws + L.gram;
+  int t = 0;
+#pragma unroll
+  for (int I = 0; I < kG4Blocks; ++I)
+#pragma unroll
+    for (int J = I; J < kG4Blocks; ++J, ++t) {
+      if ((t & 3) != w || J >= nbt) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = 16 * I + 4 * v + (lane >> 4), b = 16 * J + (lane & 15);
+        if (a < g && b < g) {
+          out[a * g + b] = acc[t >> 2][v];
+          if (I != J) out[b * g + a] = acc[t >> 2][v];
+        }
+      }
+    }
+  if (threadIdx.x == 0) ws[L.info + 4] = 0.0;
+}
+
 // Eigenbasis Gram on the matrix cores: per 16-point chunk the kernel-space rows are staged in
 // LDS (X[point][landmark]) and rotated, D = X U, with v_mfma_f64_16x16x4f64 (A = X in the
 // operand layout row = point, k = 4 landmarks; B = U, kept in registers).  The result
@@ -594,7 +725,22 @@ void launch_ks(const nyls_plan_view& pv, double* ws, hipStream_t st, int only) {
   if (pv.rec_mask & 1) launch_ks_x<NB, true, TLG>(pv, ws, st, only);
 }
 
+template <int P>
+void launch_g4_p(const nyls_plan_view& pv, double* ws, hipStream_t st, int only) {
+  if (!(pv.p_mask & (1u << P))) return;
+  if (pv.rec_mask & 2)
+    hipLaunchKernelGGL((k_gram64_mfma4<P, false>), dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, pv.d_order, ws, only);
+  if (pv.rec_mask & 1)
+    hipLaunchKernelGGL((k_gram64_mfma4<P, true>), dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, pv.d_order, ws, only);
+}
+
 void launch_ks_all(const nyls_plan_view& pv, double* ws, hipStream_t st, int only) {
+  if (pv.maxm_narrow + 2 > 64) {  // four-wave MFMA Gram, 64 < m + 2 <= 128
+    launch_g4_p<1>(pv, ws, st, only);
+    launch_g4_p<2>(pv, ws, st, only);
+    launch_g4_p<3>(pv, ws, st, only);
+    launch_g4_p<4>(pv, ws, st, only);
+  }
   launch_ks<1, false>(pv, ws, st, only);
   launch_ks<2, false>(pv, ws, st, only);
   launch_ks<2, true>(pv, ws, st, only);

@@ -252,6 +252,13 @@ ASSEMBLE_SETS = {
     **{"second-order m=%d" % m: (lambda m=m: [workloads.linear_second_order(i, n=2000, m=m)
                                               for i in range(2)])
        for m in (14, 15, 18, 31, 40, 46, 47, 48, 50, 62)},
+    # 64 < m + 2 <= 128: the four-wavefront matrix-core Gram (five to eight column blocks),
+    # orders 1, 2 and 4
+    **{"second-order m=%d" % m: (lambda m=m: [workloads.linear_second_order(i, n=2000, m=m, sigma=0.3)
+                                              for i in range(2)])
+       for m in (63, 78, 100, 126)},
+    "first-order m=90": lambda: [workloads.linear_first_order(i, n=1500, m=90) for i in range(2)],
+    "order-4 m=70": lambda: [workloads.linear_order_p(3, 4, n=2000, m=70, sigma=0.3, tau=1e-8)],
 }
 
 
