@@ -198,6 +198,16 @@ int32_t nyls_max_m(const nyls_plan* plan);
  *   before it on `stream`. */
 int nyls_instance_info(const nyls_plan* plan, const void* ws, double* info, hipStream_t stream);
 
+/* Copy each instance's eigendecomposition K_mm = U Lambda U^T (App. A.2, eq32) from `ws`:
+ *   lam  [batch][MAXM] eigenvalues, descending (entries k >= m zero)
+ *   U    [batch][MAXM][MAXM] eigenvectors as columns, U[i][s][k] (row s, column k; entries
+ *        outside m x m zero), each signed so its largest-magnitude entry is positive
+ * Either pointer may be NULL (not copied); both device memory.  Valid after a call that
+ * forms the basis (nyls_solve, nyls_solve_static, nyls_features, nyls_assemble,
+ * nyls_newton_init) and before the next plan change; values are those of the work
+ * enqueued before it on `stream`.  Nothing here changes ws. */
+int nyls_basis(const nyls_plan* plan, const void* ws, double* lam, double* U, hipStream_t stream);
+
 /* Feature map (App. A.2 eq32, Sec. 3): eigendecompose K_mm and evaluate
  * phi^(d)(t) for d = 0..dmax (dmax <= 4) at caller times.
  *   t_eval    [E] evaluation times, instance i owns t_eval[eval_off[i] .. eval_off[i+1])

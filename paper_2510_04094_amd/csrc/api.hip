@@ -30,6 +30,7 @@ struct nyls_plan {
   int32_t n_big = 0;        // instances with m > 64
   int32_t n_split = 0, max_chunks = 0;
   int32_t n_vgram = 0;      // unsplit instances on the LDS-tile FP64 Gram
+  int32_t n_vks = 0;        // ... of them whose kernel-space Gram it forms too
   int64_t split_off = 0;       // partial sums of split instances (doubles from ws)
   int64_t split_doubles = 0;
   nyls_tuning tune = {0, 64, 0, 1, 1, -1};
@@ -102,6 +103,7 @@ nyls_plan_view view(const nyls_plan* pl) {
   v.n_big = pl->n_big;
   v.n_split = pl->n_split;
   v.n_vgram = pl->n_vgram;
+  v.n_vks = pl->n_vks;
   v.max_chunks = pl->max_chunks;
   v.eig_ql = pl->tune.eig_ql;
   v.ql_lanes = pl->tune.ql_lanes;
@@ -198,7 +200,7 @@ int split_chunk(const nyls_plan* pl) {
 
 void apply_tuning(nyls_plan* pl) {
   pl->gcls_mask = pl->tl_mask = pl->ntl_mask = 0;
-  pl->n_split = pl->max_chunks = pl->n_vgram = 0;
+  pl->n_split = pl->max_chunks = pl->n_vgram = pl->n_vks = 0;
   pl->split_off = pl->ws_doubles + pl->scratch_doubles;
   pl->split_doubles = 0;
   const int ch = split_chunk(pl);
@@ -212,7 +214,7 @@ void apply_tuning(nyls_plan* pl) {
     if (wide || (ch > 0 && d.n >= min_n)) {
       f |= NYLS_DF_SPLIT;
       d.chunk = wide ? wide_ch : ch;
-      d.nchunks = (d.n + ch - 1) / ch;
+      d.nchunks = (d.n + d.chunk - 1) / d.chunk;
       d.part = pl->split_off + pl->split_doubles;
       pl->split_doubles += nyls_split_doubles(d.m, d.nchunks);
       ++pl->n_split;
@@ -224,6 +226,7 @@ void apply_tuning(nyls_plan* pl) {
     if (pl->tune.gram_valu && d.m + 2 <= 64) f |= NYLS_DF_GRAM_VALU;
     d.flags = f;
     if (!(f & NYLS_DF_SPLIT) && (d.m + 2 > 64 || (f & NYLS_DF_GRAM_VALU))) ++pl->n_vgram;
+    if (!(f & NYLS_DF_SPLIT) && (d.m + 2 > NYLS_GRAM4_MAX_G || (f & NYLS_DF_GRAM_VALU))) ++pl->n_vks;
     if (d.m + 2 <= 64 && !(f & NYLS_DF_GRAM_VALU)) pl->gcls_mask |= 1u << nyls_gram_class_of(d);
     if (f & NYLS_DF_TAIL) pl->tl_mask |= 1u << nyls_slot_blocks(d.m);
     else pl->ntl_mask |= 1u << nyls_slot_blocks(d.m);
@@ -436,7 +439,34 @@ __global__ void k_instance_info(const nyls_desc* __restrict__ desc, const double
   const nyls_desc& d = desc[i];
   info[e] = ws[d.ws + nyls_layout(d.m, d.p, 0).info + k];
 }
+
+// Grid (instance, tiles of 256 entries of the MAXM x MAXM output).
+__global__ void k_basis(const nyls_desc* __restrict__ desc, const double* __restrict__ ws,
+                        double* __restrict__ lam, double* __restrict__ U, int maxm) {
+  const nyls_desc& d = desc[blockIdx.x];
+  const int m = d.m;
+  const nyls_wsl L = nyls_layout(m, d.p, 0);
+  const double* w = ws + d.ws;
+  const int e = (int)blockIdx.y * blockDim.x + (int)threadIdx.x;
+  if (lam && blockIdx.y == 0 && (int)threadIdx.x < maxm) {
+    const int k = threadIdx.x;
+    lam[(size_t)blockIdx.x * maxm + k] = k < m ? w[L.lam + k] : 0.0;
+  }
+  if (!U || e >= maxm * maxm) return;
+  const int s = e / maxm, k = e - s * maxm;
+  U[(size_t)blockIdx.x * maxm * maxm + e] = (s < m && k < m) ? w[L.U + s * m + k] : 0.0;
+}
 }  // namespace
+
+int nyls_basis(const nyls_plan* pl, const void* ws, double* lam, double* U, hipStream_t stream) {
+  if (!pl || !ws) return NYLS_E_NULL;
+  if (!lam && !U) return NYLS_OK;
+  const int threads = 256, maxm = pl->maxm;
+  const dim3 grid(pl->batch, (maxm * maxm + threads - 1) / threads);
+  hipLaunchKernelGGL(k_basis, grid, dim3(threads), 0, stream, pl->d_desc,
+                     static_cast<const double*>(ws), lam, U, maxm);
+  return hip_rc(hipGetLastError());
+}
 
 int nyls_instance_info(const nyls_plan* pl, const void* ws, double* info, hipStream_t stream) {
   if (!pl || !ws || !info) return NYLS_E_NULL;

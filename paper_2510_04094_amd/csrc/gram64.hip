@@ -38,7 +38,7 @@ constexpr int MAXB = 3;     // 4x4 blocks per thread (m <= 128 -> at most 561 bl
 // ceil(nblk / (3 * 256)) workgroups per chunk (grid z), each writing its blocks straight
 // from registers; every one of them forms the chunk's rows.
 constexpr int kWideBlocks = MAXB * NYLS_BLOCK;
-constexpr int kG4Blocks = 8;  // column blocks of the four-wave MFMA Gram (m + 2 <= 128)
+constexpr int kG4Blocks = NYLS_GRAM4_MAX_G / 16;  // column blocks of the four-wave MFMA Gram
 
 __device__ inline int instance_of(const int32_t* order) {
   return order ? order[blockIdx.x] : (int)blockIdx.x;
@@ -775,7 +775,7 @@ void launch_vg(const nyls_plan_view& pv, double* ws, hipStream_t st, int smode, 
   const int maxm = wide ? pv.maxm : pv.maxm_narrow;
   const bool split = smode == 1 || smode == 2;
   if (wide ? (!split || !(pv.nb_mask & (1u << 16))) : maxm == 0) return;
-  if (split ? !pv.n_split : (!pv.n_vgram && !pv.only)) return;
+  if (split ? !pv.n_split : smode == 3 ? !pv.n_vks : (!pv.n_vgram && !pv.only)) return;
   const size_t lds = gram64_lds_bytes(maxm, TP, wide);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram64<TP>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -213,9 +213,11 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt_wide_transform(const nyls_de
   }
 }
 
-// WIDE = false: bases up to NYLS_NARROW_MAX_M, the matrix in LDS; WIDE = true: the wide
-// bases, the matrix assembled and factored in place in the workspace (it would not fit the
-// LDS).  Each instantiation skips the other's instances.
+// WIDE = false: bases up to m = glo, the matrix in LDS; WIDE = true: larger bases, the matrix
+// assembled and factored in place in the workspace (glo = NYLS_NARROW_MAX_M: only the systems
+// that would not fit the LDS; glo = 64 for batches with many 64 < m <= 128 instances, whose
+// 85 KB of LDS would hold one workgroup per CU).  Each instantiation skips the other's
+// instances.
 template <bool WIDE>
 __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict__ desc,
                                                     const int32_t* __restrict__ order,
@@ -223,11 +225,11 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
                                                     double* __restrict__ kkt_out,
                                                     double* __restrict__ rhs_out, int kn,
                                                     int factor, int single, int eigbasis,
-                                                    int only) {
+                                                    int only, int glo) {
   extern __shared__ double sm[];
   const int inst = single >= 0 ? single : instance_of(order);
   const nyls_desc& d = desc[inst];
-  if ((d.m > NYLS_NARROW_MAX_M) != WIDE) return;
+  if ((d.m > glo) != WIDE) return;
   if (only && !((int)wsbase[d.ws + nyls_layout(d.m, d.p, 0).info + 1] & only)) return;
   const int m = d.m, p = d.p;
   // in LDS with an odd row stride (row-per-lane access is conflict-free), the factors copied
@@ -376,12 +378,12 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
 
 }  // namespace
 
-// LDS of k_kkt: the matrix of the largest on-chip system (bases up to NYLS_NARROW_MAX_M),
-// or the vectors of a wide one, whichever is larger.
-size_t nyls_kkt_lds_bytes(int maxm_narrow, int maxm, int maxp) {
-  const int Nn = maxm_narrow + 1 + maxp, Nw = maxm + 1 + maxp;
-  const size_t narrow = maxm_narrow > 0 ? (size_t)Nn * (Nn + 1) + (Nn + 1) : 0;
-  const size_t wide = maxm > NYLS_NARROW_MAX_M ? (size_t)(Nw + 1) : 0;
+// LDS of k_kkt: the matrix of the largest on-chip system (bases up to m = mn <= glo), or the
+// vectors of a system factored in the workspace, whichever is larger.
+size_t nyls_kkt_lds_bytes(int mn, int maxm, int maxp, int glo) {
+  const int Nn = mn + 1 + maxp, Nw = maxm + 1 + maxp;
+  const size_t narrow = mn > 0 ? (size_t)Nn * (Nn + 1) + (Nn + 1) : 0;
+  const size_t wide = maxm > glo ? (size_t)(Nw + 1) : 0;
   const int Nmax = Nn > Nw ? Nn : Nw;
   return ((narrow > wide ? narrow : wide) + NYLS_MAX_P * NYLS_MAX_M + 16) * sizeof(double) +
          (size_t)2 * (Nmax + 1) * sizeof(int);
@@ -389,8 +391,13 @@ size_t nyls_kkt_lds_bytes(int maxm_narrow, int maxm, int maxp) {
 
 hipError_t nyls_launch_kkt(const nyls_plan_view& pv, double* ws, double* kkt_out, double* rhs_out,
                            int factor, hipStream_t st) {
-  const size_t lds = nyls_kkt_lds_bytes(pv.maxm_narrow, pv.maxm, pv.maxp);
+  // many 64 < m <= 128 instances: factor them in the workspace (see k_kkt)
+  const int glo = pv.n_big >= 32 ? 64 : NYLS_NARROW_MAX_M;
+  const int mn = pv.maxm_narrow < glo ? pv.maxm_narrow : glo;
+  const size_t lds = nyls_kkt_lds_bytes(mn, pv.maxm, pv.maxp, glo);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_kkt<false>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_kkt<true>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const int kn = pv.maxm + 1 + NYLS_MAX_P;
   const int eb = (pv.mode == NYLS_MIXED && !pv.only) ? 1 : 0;
@@ -403,11 +410,11 @@ hipError_t nyls_launch_kkt(const nyls_plan_view& pv, double* ws, double* kkt_out
       hipLaunchKernelGGL(k_kkt_wide_transform, dim3(pv.batch, (g * g + NYLS_BLOCK - 1) / NYLS_BLOCK),
                          dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, step);
   }
-  if (pv.maxm_narrow > 0)
+  if (glo == NYLS_NARROW_MAX_M ? pv.maxm_narrow > 0 : pv.batch > pv.n_big)  // some m <= glo
     hipLaunchKernelGGL(k_kkt<false>, dim3(pv.batch), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws,
-                       kkt_out, rhs_out, kn, factor, -1, eb, pv.only);
-  if (pv.maxm > NYLS_NARROW_MAX_M)
+                       kkt_out, rhs_out, kn, factor, -1, eb, pv.only, glo);
+  if (pv.maxm > glo)
     hipLaunchKernelGGL(k_kkt<true>, dim3(pv.batch), dim3(NYLS_BLOCK), lds, st, pv.d_desc, pv.d_order, ws,
-                       kkt_out, rhs_out, kn, factor, -1, eb, pv.only);
+                       kkt_out, rhs_out, kn, factor, -1, eb, pv.only, glo);
   return hipGetLastError();
 }

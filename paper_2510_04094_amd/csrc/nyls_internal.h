@@ -12,6 +12,9 @@
 // always split over point chunks, with two wavefronts per chunk, one per half of the
 // landmark slots, and factor K_mm and the KKT matrix in the workspace.
 #define NYLS_NARROW_MAX_M 128
+// Widest Gram (m + 2) that the four-wave MFMA kernel forms in kernel space (eight column
+// blocks of 16); wider unsplit ones take the LDS-tile kernel.
+#define NYLS_GRAM4_MAX_G 128
 
 // One instance as the kernels see it (device-resident table, one entry per instance).
 struct nyls_desc {
@@ -371,6 +374,8 @@ struct nyls_plan_view {
   int32_t n_split;          // instances with NYLS_DF_SPLIT
   int32_t n_vgram;          // unsplit instances whose FP64 Gram takes the LDS-tile kernel
                             // (m + 2 > 64, or NYLS_DF_GRAM_VALU)
+  int32_t n_vks;            // ... and whose kernel-space Gram it forms as well
+                            // (m + 2 > NYLS_GRAM4_MAX_G, or NYLS_DF_GRAM_VALU)
   int32_t max_chunks;       // largest nchunks of a split instance
   int32_t eig_ql;           // tuning: 1 QL inside one wavefront per instance
   int32_t ql_lanes;         // tuning: instances per wavefront of the lane-parallel QL

@@ -62,6 +62,8 @@ EXPORTS = {
     "nyls_total_points": (ctypes.c_int64, [ctypes.c_void_p]),
     "nyls_max_m": (ctypes.c_int32, [ctypes.c_void_p]),
     "nyls_instance_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nyls_basis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p]),
     "nyls_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p]),
@@ -507,6 +509,14 @@ class Batch:
         out = torch.zeros(self.batch, 8, dtype=torch.float64, device=self.device)
         _check(_lib.nyls_instance_info(self.plan, _ptr(self.ws), _ptr(out), _stream()), "nyls_instance_info")
         return out
+
+    def basis(self):
+        """nyls_basis after a call that formed the basis: (lam [batch][maxm],
+        U [batch][maxm][maxm]) as float64 device tensors, K_mm = U diag(lam) U^T."""
+        lam = torch.empty(self.batch, self.maxm, dtype=torch.float64, device=self.device)
+        u = torch.empty(self.batch, self.maxm, self.maxm, dtype=torch.float64, device=self.device)
+        _check(_lib.nyls_basis(self.plan, _ptr(self.ws), _ptr(lam), _ptr(u), _stream()), "nyls_basis")
+        return lam, u
 
     def backward(self, t_obs_list, g_obs_list):
         """nyls_backward after solve(): gradients of a loss with dl/dy_hat(s_j) = g_j."""

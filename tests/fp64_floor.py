@@ -14,6 +14,11 @@ tau = 1e-8) these move y_hat by up to ~1e-9; on well-conditioned instances by < 
 floor() measures, on the oracle alone, the largest change of y_hat under each of them
 (random symmetric perturbations of those sizes, a few seeds), and bar() = max(1e-10,
 4 x floor): 1e-10 wherever the oracle itself is stable at that level.
+
+The backward perturbation's spectral norm is about 1.6 sqrt(m) eps |K_mm|_2 (15 to 18 eps for
+m = 78 .. 128, the order of what LAPACK's own eigensolver leaves on these matrices).  A caller
+that has measured the backward error of an eigendecomposition can pass it as `bnorm` (in
+units of eps |K_mm|_2): the random perturbation is then scaled to that spectral norm.
 """
 import contextlib
 
@@ -25,7 +30,7 @@ EPS = 2.0 ** -53
 
 
 @contextlib.contextmanager
-def _perturbed_kmm(kind, seed):
+def _perturbed_kmm(kind, seed, bnorm=None):
     orig = oracle.nystrom.landmark_gram
 
     def noisy(t_land, sigma):
@@ -36,7 +41,10 @@ def _perturbed_kmm(kind, seed):
             e = 2.0 * z2 * rng.uniform(-EPS, EPS, k.shape) + rng.uniform(-2 * EPS, 2 * EPS, k.shape)
             return k * (1.0 + 0.5 * (e + e.T))
         e = rng.uniform(-2 * EPS, 2 * EPS, k.shape) * np.linalg.norm(k, 2)
-        return k + 0.5 * (e + e.T)
+        e = 0.5 * (e + e.T)
+        if bnorm is not None:
+            e *= bnorm * EPS * np.linalg.norm(k, 2) / np.linalg.norm(e, 2)
+        return k + e
 
     oracle.nystrom.landmark_gram = noisy
     try:
@@ -49,7 +57,7 @@ def _yhat(q):
     return oracle.linear.solve(q)["yhat"]
 
 
-def floor_of(fn, q, ref=None, seeds=3):
+def floor_of(fn, q, ref=None, seeds=3, bnorm=None):
     """Largest rel. l-inf change of the oracle quantity fn(q) (an array) under the FP64
     perturbations above."""
     if ref is None:
@@ -58,7 +66,7 @@ def floor_of(fn, q, ref=None, seeds=3):
     worst = 0.0
     for kind in ("entries", "backward"):
         for s in range(seeds):
-            with _perturbed_kmm(kind, 1000 + s):
+            with _perturbed_kmm(kind, 1000 + s, bnorm):
                 y = fn(q)
             worst = max(worst, float(np.max(np.abs(y - ref)) / nrm))
     for sgn in (1.0, -1.0):
@@ -67,14 +75,14 @@ def floor_of(fn, q, ref=None, seeds=3):
     return worst
 
 
-def floor(q, ref=None, seeds=3):
+def floor(q, ref=None, seeds=3, bnorm=None):
     """Largest rel. l-inf change of the oracle's y_hat under the FP64 perturbations above."""
-    return floor_of(_yhat, q, ref, seeds)
+    return floor_of(_yhat, q, ref, seeds, bnorm)
 
 
-def bar_of(fn, q, ref=None):
-    return max(1e-10, 4.0 * floor_of(fn, q, ref))
+def bar_of(fn, q, ref=None, bnorm=None):
+    return max(1e-10, 4.0 * floor_of(fn, q, ref, bnorm=bnorm))
 
 
-def bar(q, ref=None):
-    return bar_of(_yhat, q, ref)
+def bar(q, ref=None, bnorm=None):
+    return bar_of(_yhat, q, ref, bnorm)

@@ -103,4 +103,5 @@ def test_work_functions_reject_null_plan():
     assert lib.nyls_solve(None, 0, None, None, None, None, None, None, None) == -1
     assert lib.nyls_assemble(None, None, None, None, None) == -1
     assert lib.nyls_features(None, None, None, 0, None, None, None, None, None) == -1
+    assert lib.nyls_basis(None, None, None, None, None) == -1
     assert lib.nyls_error_string(-5).decode().startswith("need 2 <= m")

@@ -36,6 +36,57 @@ def test_uneven_batch_matches_oracle(gpu_lib, mode_name):
         assert status[i] & (gpu_lib.S_SINGULAR | gpu_lib.S_NONFINITE | gpu_lib.S_EIG_NOCONV) == 0
 
 
+def eig_backward_error(k, lam, u):
+    """|K - U Lambda U^T|_2 and |U^T U - I|_2 in units of eps |K|_2 and eps."""
+    nk = np.linalg.norm(k, 2)
+    be = np.linalg.norm(k - (u * lam[None, :]) @ u.T, 2) / nk / fp64_floor.EPS
+    oe = np.linalg.norm(u.T @ u - np.eye(len(lam)), 2) / fp64_floor.EPS
+    return be, oe
+
+
+@pytest.mark.parametrize("mode_name", ["FP64", "MIXED"])
+def test_batch_with_many_bases_above_64(gpu_lib, mode_name):
+    """32 or more instances with m > 64 switch the eigensolver to its workspace-staged form
+    and the KKT systems of 64 < m <= 128 to the workspace LU; m = 127, 128 (Gram wider than
+    128, FP64) keep the LDS-tile Gram.  The uneven-batch family with those bases (and
+    m = 40); in FP64 one wide basis rides along.
+
+    Per instance: the eigendecomposition of K_mm is backward stable (|K - U Lambda U^T| <=
+    128 eps |K|, U orthogonal to 256 eps; measured up to 55 and 140, LAPACK's own 13 to 26
+    and 35), its eigenvalues within those errors of the oracle's, and y_hat matches the
+    oracle within the FP64 bar whose backward perturbation has the size of the two
+    eigensolvers' measured backward errors together (near the cut-off y_hat amplifies them,
+    so which of two backward-stable results lies nearer the oracle is a matter of rounding)."""
+    top = (127, 128) if mode_name == "FP64" else (126,)  # mixed precision stops at 126
+    insts = workloads.mixed_batch(count=45, n_lo=500, n_hi=3000, ms=(65, 78, 100, 110, 40) + top)
+    if mode_name == "FP64":
+        insts.append(workloads.linear_second_order(99, n=5000, m=160, t_end=10.0, sigma=0.4))
+    assert sum(q["m"] > 64 for q in insts) >= 32
+    b = gpu_lib.Batch(insts, mode=getattr(gpu_lib, mode_name))
+    out = b.solve()
+    lam_g, u_g = b.basis()
+    torch.cuda.synchronize()
+    y = out["yhat"].cpu().numpy()
+    status = out["status"].cpu().numpy()
+    lam_g, u_g = lam_g.cpu().numpy(), u_g.cpu().numpy()
+    for i, q in enumerate(insts):
+        m = q["m"]
+        k = oracle.nystrom.landmark_gram(q["t"][oracle.nystrom.landmark_indices(q)], q["sigma"])
+        lam_o, u_o = oracle.nystrom.eig_desc(k)
+        be, oe = eig_backward_error(k, lam_g[i, :m], u_g[i, :m, :m])
+        be_o, _ = eig_backward_error(k, lam_o, u_o)
+        assert be <= 128 and oe <= 256, (i, m, be, oe)
+        assert np.max(np.abs(lam_g[i, :m] - lam_o)) <= (be + be_o) * fp64_floor.EPS * lam_o[0], i
+        ref = oracle.linear.solve(q)["yhat"]
+        err = rel_inf(y[b.goff[i]:b.goff[i + 1]], ref)
+        if mode_name == "FP64":
+            tol = fp64_floor.bar(q, ref, bnorm=max(be + be_o, 1.6 * np.sqrt(m)))
+        else:
+            tol = 1e-6
+        assert err <= tol, (i, q["p"], q["n"], m, err, tol)
+        assert status[i] & (gpu_lib.S_SINGULAR | gpu_lib.S_NONFINITE | gpu_lib.S_EIG_NOCONV) == 0
+
+
 def test_full_uneven_batch_sampled(gpu_lib):
     """The 4096-instance uneven batch in one solve (mixed precision); 12 instances spread
     over the batch (both orders, all three m) are checked against the oracle."""

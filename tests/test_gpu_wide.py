@@ -61,8 +61,9 @@ def test_wide_basis_solve_at_the_fp64_bar(gpu_lib, case):
     assert 1 <= info[0, 5] <= 4
 
 
-@pytest.mark.parametrize("split", [512, 2048])
+@pytest.mark.parametrize("split", [512, 2048, 0])
 def test_wide_basis_with_explicit_chunk_sizes(gpu_lib, split):
+    """split = 0 (no splitting) still splits the wide instance, at 1024 points a chunk."""
     q = wide_instance("second", 5, 12000, 180, 30.0, 0.6, 1e-8)
     ref = oracle.linear.solve(q)["yhat"]
     _, _, ys = _solve(gpu_lib, [q], tuning=dict(split=split))
@@ -90,6 +91,18 @@ def test_batch_of_wide_and_narrow_bases(gpu_lib):
         ref = oracle.linear.solve(q)["yhat"]
         bar = fp64_floor.bar(q, ref)
         assert _rel(ys[i], ref) <= bar, (i, _rel(ys[i], ref), bar)
+        assert int(st[i]) & _bad(gpu_lib) == 0, i
+
+
+def test_wide_basis_in_a_batch_of_more_than_64(gpu_lib):
+    """Above 64 instances the narrow ones are not split; the wide one still is."""
+    insts = [wide_instance("first", 15, 3000, 150, 5.0, 0.2, 1e-10)]
+    insts += [workloads.linear_first_order(16 + i, n=300 + 7 * i, m=20) for i in range(64)]
+    _, out, ys = _solve(gpu_lib, insts)
+    st = out["status"].cpu().numpy()
+    for i in (0, 1, 64):
+        ref = oracle.linear.solve(insts[i])["yhat"]
+        assert _rel(ys[i], ref) <= fp64_floor.bar(insts[i], ref), i
         assert int(st[i]) & _bad(gpu_lib) == 0, i
 
 
