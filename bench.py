@@ -34,8 +34,8 @@ TRAFFIC = {
     "backward": {
         "sources": ["paper_2510_04094_amd/csrc/adjoint.hip", "paper_2510_04094_amd/csrc/nyls_walk.h",
                     "paper_2510_04094_amd/csrc/nyls_dense.h", "paper_2510_04094_amd/csrc/nyls_internal.h"],
-        "sha1": "8a984ba4ab2bbbf484e313a075a1257e68c578cf",
-        "kib": {"mixed": (2166567.4, 1128657.0), "fp64": (2225698.7, 1129576.5)},
+        "sha1": "8382b3c3e7262e17c228f394d7ebcac7fa1c69ee",
+        "kib": {"mixed": (2165585.6, 1128646.2), "fp64": (2274802.2, 1129529.2)},
         "scale": (2.0, 1.0),
     },
 }
@@ -458,6 +458,29 @@ def newton_rate(nyls, count, steps, procs, check):
     return res
 
 
+def legs(nyls, line, args, procs, insts):
+    """The bench's legs beside the headline step (uneven batch, Newton, plain comparator,
+    long single instances), each added to the line under its own key."""
+    if args.uneven > 0:
+        log("uneven batch")
+        line["uneven_batch"] = {name: uneven_batch_rate(nyls, {"fp64": nyls.FP64, "mixed": nyls.MIXED}[name],
+                                                        args.uneven, args.steps, procs, args.check, args.tune)
+                                for name in args.modes.split(",")}
+    if args.newton > 0:
+        log("Newton leg")
+        line["newton_riccati"] = newton_rate(nyls, args.newton, args.steps, procs, args.check)
+    if args.plain > 0:
+        log("plain per-instance FP64 solve")
+        line["plain_fp64_per_instance"] = {"solves_per_s": plain_fp64_rate(nyls, insts[:args.plain]),
+                                           "instances": args.plain, "note": "forward only"}
+    if args.long:
+        log("long single instances")
+        line["long_single_instance"] = dict(long_single_ms(nyls), n=50000, m=100,
+                                            note="first-order family on [0, 20], FP64; solve, and adjoint "
+                                                 "for 100 observations")
+        line["long_time_m200"] = long_time_wide_ms(nyls)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -477,6 +500,9 @@ def main():
                     help="time long single instances (n = 5e4, m = 100; and m = 200 on [0, 100])")
     ap.add_argument("--uneven", type=int, default=4096, help="instances of the uneven-batch leg (0: skip)")
     ap.add_argument("--newton", type=int, default=64, help="instances of the Newton (Riccati) leg (0: skip)")
+    ap.add_argument("--headline", type=int, default=1,
+                    help="0: skip the headline step (profiling runs of the other legs; the line "
+                         "then holds only those legs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -497,6 +523,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if not args.headline:
+        line = {"headline": "skipped (--headline 0)"}
+        legs(nyls, line, args, procs,
+             make_instances(args.plain, args.n, args.m, seed_config) if args.plain > 0 else [])
+        print(json.dumps(line))
+        return
     insts = make_instances(args.batch, args.n, args.m, seed_config)
 
     results = {}
@@ -585,24 +617,7 @@ def main():
                       "kernel_ms": {kk: vv[0] / max(vv[1], 1) for kk, vv in v["prof"].items() if vv[1]}}
                   for k, v in results.items()},
     }
-    if args.uneven > 0:
-        log("uneven batch")
-        line["uneven_batch"] = {name: uneven_batch_rate(nyls, {"fp64": nyls.FP64, "mixed": nyls.MIXED}[name],
-                                                        args.uneven, args.steps, procs, args.check, args.tune)
-                                for name in args.modes.split(",")}
-    if args.newton > 0:
-        log("Newton leg")
-        line["newton_riccati"] = newton_rate(nyls, args.newton, args.steps, procs, args.check)
-    if args.plain > 0:
-        log("plain per-instance FP64 solve")
-        line["plain_fp64_per_instance"] = {"solves_per_s": plain_fp64_rate(nyls, insts[:args.plain]),
-                                           "instances": args.plain, "note": "forward only"}
-    if args.long:
-        log("long single instances")
-        line["long_single_instance"] = dict(long_single_ms(nyls), n=50000, m=100,
-                                            note="first-order family on [0, 20], FP64; solve, and adjoint "
-                                                 "for 100 observations")
-        line["long_time_m200"] = long_time_wide_ms(nyls)
+    legs(nyls, line, args, procs, insts)
     if not args.no_cpu:
         log("CPU oracle baseline")
         count = args.cpu_sample or 6 * procs
