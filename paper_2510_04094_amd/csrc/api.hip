@@ -40,9 +40,10 @@ struct nyls_plan {
   std::vector<nyls_desc> h_desc;
   rocblas_handle blas = nullptr;
   // FP64 solves run the kernel-space Gram on `side` while the eigensolver runs on the
-  // caller's stream (fork and join through the two events)
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // caller's stream (fork and join through the events); with bases on both sides of 64
+  // landmarks the eigensolver of the m <= 64 ones runs on `side2` (joined by ev_join2)
+  hipStream_t side = nullptr, side2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
 };
 
 namespace {
@@ -344,8 +345,10 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
   if (ok && mode == NYLS_FP64_EXPLICIT) ok = rocblas_create_handle(&pl->blas) == rocblas_status_success;
   if (ok && mode == NYLS_FP64)
     ok = hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) == hipSuccess &&
+         hipStreamCreateWithFlags(&pl->side2, hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) == hipSuccess &&
-         hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) == hipSuccess;
+         hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&pl->ev_join2, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     nyls_plan_destroy(pl);
     return NYLS_E_HIP;
@@ -359,7 +362,9 @@ void nyls_plan_destroy(nyls_plan* pl) {
   if (pl->blas) rocblas_destroy_handle(pl->blas);
   if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
   if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
+  if (pl->ev_join2) (void)hipEventDestroy(pl->ev_join2);
   if (pl->side) (void)hipStreamDestroy(pl->side);
+  if (pl->side2) (void)hipStreamDestroy(pl->side2);
   if (pl->d_desc) (void)hipFree(pl->d_desc);
   if (pl->d_lidx) (void)hipFree(pl->d_lidx);
   if (pl->d_order) (void)hipFree(pl->d_order);
@@ -551,18 +556,30 @@ int solve_impl(const nyls_plan* pl, int32_t refine_steps, double* omega, double*
     // latency-bound (part of it runs one lane per instance on a few CUs): the Grams run on
     // the side stream meanwhile, and the eigenbasis Grams that replace them where K_mm is
     // ill-conditioned follow the join.
+    // With bases on both sides of 64 landmarks the two eigensolver paths (disjoint
+    // instances, each latency-bound on few CUs) run side by side as well.
+    const bool split_eig = (pv.nb_mask & (4 | 16)) && (pv.nb_mask & (256 | (1u << 16)));
     e = hipEventRecord(pl->ev_fork, stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(pl->side, pl->ev_fork, 0);
+    if (e == hipSuccess && split_eig) e = hipStreamWaitEvent(pl->side2, pl->ev_fork, 0);
     nyls_prof_begin(NYLS_K_GRAM64, pl->side);
     if (e == hipSuccess) e = nyls_launch_gram64_kspace(pv, w, pl->side);
     nyls_prof_end(NYLS_K_GRAM64, pl->side);
     hipError_t ej = hipEventRecord(pl->ev_join, pl->side);
+    hipError_t ej2 = hipSuccess;
+    if (split_eig) {
+      if (e == hipSuccess) e = nyls_launch_eig(pv, w, -1, pl->side2, NYLS_EIG_NARROW);
+      ej2 = hipEventRecord(pl->ev_join2, pl->side2);
+    }
     nyls_prof_begin(NYLS_K_EIG, stream);
-    if (e == hipSuccess) e = nyls_launch_eig(pv, w, -1, stream);
+    if (e == hipSuccess)
+      e = nyls_launch_eig(pv, w, -1, stream, split_eig ? NYLS_EIG_BIG : NYLS_EIG_NARROW | NYLS_EIG_BIG);
     nyls_prof_end(NYLS_K_EIG, stream);
-    // joined whatever happened above, so no work is left running on the side stream
+    // joined whatever happened above, so no work is left running on the side streams
     if (ej == hipSuccess) ej = hipStreamWaitEvent(stream, pl->ev_join, 0);
+    if (split_eig && ej2 == hipSuccess) ej2 = hipStreamWaitEvent(stream, pl->ev_join2, 0);
     if (e == hipSuccess) e = ej;
+    if (e == hipSuccess) e = ej2;
     if (e == hipSuccess) e = nyls_launch_gram64_rest(pv, w, stream, true);
   } else {
     nyls_prof_begin(NYLS_K_EIG, stream);

@@ -936,6 +936,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_eig_wide(const nyls_desc* __rest
       dd[m - 1] = A[(m - 1) * m + m - 1];
       ee[m - 1] = 0.0;
     }
+    // the owners of the last two columns overwrite those entries next
+    __syncthreads();
     // 2. Q in place (the trailing 2 x 2 block starts as the identity)
     if (own && j >= m - 2) {
       A[(m - 2) * m + j] = j == m - 2 ? 1.0 : 0.0;
@@ -1216,8 +1218,9 @@ __global__ __launch_bounds__(64) void k_eig_wide_replay(const nyls_desc* __restr
 
 }  // namespace
 
-hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hipStream_t st) {
-  if (pv.nb_mask & (4 | 16)) {  // some instance has m <= 64
+hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hipStream_t st,
+                           int parts) {
+  if ((parts & NYLS_EIG_NARROW) && (pv.nb_mask & (4 | 16))) {  // some instance has m <= 64
     const int mq = pv.maxm < kQlMaxM ? pv.maxm : kQlMaxM;
     const int lda = mq | 1;
     const size_t lds = (size_t)lda * lda * sizeof(double) + 3 * 64 * sizeof(double) +
@@ -1240,6 +1243,7 @@ hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hip
                          (int)QL_REDO);
     }
   }
+  if (!(parts & NYLS_EIG_BIG)) return hipGetLastError();
   if (pv.nb_mask & (1u << 16)) {  // wide bases (never in single-instance launches)
     const int lo = NYLS_NARROW_MAX_M;
     hipLaunchKernelGGL(k_eig_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, ws, (int)WIDE_REDUCE, lo, NYLS_MAX_M, 0);

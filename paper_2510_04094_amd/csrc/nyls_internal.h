@@ -382,8 +382,13 @@ struct nyls_plan_view {
   int32_t overlap;          // tuning: FP64 kernel-space Gram beside the eigensolver
 };
 
-// `single` >= 0 restricts a launch to that one instance (one workgroup).
-hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hipStream_t st);
+// `single` >= 0 restricts a launch to that one instance (one workgroup).  `parts` selects
+// the instances by basis size: NYLS_EIG_NARROW (m <= 64), NYLS_EIG_BIG (m > 64); the two
+// touch disjoint instances, so they may run on different streams.
+#define NYLS_EIG_NARROW 1
+#define NYLS_EIG_BIG 2
+hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hipStream_t st,
+                           int parts = NYLS_EIG_NARROW | NYLS_EIG_BIG);
 hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t st);
 // The two halves of nyls_launch_gram64 for a solve that overlaps the Gram with the
 // eigensolver: the kernel-space Grams of every instance (they read nothing the eigensolver
