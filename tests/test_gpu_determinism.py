@@ -54,3 +54,31 @@ def test_split_instances_are_deterministic(gpu_lib):
     insts = [workloads.linear_first_order(30, n=50000, m=100, t_end=20.0, sigma=0.25, tau=1e-10),
              workloads.linear_second_order(31, n=20000, m=50, t_end=20.0)]
     _assert_identical(_solves(gpu_lib, insts, backward=True))
+
+
+def test_mixed_precision_solve_is_deterministic(gpu_lib):
+    """FP32 Gram on the matrix cores and the FP64 re-solve of the instances it fails."""
+    insts = workloads.mixed_batch(count=256, n_lo=500, n_hi=2000)
+    b = gpu_lib.Batch(insts, mode=gpu_lib.MIXED)
+    outs = []
+    for _ in range(3):
+        out = b.solve()
+        outs.append([out["yhat"].cpu().numpy().copy(), out["status"].cpu().numpy().copy()])
+    _assert_identical(outs)
+
+
+def test_newton_and_leverage_are_deterministic(gpu_lib):
+    """The 256-thread Newton step (with its dense small-pivot system) and the leverage
+    scores, on batches of first- and second-order instances."""
+    insts = [workloads.riccati(i, n=1500) for i in range(64)]
+    q = torch.tensor(np.concatenate([p["q"] for p in insts]), dtype=torch.float64, device="cuda")
+    xs = []
+    for _ in range(3):
+        b = gpu_lib.Batch(insts, mode=gpu_lib.FP64)
+        x, _ = b.riccati_newton(q, max_iter=6, tol=0.0, gauss_newton_steps=2)
+        torch.cuda.synchronize()
+        xs.append([x.cpu().numpy().copy()])
+    _assert_identical(xs)
+    lev = [workloads.linear_second_order(i, n=3000, m=m) for i, m in enumerate((30, 50, 62, 100))]
+    b = gpu_lib.Batch(lev, mode=gpu_lib.FP64)
+    _assert_identical([[b.leverage_scores().cpu().numpy().copy()] for _ in range(3)])
