@@ -50,7 +50,8 @@ enum {
   NYLS_MIXED = 1,         /* FP32 kernel values, rotated into the eigenbasis and contracted
                              on the matrix cores (FP32 MFMA, FP64 cross-tile sums), FP64
                              eigen, solve and matrix-free FP64 iterative refinement;
-                             m <= 126 */
+                             m <= 126; bases with m + 2 > 64 take the FP64 Gram of
+                             NYLS_FP64 instead of the FP32 one */
   NYLS_FP64_EXPLICIT = 2  /* reference-style FP64: explicit feature matrices, one instance
                              per launch sequence (a baseline, not the fast path) */
 };

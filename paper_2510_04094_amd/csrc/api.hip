@@ -179,6 +179,15 @@ double* scratch_for_current_device() {
   return g_scratch_ptr[dev];
 }
 
+// NYLS_MIXED: the FP32 Gram of the bases with m + 2 <= 64; wider ones take the FP64 Gram
+// from the start (their FP32 refinement failed on every such instance of the uneven batch,
+// and rotating their rows into the eigenbasis costs m^2 multiply-adds per point).
+hipError_t launch_gram_mixed(const nyls_plan_view& pv, double* w, hipStream_t stream) {
+  hipError_t e = nyls_launch_gram32(pv, w, stream);
+  if (e == hipSuccess && (pv.nt_mask >> 5)) e = nyls_launch_gram64_over64(pv, w, stream);
+  return e;
+}
+
 // Clears n doubles at p (a kernel rather than hipMemsetAsync, so a captured graph replays it
 // faithfully).
 __global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
@@ -224,7 +233,7 @@ void apply_tuning(nyls_plan* pl) {
     if (pl->tune.tail_layout && d.rec == 1 && nyls_walk_tail(d.m) != 0 && !(f & NYLS_DF_SPLIT))
       f |= NYLS_DF_TAIL;
     if (pl->tune.tail_layout && (nyls_gram_class(d.m) & 1)) f |= NYLS_DF_GRAM_TAIL;
-    if (pl->tune.gram_valu && d.m + 2 <= 64) f |= NYLS_DF_GRAM_VALU;
+    if (pl->tune.gram_valu && d.m + 2 <= 64 && pl->mode == NYLS_FP64) f |= NYLS_DF_GRAM_VALU;
     d.flags = f;
     if (!(f & NYLS_DF_SPLIT) && (d.m + 2 > 64 || (f & NYLS_DF_GRAM_VALU))) ++pl->n_vgram;
     if (!(f & NYLS_DF_SPLIT) && (d.m + 2 > NYLS_GRAM4_MAX_G || (f & NYLS_DF_GRAM_VALU))) ++pl->n_vks;
@@ -504,7 +513,7 @@ int nyls_assemble(const nyls_plan* pl, double* kkt, double* rhs, void* ws, hipSt
   double* w = static_cast<double*>(ws);
   hipError_t e = nyls_launch_eig(pv, w, -1, stream);
   if (e == hipSuccess)
-    e = (pl->mode == NYLS_MIXED) ? nyls_launch_gram32(pv, w, stream) : nyls_launch_gram64(pv, w, stream);
+    e = (pl->mode == NYLS_MIXED) ? launch_gram_mixed(pv, w, stream) : nyls_launch_gram64(pv, w, stream);
   if (e == hipSuccess) e = nyls_launch_kkt(pv, w, kkt, rhs, 0, stream);
   return hip_rc(e);
 }
@@ -586,7 +595,7 @@ int solve_impl(const nyls_plan* pl, int32_t refine_steps, double* omega, double*
     e = nyls_launch_eig(pv, w, -1, stream);
     nyls_prof_end(NYLS_K_EIG, stream);
     nyls_prof_begin(NYLS_K_GRAM32, stream);
-    if (e == hipSuccess) e = nyls_launch_gram32(pv, w, stream);
+    if (e == hipSuccess) e = launch_gram_mixed(pv, w, stream);
     nyls_prof_end(NYLS_K_GRAM32, stream);
   }
   nyls_prof_begin(NYLS_K_KKT, stream);

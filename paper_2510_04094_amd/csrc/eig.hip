@@ -836,31 +836,35 @@ __global__ __launch_bounds__(64) void k_eig_ql2(const nyls_desc* __restrict__ de
 enum { WIDE_REDUCE = 0, WIDE_FINISH = 1 };
 constexpr int kWideRows = 64;  // rows of Z per replay workgroup
 
-// A[c m + j] -= u[c] * a + w[c] * b for c in [c0, m) (thread-owned column j), eight loads
-// issued before the stores.
+// Entries of a thread-owned column loaded together before any is used or stored: a thread's
+// loads would otherwise each wait a round trip to L2 (and behind its own earlier stores).
+constexpr int kColBatch = 8;
+
+// A[c m + j] -= delta(c) for c in [c0, m) (thread-owned column j), in batches of kColBatch
+// loads issued before their stores.
 template <class F>
 __device__ inline void wide_col_update(double* A, int m, int j, int c0, F delta) {
   int c = c0;
-  for (; c + 8 <= m; c += 8) {
-    double v[8];
+  for (; c + kColBatch <= m; c += kColBatch) {
+    double v[kColBatch];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = A[(c + u) * m + j];
+    for (int u = 0; u < kColBatch; ++u) v[u] = A[(c + u) * m + j];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) A[(c + u) * m + j] = v[u] - delta(c + u);
+    for (int u = 0; u < kColBatch; ++u) A[(c + u) * m + j] = v[u] - delta(c + u);
   }
   for (; c < m; ++c) A[c * m + j] -= delta(c);
 }
 
-// sum over c in [c0, m) of A[c m + j] * x[c] (x in LDS)
+// sum over c in [c0, m) of A[c m + j] * x[c] (x in LDS), added in order of c
 __device__ inline double wide_col_dot(const double* A, int m, int j, int c0, const double* x) {
   double acc = 0.0;
   int c = c0;
-  for (; c + 8 <= m; c += 8) {
-    double v[8];
+  for (; c + kColBatch <= m; c += kColBatch) {
+    double v[kColBatch];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = A[(c + u) * m + j];
+    for (int u = 0; u < kColBatch; ++u) v[u] = A[(c + u) * m + j];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc += v[u] * x[c + u];
+    for (int u = 0; u < kColBatch; ++u) acc += v[u] * x[c + u];
   }
   for (; c < m; ++c) acc += A[c * m + j] * x[c];
   return acc;

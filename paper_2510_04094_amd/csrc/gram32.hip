@@ -180,7 +180,8 @@ hipError_t launch_nt(const nyls_plan_view& pv, double* ws, hipStream_t st) {
 }  // namespace
 
 hipError_t nyls_launch_gram32(const nyls_plan_view& pv, double* ws, hipStream_t st) {
-  const unsigned mask = pv.nt_mask;
+  // bases with m + 2 > 64 take the FP64 Gram (nyls_launch_gram64_over64)
+  const unsigned mask = pv.nt_mask & 0x1f;
   hipError_t e = hipSuccess;
   if ((mask >> 1) & 1) e = launch_nt<1>(pv, ws, st);
   if (e == hipSuccess && ((mask >> 2) & 1)) e = launch_nt<2>(pv, ws, st);

@@ -95,8 +95,13 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64(const nyls_desc* __restri
   // Ill-conditioned K_mm (retained eigenvalues below 1e-9 lambda_1): the kernel-space Gram
   // would lose most digits in W^T S W, so the rows are rotated by U^T first and the Gram is
   // accumulated in the eigenbasis (the KKT kernel then scales by Lambda^{-1/2}).
+  // FP64 re-solves (only) take the eigenbasis, except unsplit bases with 64 < m + 2 <= 128:
+  // those keep the kernel-space Gram of the four-wave MFMA kernel unless K_mm is
+  // ill-conditioned (the FP64 mode's own rule), which this kernel would otherwise rotate on
+  // the VALU.
   const int rank = (smode == 1 || smode == 3) ? 0 : (int)ws[L.info + 0];
-  const bool rotate = only || (rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam]);
+  const bool g4 = !split && m + 2 > 64 && m + 2 <= 16 * kG4Blocks;
+  const bool rotate = (only && !g4) || (rank > 0 && ws[L.lam + rank - 1] < 1e-9 * ws[L.lam]);
   if ((smode == 2 || smode == 4) && !rotate) return;  // the kernel-space Gram stands
   // m + 2 <= 64: the one-wave MFMA kernels take the instance unless its tuning asks for this
   // one, m + 2 <= 128 in kernel space the four-wave one (split instances always come here)
@@ -451,8 +456,10 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_gram64_mfma4(const nyls_desc* __
   const nyls_wsl L = nyls_layout(m, P, 0);
   double* ws = wsbase + d.ws;
   // only < 0: every instance, before the eigensolver has chosen the basis (instances that
-  // turn out to need the eigenbasis are redone by k_gram64)
-  if (only >= 0 && use_eigenbasis(ws, L, only)) return;
+  // turn out to need the eigenbasis are redone by k_gram64); only > 0: the FP64 re-solve of
+  // the flagged instances, in kernel space unless K_mm is ill-conditioned
+  if (only > 0 && !((int)ws[L.info + 1] & only)) return;
+  if (only >= 0 && use_eigenbasis(ws, L, 0)) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int s0 = 16 * NBW * w;
 
@@ -734,13 +741,17 @@ void launch_g4_p(const nyls_plan_view& pv, double* ws, hipStream_t st, int only)
     hipLaunchKernelGGL((k_gram64_mfma4<P, true>), dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, pv.d_order, ws, only);
 }
 
-void launch_ks_all(const nyls_plan_view& pv, double* ws, hipStream_t st, int only) {
+void launch_g4_all(const nyls_plan_view& pv, double* ws, hipStream_t st, int only) {
   if (pv.maxm_narrow + 2 > 64) {  // four-wave MFMA Gram, 64 < m + 2 <= 128
     launch_g4_p<1>(pv, ws, st, only);
     launch_g4_p<2>(pv, ws, st, only);
     launch_g4_p<3>(pv, ws, st, only);
     launch_g4_p<4>(pv, ws, st, only);
   }
+}
+
+void launch_ks_all(const nyls_plan_view& pv, double* ws, hipStream_t st, int only) {
+  launch_g4_all(pv, ws, st, only);
   launch_ks<1, false>(pv, ws, st, only);
   launch_ks<2, false>(pv, ws, st, only);
   launch_ks<2, true>(pv, ws, st, only);
@@ -803,10 +814,18 @@ hipError_t nyls_launch_gram64_kspace(const nyls_plan_view& pv, double* ws, hipSt
   return hipGetLastError();
 }
 
+hipError_t nyls_launch_gram64_over64(const nyls_plan_view& pv, double* ws, hipStream_t st) {
+  launch_g4_all(pv, ws, st, 0);   // kernel space on the matrix cores
+  launch_vg<64>(pv, ws, st, 0, 0);  // eigenbasis where K_mm is ill-conditioned
+  return hipGetLastError();
+}
+
 hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t st) {
   if (!pv.only) {
     launch_ks_all(pv, ws, st, 0);
     launch_split_parts(pv, ws, st, 1);
+  } else {
+    launch_g4_all(pv, ws, st, pv.only);  // re-solve: 64 < m + 2 <= 128 in kernel space
   }
   return nyls_launch_gram64_rest(pv, ws, st, false);
 }

@@ -166,7 +166,8 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt_mfma_wide(const nyls_desc* _
   const nyls_wsl L = nyls_layout(m, d.p, 0);
   double* ws = wsbase + d.ws;
   if (only && !((int)ws[L.info + 1] & only)) return;
-  if (eigbasis || ws[L.info + 4] != 0.0) return;
+  (void)eigbasis;  // (the FP32 eigenbasis Gram covers m + 2 <= 64 only)
+  if (ws[L.info + 4] != 0.0) return;
   const int r = (int)ws[L.info + 0];
   double* T = ws + L.tmp;
   kkt_transform_mfma<(NYLS_NARROW_MAX_M + 2 + 15) / 16>(ws + L.gram, ws + L.W, m, r, d.gamma,
@@ -256,7 +257,9 @@ __global__ __launch_bounds__(NYLS_BLOCK) void k_kkt(const nyls_desc* __restrict_
   // (here for g <= 64, from k_kkt_mfma_wide in the T scratch otherwise); with the eigenbasis
   // Gram (rows rotated by U^T) the transform is the diagonal Lambda^{-1/2}.
   const double* lamv = ws + L.lam;
-  if (!eigbasis) eigbasis = ws[L.info + 4] != 0.0 ? 1 : 0;  // per-instance choice of the FP64 Gram
+  // per-instance choice of the FP64 Gram (eigbasis: the FP32 Gram of NYLS_MIXED, which
+  // bases with m + 2 > 64 do not take)
+  if (!eigbasis || g > 64) eigbasis = ws[L.info + 4] != 0.0 ? 1 : 0;
   const bool mx = !eigbasis;
   if (mx && g <= 64)
     kkt_transform_mfma<4>(S, W, m, r, gam, [&](int a, int b, double v) {
@@ -401,7 +404,7 @@ hipError_t nyls_launch_kkt(const nyls_plan_view& pv, double* ws, double* kkt_out
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const int kn = pv.maxm + 1 + NYLS_MAX_P;
   const int eb = (pv.mode == NYLS_MIXED && !pv.only) ? 1 : 0;
-  if (pv.maxm_narrow + 2 > 64 && !eb)
+  if (pv.maxm_narrow + 2 > 64)  // (NYLS_MIXED too: those bases take the FP64 Gram)
     hipLaunchKernelGGL(k_kkt_mfma_wide, dim3(pv.batch), dim3(NYLS_BLOCK), 0, st, pv.d_desc, pv.d_order, ws,
                        -1, eb, pv.only);
   if (pv.maxm > NYLS_NARROW_MAX_M && !eb) {

@@ -390,6 +390,10 @@ struct nyls_plan_view {
 hipError_t nyls_launch_eig(const nyls_plan_view& pv, double* ws, int single, hipStream_t st,
                            int parts = NYLS_EIG_NARROW | NYLS_EIG_BIG);
 hipError_t nyls_launch_gram64(const nyls_plan_view& pv, double* ws, hipStream_t st);
+// The FP64 Grams of the unsplit bases with m + 2 > 64 only (NYLS_MIXED: the FP32 Gram takes
+// the others): kernel space on the matrix cores, the eigenbasis where K_mm is
+// ill-conditioned.
+hipError_t nyls_launch_gram64_over64(const nyls_plan_view& pv, double* ws, hipStream_t st);
 // The two halves of nyls_launch_gram64 for a solve that overlaps the Gram with the
 // eigensolver: the kernel-space Grams of every instance (they read nothing the eigensolver
 // writes), then, once the eigensolver is done (ks_done = true), the eigenbasis Grams that
