@@ -82,3 +82,22 @@ def test_newton_and_leverage_are_deterministic(gpu_lib):
     lev = [workloads.linear_second_order(i, n=3000, m=m) for i, m in enumerate((30, 50, 62, 100))]
     b = gpu_lib.Batch(lev, mode=gpu_lib.FP64)
     _assert_identical([[b.leverage_scores().cpu().numpy().copy()] for _ in range(3)])
+
+
+@pytest.mark.parametrize("mode_name", ["FP64", "MIXED"])
+def test_throughput_workload_step_is_deterministic(gpu_lib, mode_name):
+    """The bench step on 1024 instances of its workload (n = 1e4, m = 50, 100 observations):
+    solve, predict at the observations and adjoint, twice."""
+    insts = [workloads.linear_second_order(i, n=10000, m=50, obs=100) for i in range(1024)]
+    b = gpu_lib.Batch(insts, mode=getattr(gpu_lib, mode_name))
+    t_obs = [q["t_obs"] for q in insts]
+    outs = []
+    for _ in range(2):
+        out = b.solve()
+        yo, _ = b.predict(t_obs, 0)
+        g = yo - torch.tensor(np.concatenate([q["y_obs"] for q in insts]), device=yo.device)
+        bw = b.backward(t_obs, g)
+        torch.cuda.synchronize()
+        outs.append([out["yhat"].cpu().numpy().copy(), yo.cpu().numpy().copy()] +
+                    [v.cpu().numpy().copy() for _, v in sorted(bw.items())])
+    _assert_identical(outs)
