@@ -34,8 +34,8 @@ TRAFFIC = {
     "backward": {
         "sources": ["paper_2510_04094_amd/csrc/adjoint.hip", "paper_2510_04094_amd/csrc/nyls_walk.h",
                     "paper_2510_04094_amd/csrc/nyls_dense.h", "paper_2510_04094_amd/csrc/nyls_internal.h"],
-        "sha1": "8382b3c3e7262e17c228f394d7ebcac7fa1c69ee",
-        "kib": {"mixed": (2165585.6, 1128646.2), "fp64": (2274802.2, 1129529.2)},
+        "sha1": "f9576f75c160e9a303616b3fb07a7bbfc69f4a98",
+        "kib": {"mixed": (2179413.4, 1128721.9), "fp64": (2267761.0, 1129501.6)},
         "scale": (2.0, 1.0),
     },
 }
