@@ -15,7 +15,7 @@
  *     otherwise, row-major, owned by the caller.  The library never frees them.
  *   - Work functions only enqueue kernels on `stream` (no host synchronisation, no
  *     allocation) and return 0, or a negative NYLS_E* code when an argument is invalid;
- *     nothing is enqueued then.  nyls_solve in NYLS_FP64 mode forks part of its work onto
+ *     nothing is enqueued then.  nyls_solve (NYLS_FP64, NYLS_MIXED) forks part of its work onto
  *     streams the plan owns and joins it back on `stream` (events), so later work on
  *     `stream` is ordered after all of it; graph capture of `stream` captures all of it.
  *     Numerical outcomes are reported per instance in the `status` bitmask (NYLS_S*),
@@ -25,8 +25,9 @@
  *     for nyls_predict / nyls_backward; nyls_newton_step keeps its basis there.  One plan
  *     with one workspace must not be used from two streams at once; distinct plans can.
  *   - Per-instance padded layouts use MAXM = max m over the batch and KN = MAXM + 1 + 4.
- *   - Only the plan functions allocate (the device descriptor table; an NYLS_FP64 plan
- *     also creates two non-blocking streams at default priority and three events).
+ *   - Only the plan functions allocate (the device descriptor table; an NYLS_FP64 or
+ *     NYLS_MIXED plan also creates two non-blocking streams at default priority and six
+ *     events).
  */
 #ifndef NYLS_H
 #define NYLS_H
@@ -166,10 +167,12 @@ int nyls_plan_set_params(nyls_plan* plan, const double* sigma, const double* gam
  *   tail_layout  1 = a last block of at most four landmarks (m = 16 k + 1..4) is walked in
  *                the tail layout by the refinement/output passes and accumulated on the VALU by
  *                the matrix-core Gram; 0 = treated as a full 16-slot block
- *   overlap      FP64 solves: 1 = kernel-space Gram on the plan's side stream beside the
- *                eigensolver (and, in batches with bases on both sides of 64 landmarks,
+ *   overlap      1 = FP64 solves run the kernel-space Gram on the plan's side stream beside
+ *                the eigensolver (and, in batches with bases on both sides of 64 landmarks,
  *                the eigensolver of the m <= 64 ones on a second side stream beside that of
- *                the larger ones); 0 = everything in order on the caller's stream
+ *                the larger ones); FP64 and mixed solves run the refinement/output passes of
+ *                different landmark-slot classes (m <= 32, <= 64, larger) on the three
+ *                streams; 0 = everything in order on the caller's stream
  *   split        FP64 solves of long instances: grid points per workgroup when the Gram and
  *                the refinement/output passes of one instance are split over many
  *                workgroups (a multiple of 64, at least 512; every instance runs the chunked

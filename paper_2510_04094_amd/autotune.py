@@ -95,6 +95,11 @@ def lookup(key, path=None):
     return {k: int(tun[k]) for k in nyls.TUNING_FIELDS}
 
 
+def _slot_class(m):
+    """Landmark-slot class of the one-wave passes (their launches run side by side)."""
+    return 0 if m <= 32 else (1 if m <= 64 else 2)
+
+
 def knob_values(max_m, min_m, mode, max_n=0):
     """The values worth trying per knob for a batch (others are no-ops there)."""
     knobs = {}
@@ -104,8 +109,9 @@ def knob_values(max_m, min_m, mode, max_n=0):
     if mode == nyls.FP64 and min_m + 2 <= 64:
         knobs["gram_valu"] = [0, 1]
     knobs["tail_layout"] = [1, 0]
+    if mode == nyls.FP64 or _slot_class(min_m) != _slot_class(max_m):
+        knobs["overlap"] = [1, 0]  # (mixed mode: only the passes of different slot classes)
     if mode == nyls.FP64:
-        knobs["overlap"] = [1, 0]
         if max_n >= 4096:
             knobs["split"] = [-1, 0, 2048, 512]
     return knobs

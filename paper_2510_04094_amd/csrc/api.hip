@@ -41,9 +41,12 @@ struct nyls_plan {
   rocblas_handle blas = nullptr;
   // FP64 solves run the kernel-space Gram on `side` while the eigensolver runs on the
   // caller's stream (fork and join through the events); with bases on both sides of 64
-  // landmarks the eigensolver of the m <= 64 ones runs on `side2` (joined by ev_join2)
+  // landmarks the eigensolver of the m <= 64 ones runs on `side2` (joined by ev_join2).
+  // (NYLS_FP64 and NYLS_MIXED plans.)
   hipStream_t side = nullptr, side2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
+  // the refinement/output passes of different slot classes run on the three streams as well
+  hipEvent_t ev_fork_p = nullptr, ev_join_p = nullptr, ev_join_p2 = nullptr;
 };
 
 namespace {
@@ -352,12 +355,15 @@ int nyls_plan_create(const nyls_problem* probs, int32_t batch, int32_t mode, nyl
              hipSuccess;
   }
   if (ok && mode == NYLS_FP64_EXPLICIT) ok = rocblas_create_handle(&pl->blas) == rocblas_status_success;
-  if (ok && mode == NYLS_FP64)
+  if (ok && mode != NYLS_FP64_EXPLICIT)
     ok = hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) == hipSuccess &&
          hipStreamCreateWithFlags(&pl->side2, hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) == hipSuccess &&
          hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) == hipSuccess &&
-         hipEventCreateWithFlags(&pl->ev_join2, hipEventDisableTiming) == hipSuccess;
+         hipEventCreateWithFlags(&pl->ev_join2, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&pl->ev_fork_p, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&pl->ev_join_p, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&pl->ev_join_p2, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     nyls_plan_destroy(pl);
     return NYLS_E_HIP;
@@ -372,6 +378,9 @@ void nyls_plan_destroy(nyls_plan* pl) {
   if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
   if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
   if (pl->ev_join2) (void)hipEventDestroy(pl->ev_join2);
+  if (pl->ev_fork_p) (void)hipEventDestroy(pl->ev_fork_p);
+  if (pl->ev_join_p) (void)hipEventDestroy(pl->ev_join_p);
+  if (pl->ev_join_p2) (void)hipEventDestroy(pl->ev_join_p2);
   if (pl->side) (void)hipStreamDestroy(pl->side);
   if (pl->side2) (void)hipStreamDestroy(pl->side2);
   if (pl->d_desc) (void)hipFree(pl->d_desc);
@@ -602,8 +611,29 @@ int solve_impl(const nyls_plan* pl, int32_t refine_steps, double* omega, double*
   if (e == hipSuccess) e = nyls_launch_kkt(pv, w, nullptr, nullptr, 1, stream);
   nyls_prof_end(NYLS_K_KKT, stream);
   nyls_prof_begin(NYLS_K_POINTS, stream);
-  if (e == hipSuccess)
+  const unsigned cls = pv.nb_mask & (4 | 16 | 256);
+  if (e == hipSuccess && pl->side && pl->tune.overlap && (cls & (cls - 1))) {
+    // several slot classes (disjoint instances; each launch holds only its own instances'
+    // wavefronts): m <= 32 on side2, 32 < m <= 64 on side, the rest and the split instances
+    // here, joined before anything else reads the solution
+    e = hipEventRecord(pl->ev_fork_p, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(pl->side, pl->ev_fork_p, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(pl->side2, pl->ev_fork_p, 0);
+    if (e == hipSuccess)
+      e = nyls_launch_points(pv, w, refine_steps, yhat, omega, bias, lambda, status, -1, pl->side2, 4);
+    hipError_t ej2 = hipEventRecord(pl->ev_join_p2, pl->side2);
+    if (e == hipSuccess)
+      e = nyls_launch_points(pv, w, refine_steps, yhat, omega, bias, lambda, status, -1, pl->side, 16);
+    hipError_t ej = hipEventRecord(pl->ev_join_p, pl->side);
+    if (e == hipSuccess)
+      e = nyls_launch_points(pv, w, refine_steps, yhat, omega, bias, lambda, status, -1, stream, 256 | 1);
+    if (ej == hipSuccess) ej = hipStreamWaitEvent(stream, pl->ev_join_p, 0);
+    if (ej2 == hipSuccess) ej2 = hipStreamWaitEvent(stream, pl->ev_join_p2, 0);
+    if (e == hipSuccess) e = ej;
+    if (e == hipSuccess) e = ej2;
+  } else if (e == hipSuccess) {
     e = nyls_launch_points(pv, w, refine_steps, yhat, omega, bias, lambda, status, -1, stream);
+  }
   nyls_prof_end(NYLS_K_POINTS, stream);
   if (pl->mode == NYLS_MIXED && refine_steps > 0 && e == hipSuccess) {
     // Instances whose refinement on the FP32 Gram did not converge (K_mm too ill-conditioned

@@ -403,9 +403,12 @@ hipError_t nyls_launch_gram64_rest(const nyls_plan_view& pv, double* ws, hipStre
 hipError_t nyls_launch_gram32(const nyls_plan_view& pv, double* ws, hipStream_t st);
 hipError_t nyls_launch_kkt(const nyls_plan_view& pv, double* ws, double* kkt_out, double* rhs_out,
                            int factor, hipStream_t st);
+// `classes`: the slot classes to launch (bits of nyls_plan_view::nb_mask: 4, 16, 256; the
+// split instances go with bit 1); classes touch disjoint instances, so they may run on
+// different streams.
 hipError_t nyls_launch_points(const nyls_plan_view& pv, double* ws, int refine, double* yhat,
                               double* omega, double* bias, double* lambda, int32_t* status,
-                              int single, hipStream_t st);
+                              int single, hipStream_t st, unsigned classes = ~0u);
 hipError_t nyls_launch_features(const nyls_plan_view& pv, const double* ws, const double* t_eval,
                                 const int64_t* eval_off, int dmax, double* phi, double* eigval,
                                 int32_t* rank, int64_t max_eval, int single, hipStream_t st);

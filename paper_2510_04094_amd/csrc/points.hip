@@ -719,11 +719,12 @@ void launch_split_points(const nyls_plan_view& pv, double* ws, int refine, doubl
 
 hipError_t nyls_launch_points(const nyls_plan_view& pv, double* ws, int refine, double* yhat,
                               double* omega, double* bias, double* lambda, int32_t* status,
-                              int single, hipStream_t st) {
-  if (pv.nb_mask & 4) launch_nb<2>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
-  if (pv.nb_mask & 16) launch_nb<4>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
-  if (pv.nb_mask & 256) launch_nb<8>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
-  if (pv.n_split && single < 0 && !pv.only)
+                              int single, hipStream_t st, unsigned classes) {
+  const unsigned nb = pv.nb_mask & classes;
+  if (nb & 4) launch_nb<2>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
+  if (nb & 16) launch_nb<4>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
+  if (nb & 256) launch_nb<8>(pv, ws, refine, yhat, omega, bias, lambda, status, single, st);
+  if ((classes & 1) && pv.n_split && single < 0 && !pv.only)
     launch_split_points(pv, ws, refine, yhat, omega, bias, lambda, status, st);
   return hipGetLastError();
 }

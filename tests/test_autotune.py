@@ -23,8 +23,10 @@ def test_knob_values_skip_choices_that_cannot_apply():
     assert "split" in k and k["split"][0] == nyls.DEFAULT_TUNING["split"]
     k = autotune.knob_values(100, 70, nyls.FP64)
     assert "eig_ql" not in k and "gram_valu" not in k  # every basis beyond the one-wave kernels
+    k = autotune.knob_values(50, 40, nyls.MIXED)
+    assert "gram_valu" not in k and "overlap" not in k  # FP64-only choices, one slot class
     k = autotune.knob_values(50, 20, nyls.MIXED)
-    assert "gram_valu" not in k and "overlap" not in k  # FP64-only choices
+    assert "overlap" in k  # the passes of the two slot classes may run side by side
     for name, vals in autotune.knob_values(20, 20, nyls.FP64).items():
         assert vals[0] == nyls.DEFAULT_TUNING[name]  # the search starts from the defaults
 
