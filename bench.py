@@ -34,8 +34,8 @@ TRAFFIC = {
     "backward": {
         "sources": ["paper_2510_04094_amd/csrc/adjoint.hip", "paper_2510_04094_amd/csrc/nyls_walk.h",
                     "paper_2510_04094_amd/csrc/nyls_dense.h", "paper_2510_04094_amd/csrc/nyls_internal.h"],
-        "sha1": "f9576f75c160e9a303616b3fb07a7bbfc69f4a98",
-        "kib": {"mixed": (2179413.4, 1128721.9), "fp64": (2267761.0, 1129501.6)},
+        "sha1": "fb793b96100193ff350f0670e346a0097096bdb0",
+        "kib": {"mixed": (2126766.0, 1128630.5), "fp64": (2269630.2, 1129528.3)},
         "scale": (2.0, 1.0),
     },
 }
