@@ -508,7 +508,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the batch is data-parallel over independent "
-              "instances and this build runs on a single MI355X (see DESIGN.md for sharding).")
+              "instances and the library runs on a single MI355X; use --gpus 1.")
         sys.exit(2)
 
     import torch
