@@ -580,6 +580,9 @@ int solve_impl(const nyls_plan* pl, int32_t refine_steps, double* omega, double*
     e = hipEventRecord(pl->ev_fork, stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(pl->side, pl->ev_fork, 0);
     if (e == hipSuccess && split_eig) e = hipStreamWaitEvent(pl->side2, pl->ev_fork, 0);
+    // (the eigensolver of the larger bases, the longest chain, is enqueued first)
+    nyls_prof_begin(NYLS_K_EIG, stream);
+    if (e == hipSuccess && split_eig) e = nyls_launch_eig(pv, w, -1, stream, NYLS_EIG_BIG);
     nyls_prof_begin(NYLS_K_GRAM64, pl->side);
     if (e == hipSuccess) e = nyls_launch_gram64_kspace(pv, w, pl->side);
     nyls_prof_end(NYLS_K_GRAM64, pl->side);
@@ -589,9 +592,7 @@ int solve_impl(const nyls_plan* pl, int32_t refine_steps, double* omega, double*
       if (e == hipSuccess) e = nyls_launch_eig(pv, w, -1, pl->side2, NYLS_EIG_NARROW);
       ej2 = hipEventRecord(pl->ev_join2, pl->side2);
     }
-    nyls_prof_begin(NYLS_K_EIG, stream);
-    if (e == hipSuccess)
-      e = nyls_launch_eig(pv, w, -1, stream, split_eig ? NYLS_EIG_BIG : NYLS_EIG_NARROW | NYLS_EIG_BIG);
+    if (e == hipSuccess && !split_eig) e = nyls_launch_eig(pv, w, -1, stream);
     nyls_prof_end(NYLS_K_EIG, stream);
     // joined whatever happened above, so no work is left running on the side streams
     if (ej == hipSuccess) ej = hipStreamWaitEvent(stream, pl->ev_join, 0);
