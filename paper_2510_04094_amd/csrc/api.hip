@@ -33,6 +33,10 @@ struct nyls_plan {
   int32_t n_vks = 0;        // ... of them whose kernel-space Gram it forms too
   int64_t split_off = 0;       // partial sums of split instances (doubles from ws)
   int64_t split_doubles = 0;
+  // work of the one-wave refinement/output passes per (slot class 2, 4, 8 blocks; order p),
+  // sum of n (m + 2) over the unsplit instances: the solve shares these launches out over
+  // its streams
+  double pcost[3][NYLS_MAX_P + 1] = {};
   nyls_tuning tune = {0, 64, 0, 1, 1, -1};
   nyls_desc* d_desc = nullptr;
   int32_t* d_lidx = nullptr;
@@ -216,6 +220,8 @@ void apply_tuning(nyls_plan* pl) {
   pl->n_split = pl->max_chunks = pl->n_vgram = pl->n_vks = 0;
   pl->split_off = pl->ws_doubles + pl->scratch_doubles;
   pl->split_doubles = 0;
+  for (auto& row : pl->pcost)
+    for (double& c : row) c = 0.0;
   const int ch = split_chunk(pl);
   const int min_n = pl->tune.split > 0 ? 0 : 4096;
   const int wide_ch = pl->tune.split > 0 ? pl->tune.split : 1024;
@@ -243,6 +249,10 @@ void apply_tuning(nyls_plan* pl) {
     if (d.m + 2 <= 64 && !(f & NYLS_DF_GRAM_VALU)) pl->gcls_mask |= 1u << nyls_gram_class_of(d);
     if (f & NYLS_DF_TAIL) pl->tl_mask |= 1u << nyls_slot_blocks(d.m);
     else pl->ntl_mask |= 1u << nyls_slot_blocks(d.m);
+    if (!(f & NYLS_DF_SPLIT) && d.m <= NYLS_NARROW_MAX_M) {
+      const int nb = nyls_slot_blocks(d.m);
+      pl->pcost[nb == 2 ? 0 : (nb == 4 ? 1 : 2)][d.p] += (double)d.n * (d.m + 2);
+    }
   }
 }
 }  // namespace
@@ -612,22 +622,34 @@ int solve_impl(const nyls_plan* pl, int32_t refine_steps, double* omega, double*
   if (e == hipSuccess) e = nyls_launch_kkt(pv, w, nullptr, nullptr, 1, stream);
   nyls_prof_end(NYLS_K_KKT, stream);
   nyls_prof_begin(NYLS_K_POINTS, stream);
-  const unsigned cls = pv.nb_mask & (4 | 16 | 256);
-  if (e == hipSuccess && pl->side && pl->tune.overlap && (cls & (cls - 1))) {
-    // several slot classes (disjoint instances; each launch holds only its own instances'
-    // wavefronts): m <= 32 on side2, 32 < m <= 64 on side, the rest and the split instances
-    // here, joined before anything else reads the solution
+  // the one-wave pass launches, one per (slot class, order p) present, largest work first
+  struct pitem { double cost; unsigned cls; int p; };
+  pitem items[3 * NYLS_MAX_P];
+  int nitems = 0;
+  for (int c = 0; c < 3; ++c)
+    for (int p = 1; p <= NYLS_MAX_P; ++p)
+      if (pl->pcost[c][p] > 0.0) items[nitems++] = {pl->pcost[c][p], 1u << (2 << c), p};
+  std::sort(items, items + nitems, [](const pitem& a, const pitem& b) { return a.cost > b.cost; });
+  if (e == hipSuccess && pl->side && pl->tune.overlap && nitems >= 2) {
+    // several such launches (disjoint instances; each holds only its own instances'
+    // wavefronts): shared out over the three streams, each to the least loaded so far, the
+    // split instances here; joined before anything else reads the solution
     e = hipEventRecord(pl->ev_fork_p, stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(pl->side, pl->ev_fork_p, 0);
     if (e == hipSuccess) e = hipStreamWaitEvent(pl->side2, pl->ev_fork_p, 0);
+    hipStream_t sts[3] = {stream, pl->side, pl->side2};
+    double load[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < nitems && e == hipSuccess; ++k) {
+      const int t = load[0] <= load[1] ? (load[0] <= load[2] ? 0 : 2) : (load[1] <= load[2] ? 1 : 2);
+      load[t] += items[k].cost;
+      nyls_plan_view pq = pv;
+      pq.p_mask = pv.p_mask & (1u << items[k].p);
+      e = nyls_launch_points(pq, w, refine_steps, yhat, omega, bias, lambda, status, -1, sts[t], items[k].cls);
+    }
     if (e == hipSuccess)
-      e = nyls_launch_points(pv, w, refine_steps, yhat, omega, bias, lambda, status, -1, pl->side2, 4);
-    hipError_t ej2 = hipEventRecord(pl->ev_join_p2, pl->side2);
-    if (e == hipSuccess)
-      e = nyls_launch_points(pv, w, refine_steps, yhat, omega, bias, lambda, status, -1, pl->side, 16);
+      e = nyls_launch_points(pv, w, refine_steps, yhat, omega, bias, lambda, status, -1, stream, 1);
     hipError_t ej = hipEventRecord(pl->ev_join_p, pl->side);
-    if (e == hipSuccess)
-      e = nyls_launch_points(pv, w, refine_steps, yhat, omega, bias, lambda, status, -1, stream, 256 | 1);
+    hipError_t ej2 = hipEventRecord(pl->ev_join_p2, pl->side2);
     if (ej == hipSuccess) ej = hipStreamWaitEvent(stream, pl->ev_join_p, 0);
     if (ej2 == hipSuccess) ej2 = hipStreamWaitEvent(stream, pl->ev_join_p2, 0);
     if (e == hipSuccess) e = ej;
